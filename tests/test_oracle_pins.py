@@ -1,0 +1,455 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks a closed form, an
+invariant, a physical identity or an independent differentiation, chosen so
+that a dropped term, a wrong sign or index or a transposed operand anywhere in
+the oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1810_01054_amd import scenes as S
+from tests.helpers import oscene, f64, rel_err
+from tests import torch_ref
+
+RNG = np.random.default_rng(1810)
+
+
+# --------------------------------------------------------------------------
+# P1  quadratic B-spline (Table I, N; D = 4/dx^2 of the P2G/G2P equations)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("inv_dx", [16.0, 64.0, 256.0])
+def test_bspline_moments(inv_dx):
+    dx = 1.0 / inv_dx
+    for xp in RNG.uniform(4 * dx, 1 - 4 * dx, size=200):
+        base, f, w, dw = oracle.bspline(xp, inv_dx)
+        assert 0.5 <= f < 1.5
+        assert base == np.floor(xp * inv_dx - 0.5)
+        delta = (base + np.arange(3)) * dx - xp      # x_i - x_p
+        assert abs(w.sum() - 1.0) < 1e-14            # partition of unity
+        assert abs((w * delta).sum()) < 1e-15        # first moment
+        # second moment dx^2/4: the reason the affine scale is 4/dx^2
+        assert abs((w * delta * delta).sum() - dx * dx / 4) < 1e-15
+        assert (w >= 0).all()
+        # derivative: sum of dw is 0 (partition of unity is constant in x_p)
+        assert abs(dw.sum()) < 1e-10 * inv_dx
+        # derivative against central differences of the weights
+        h = 1e-7 * dx
+        _, _, wp, _ = oracle.bspline(xp + h, inv_dx)
+        _, _, wm, _ = oracle.bspline(xp - h, inv_dx)
+        bp, _, _, _ = oracle.bspline(xp + h, inv_dx)
+        bm, _, _, _ = oracle.bspline(xp - h, inv_dx)
+        if bp == base and bm == base:
+            assert np.allclose((wp - wm) / (2 * h), dw, rtol=1e-6, atol=1e-6 * inv_dx)
+
+
+def test_bspline_tie_at_half():
+    # f = 0.5 exactly: the third node has zero weight and zero derivative,
+    # and the kernel values match the textbook ones (1/2, 1/2, 0).
+    inv_dx = 64.0
+    xp = 11.0 / inv_dx   # x/dx = 11: base = floor(10.5) = 10, f = 1
+    base, f, w, dw = oracle.bspline(xp, inv_dx)
+    assert base == 10 and f == 1.0
+    assert np.allclose(w, [0.125, 0.75, 0.125], atol=0, rtol=0)
+    xp = 10.5 / inv_dx   # x/dx - 0.5 = 10 (integer): base 10, f = 0.5
+    base, f, w, dw = oracle.bspline(xp, inv_dx)
+    assert base == 10 and f == 0.5
+    assert np.array_equal(w, [0.5, 0.5, 0.0])
+    assert dw[2] == 0.0
+
+
+# --------------------------------------------------------------------------
+# P6  neo-Hookean PK1 stress (Table I: P = dpsi/dF)
+# --------------------------------------------------------------------------
+
+def _psi(F, mu, la):
+    d = F.shape[0]
+    J = np.linalg.det(F)
+    return 0.5 * mu * (np.trace(F.T @ F) - d) - mu * np.log(J) + 0.5 * la * np.log(J) ** 2
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_neohookean_is_energy_gradient(d):
+    mu, la = oracle.lame(10.0, 0.3)
+    assert abs(mu - 10 / 2.6) < 1e-12 and abs(la - 3.0 / (1.3 * 0.4)) < 1e-12
+    for _ in range(20):
+        F = np.eye(d) + RNG.uniform(-0.3, 0.3, (d, d))
+        P = oracle.neohookean_P(F, mu, la)
+        h = 1e-6
+        Pfd = np.zeros((d, d))
+        for a in range(d):
+            for b in range(d):
+                E = np.zeros((d, d)); E[a, b] = h
+                Pfd[a, b] = (_psi(F + E, mu, la) - _psi(F - E, mu, la)) / (2 * h)
+        assert np.allclose(P, Pfd, rtol=1e-8, atol=1e-8)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_neohookean_rest_and_rotation(d):
+    mu, la = oracle.lame(10.0, 0.3)
+    assert np.abs(oracle.neohookean_P(np.eye(d), mu, la)).max() < 1e-15
+    for _ in range(10):
+        F = np.eye(d) + RNG.uniform(-0.3, 0.3, (d, d))
+        Q, _ = np.linalg.qr(RNG.normal(size=(d, d)))
+        if np.linalg.det(Q) < 0:
+            Q[:, 0] *= -1
+        P = oracle.neohookean_P(F, mu, la)
+        PR = oracle.neohookean_P(Q @ F, mu, la)
+        assert np.allclose(PR, Q @ P, atol=1e-12)
+
+
+def test_neohookean_inverted_is_error():
+    mu, la = oracle.lame(10.0, 0.3)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.neohookean_P(np.diag([1.0, -1.0]), mu, la)
+    assert e.value.code == -4
+
+
+# --------------------------------------------------------------------------
+# P2, P3  mass and momentum of P2G (section III, P2G equations)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mk", [S.tiny_2d, S.tiny_3d])
+def test_p2g_mass_and_momentum(mk):
+    sc = mk()
+    os_ = oscene(sc)
+    act = RNG.uniform(-2, 2, size=sc.n_act)
+    gm, gp = oracle.p2g(os_, f64(sc.state), sc.act_id, act)
+    mp = sc.rho * sc.V0
+    N = sc.n_particles
+    assert abs(gm.sum() - N * mp) < 1e-13 * N * mp
+    # sum_i p_i = sum_p m_p v_p for any stress, affine C and actuation
+    mom = mp * np.asarray(sc.v, np.float64).sum(1)
+    assert np.allclose(gp.sum(1), mom, rtol=0, atol=1e-13 * mp * N)
+    # and the stress/affine part alone carries no net momentum
+    assert np.abs(gp.sum(1) - mom).max() < 1e-12 * mp * N
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_p2g_second_moment_reproduces_C(d):
+    # one stress-free particle with affine field C = A: sum_i p_i (x_i-x_p)^T
+    # = m_p A dx^2/4 (B-spline second moment through the APIC term).
+    n = 16
+    A = RNG.uniform(-3, 3, (d, d))
+    xp = RNG.uniform(0.4, 0.6, size=(d, 1))
+    sc = oracle.Scene(dim=d, n_grid=n, n_particles=1, V0=(0.5 / n) ** d,
+                      gravity=(0, 0, 0), wall=0)
+    x = xp
+    v = np.zeros((d, 1))
+    C = A.reshape(d * d, 1)
+    F = np.eye(d).reshape(d * d, 1)
+    gm, gp = oracle.p2g(sc, (x, v, C, F))
+    mp = sc.rho * sc.V0
+    idx = np.nonzero(gm)[0]
+    pos = np.stack(np.unravel_index(idx, (n,) * d), 0) / n      # node positions
+    delta = pos - xp
+    M2 = gp[:, idx] @ delta.T
+    assert np.allclose(M2, mp * A / (4 * n * n), rtol=1e-12, atol=1e-18)
+
+
+@pytest.mark.parametrize("mk", [S.tiny_2d, S.tiny_3d])
+def test_p2g_stress_is_energy_gradient(mk):
+    """The stress part of the grid momentum equals -dt dE/dx^_i, E the total
+    elastic + actuation energy of the particles deformed by a virtual grid
+    displacement through the MLS gradient D N (x_i - x_p) (MLS-MPM force).
+    psi_act = tr(F sigma F^T)/2 gives the actuation stress F sigma."""
+    sc = mk()
+    d, n, N = sc.dim, sc.n_grid, sc.n_particles
+    os_ = oscene(sc)
+    act = RNG.uniform(-2, 2, size=sc.n_act)
+    x, _, _, F = f64(sc.state)
+    zeros_v = np.zeros_like(x)
+    zeros_C = np.zeros((d * d, N))
+    gm, gp = oracle.p2g(os_, (x, zeros_v, zeros_C, F), sc.act_id, act)
+    mu, la = oracle.lame(sc.E, sc.nu)
+    Dinv = 4.0 * n * n
+    # per-particle stencil from the (pinned) B-spline
+    st = []
+    for p in range(N):
+        bw = [oracle.bspline(x[a, p], float(n)) for a in range(d)]
+        nodes, grads = [], []
+        for off in np.ndindex(*(3,) * d):
+            Nw = np.prod([bw[a][2][off[a]] for a in range(d)])
+            node = np.array([bw[a][0] + off[a] for a in range(d)])
+            delta = node / n - x[:, p]
+            nodes.append(np.ravel_multi_index(node, (n,) * d))
+            grads.append(Dinv * Nw * delta)
+        st.append((nodes, grads))
+    sig = np.zeros((N, d))
+    for p in range(N):
+        j = sc.act_id[p]
+        if j >= 0:
+            sig[p] = act[j] * np.array(sc.act_axis[:d])
+
+    def energy(disp):  # disp [n^d][d]
+        E = 0.0
+        for p in range(N):
+            Fp = F[:, p].reshape(d, d)
+            Gsum = np.zeros((d, d))
+            for node, gr in zip(*st[p]):
+                Gsum += np.outer(disp[node], gr)
+            Fh = (np.eye(d) + Gsum) @ Fp
+            E += sc.V0 * (_psi(Fh, mu, la) + 0.5 * np.trace(Fh @ np.diag(sig[p]) @ Fh.T))
+        return E
+
+    touched = np.nonzero(gm)[0]
+    h = 1e-6
+    zero = np.zeros((n ** d, d))
+    for node in RNG.choice(touched, size=min(12, len(touched)), replace=False):
+        for a in range(d):
+            dp = zero.copy(); dp[node, a] = h
+            dE = (energy(dp) - energy(-dp)) / (2 * h)
+            assert abs(gp[a, node] - (-sc.dt * dE)) <= 1e-7 * abs(sc.dt * dE) + 1e-16
+
+
+# --------------------------------------------------------------------------
+# P4, P5  affine reproduction and rigid translation of a full step
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_affine_field_reproduced(d):
+    n, N = 16, 30
+    A = RNG.uniform(-2, 2, (d, d))
+    b = RNG.uniform(-1, 1, d)
+    x = RNG.uniform(0.3, 0.7, size=(d, N))
+    v = A @ x + b[:, None]
+    C = np.repeat(A.reshape(d * d, 1), N, 1)
+    F = np.repeat((np.eye(d) + RNG.uniform(-0.1, 0.1, (d, d))).reshape(d * d, 1), N, 1)
+    sc = oracle.Scene(dim=d, n_grid=n, n_particles=N, E=0.0, V0=(0.5 / n) ** d,
+                      gravity=(0, 0, 0), wall=0)
+    x1, v1, C1, F1 = oracle.step_fwd(sc, (x, v, C, F))
+    assert np.allclose(v1, A @ x + b[:, None], rtol=0, atol=1e-12)
+    assert np.allclose(C1, C, rtol=0, atol=1e-11)
+    Fm = F[:, 0].reshape(d, d)
+    assert np.allclose(F1, np.repeat(((np.eye(d) + sc.dt * A) @ Fm).reshape(d * d, 1), N, 1),
+                       atol=1e-14)
+    assert np.allclose(x1, x + sc.dt * v1, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_rigid_translation_and_shift(d):
+    n, N = 32, 40
+    x = RNG.uniform(0.35, 0.55, size=(d, N))
+    v0 = RNG.uniform(-1, 1, d)
+    v = np.repeat(v0[:, None], N, 1)
+    C = np.zeros((d * d, N))
+    F = np.repeat(np.eye(d).reshape(d * d, 1), N, 1)
+    sc = oracle.Scene(dim=d, n_grid=n, n_particles=N, V0=(0.5 / n) ** d,
+                      gravity=(0, 0, 0))
+    x1, v1, C1, F1 = oracle.step_fwd(sc, (x, v, C, F))
+    assert np.allclose(v1, v, atol=1e-13)
+    assert np.abs(C1).max() < 1e-11
+    assert np.allclose(F1, F, atol=1e-15)
+    # whole-cell shift of a random deformed scene: identical result, shifted
+    sc2 = oracle.Scene(dim=d, n_grid=n, n_particles=N, V0=(0.5 / n) ** d, n_act=2)
+    vr = RNG.uniform(-1, 1, (d, N))
+    Cr = RNG.uniform(-2, 2, (d * d, N))
+    Fr = (np.eye(d).reshape(d * d, 1) + RNG.uniform(-0.1, 0.1, (d * d, N)))
+    ids = RNG.integers(-1, 2, N).astype(np.int32)
+    act = np.array([0.7, -1.3])
+    shift = np.zeros((d, 1)); shift[0] = 3.0 / n; shift[d - 1] = -2.0 / n
+    a = oracle.step_fwd(sc2, (x, vr, Cr, Fr), ids, act)
+    b = oracle.step_fwd(sc2, (x + shift, vr, Cr, Fr), ids, act)
+    assert np.allclose(b[0] - shift, a[0], atol=1e-15)
+    for k in (1, 2, 3):
+        assert np.allclose(b[k], a[k], rtol=1e-12, atol=1e-12)
+    ga, pa = oracle.p2g(sc2, (x, vr, Cr, Fr), ids, act)
+    gb, pb = oracle.p2g(sc2, (x + shift, vr, Cr, Fr), ids, act)
+    sh = [3] + [0] * (d - 2) + [-2]
+    assert np.allclose(np.roll(ga.reshape((n,) * d), sh, axis=tuple(range(d))).ravel(), gb,
+                       atol=1e-18)
+
+
+# --------------------------------------------------------------------------
+# gravity, walls (the boundary conditions the paper omits)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_grid_update_wall_band(d):
+    # sticky box walls `wall` nodes thick on every side: v = 0 exactly on the
+    # band (index < wall or >= n - wall on any axis), v = p/m + dt g inside
+    n, wall = 12, 3
+    sc = oracle.Scene(dim=d, n_grid=n, n_particles=0, wall=wall,
+                      gravity=(0.5, -9.8, 1.5))
+    m = RNG.uniform(0.5, 2.0, n ** d)
+    m[RNG.choice(n ** d, 5, replace=False)] = 0.0
+    p = RNG.normal(size=(d, n ** d))
+    p[:, m == 0] = 0.0
+    v = oracle.grid_update(sc, m, p)
+    idx = np.stack(np.unravel_index(np.arange(n ** d), (n,) * d), 0)
+    band = ((idx < wall) | (idx >= n - wall)).any(0)
+    assert band.sum() == n ** d - (n - 2 * wall) ** d
+    assert np.array_equal(v[:, band], np.zeros((d, band.sum())))
+    inner = ~band & (m > 0)
+    g = np.array(sc.gravity[:d])[:, None]
+    assert np.allclose(v[:, inner], p[:, inner] / m[inner] + sc.dt * g, rtol=1e-15, atol=0)
+    assert np.array_equal(v[:, ~band & (m == 0)], np.zeros((d, (~band & (m == 0)).sum())))
+
+
+def test_gravity_and_wall_freeze():
+    d, n = 2, 32
+    # particle 0 deep inside the corner walls (stencil nodes 0..2 all wall
+    # nodes); particle 1 in free space.
+    x = np.array([[1.2 / n, 0.5], [1.3 / n, 0.5]])
+    v = np.array([[0.3, -0.2], [0.4, 0.1]])
+    C = np.zeros((4, 2)); C[1] = 1.0
+    F = np.repeat(np.eye(2).reshape(4, 1), 2, 1)
+    sc = oracle.Scene(dim=d, n_grid=n, n_particles=2, V0=(0.5 / n) ** 2, E=0.0,
+                      gravity=(0.0, -9.8, 0.0))
+    x1, v1, C1, F1 = oracle.step_fwd(sc, (x, v, C, F))
+    assert np.array_equal(v1[:, 0], [0, 0]) and np.array_equal(C1[:, 0], np.zeros(4))
+    assert np.array_equal(x1[:, 0], x[:, 0]) and np.array_equal(F1[:, 0], F[:, 0])
+    # a single stress-free particle away from walls: v' = v + dt g exactly
+    assert np.allclose(v1[:, 1], v[:, 1] + sc.dt * np.array([0, -9.8]), atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# P7  free flight: exact centroid and exact gradients of a rollout
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_free_flight_closed_forms(d):
+    if d == 2:
+        sc = S.block_2d(32, (0.4, 0.45), (0.6, 0.6), seed=3)
+    else:
+        sc = S.box_3d(16, (6, 6, 6), (10, 10, 10), seed=4)
+    sc = S.perturb(sc, 11, v_scale=0.3, C_scale=1.0, F_scale=0.03)
+    T = 12
+    os_ = oscene(sc)
+    acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase)
+    N = sc.n_particles
+    x0, v0, C0, F0 = f64(sc.state)
+    gT = (np.zeros_like(x0), np.zeros_like(v0), np.zeros_like(C0), np.zeros_like(F0))
+    gT[0][0, :] = 1.0 / N          # L = mean_p x_{p,0}^T
+    (xT, vT, CT, FT), g0, gact = oracle.rollout(os_, (x0, v0, C0, F0), T, sc.act_id,
+                                                acts, gT)
+    g = np.array(sc.gravity[:d])
+    dt = sc.dt
+    # centroid: mean x^T = mean x^0 + T dt mean v^0 + dt^2 g T(T+1)/2
+    exp = x0.mean(1) + T * dt * v0.mean(1) + dt * dt * g * T * (T + 1) / 2
+    assert np.allclose(xT.mean(1), exp, rtol=0, atol=1e-14)
+    # exact gradients
+    ex = np.zeros((d, N)); ex[0] = 1.0 / N
+    assert np.allclose(g0[0], ex, rtol=0, atol=1e-12 / N)
+    assert np.allclose(g0[1], T * dt * ex, rtol=0, atol=1e-14 / N)
+    assert np.abs(g0[2]).max() < 1e-15
+    assert np.abs(g0[3]).max() < 1e-14
+    assert np.abs(gact).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# P9  reverse pass: independent autograd and central finite differences
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mk", [S.tiny_2d, S.tiny_3d])
+def test_forward_matches_independent_torch(mk):
+    sc = mk()
+    os_ = oscene(sc)
+    act = RNG.uniform(-2, 2, size=sc.n_act)
+    st = f64(sc.state)
+    ref = torch_ref.step(sc.params(), *[torch.tensor(a) for a in st],
+                         torch.tensor(act), sc.act_id)
+    out = oracle.step_fwd(os_, st, sc.act_id, act)
+    for a, b in zip(out, ref[:4]):
+        assert rel_err(a, b.numpy()) < 1e-13
+    gm, gp = oracle.p2g(os_, st, sc.act_id, act)
+    assert rel_err(gm, ref[4][0].numpy()) < 1e-14
+    assert rel_err(gp, ref[4][1].numpy().T) < 1e-13
+
+
+@pytest.mark.parametrize("mk", [S.tiny_2d, S.tiny_3d])
+def test_reverse_matches_torch_autograd(mk):
+    sc = mk()
+    os_ = oscene(sc)
+    act = RNG.uniform(-2, 2, size=sc.n_act)
+    st = f64(sc.state)
+    ts = [torch.tensor(a, requires_grad=True) for a in st]
+    ta = torch.tensor(act, requires_grad=True)
+    out = torch_ref.step(sc.params(), *ts, ta, sc.act_id)[:4]
+    w = [RNG.normal(size=a.shape) for a in st]
+    L = sum((o * torch.tensor(wi)).sum() for o, wi in zip(out, w))
+    grads = torch.autograd.grad(L, ts + [ta])
+    g, gact = oracle.step_bwd(os_, st, w, sc.act_id, act)
+    for a, b in zip(g, grads[:4]):
+        assert rel_err(a, b.numpy()) < 1e-11
+    assert rel_err(gact, grads[4].numpy()) < 1e-11
+
+
+@pytest.mark.parametrize("mk,T", [(S.tiny_2d, 6), (S.tiny_3d, 4)])
+def test_rollout_gradient_central_fd(mk, T):
+    sc = mk()
+    os_ = oscene(sc)
+    acts = RNG.uniform(-2, 2, size=(T, sc.n_act))
+    st = f64(sc.state)
+    w = [RNG.normal(size=a.shape) for a in st]
+
+    def loss(state, a):
+        out = oracle.rollout(os_, state, T, sc.act_id, a)
+        return sum((o * wi).sum() for o, wi in zip(out, w))
+
+    _, g0, gact = oracle.rollout(os_, st, T, sc.act_id, acts, w)
+    h = 1e-6
+    for k in range(4):       # one random direction per state component
+        u = [np.zeros_like(a) for a in st]
+        u[k] = RNG.normal(size=st[k].shape)
+        plus = [a + h * b for a, b in zip(st, u)]
+        minus = [a - h * b for a, b in zip(st, u)]
+        fd = (loss(plus, acts) - loss(minus, acts)) / (2 * h)
+        an = (g0[k] * u[k]).sum()
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9, (k, fd, an)
+    ua = RNG.normal(size=acts.shape)
+    fd = (loss(st, acts + h * ua) - loss(st, acts - h * ua)) / (2 * h)
+    an = (gact * ua).sum()
+    assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9
+
+
+def test_act_bank_reverse_fd():
+    T, dt = 50, float(np.float32(1e-4))
+    freq = np.array([10.0, 20.0])
+    amp = RNG.uniform(-1, 1, (3, 2))
+    phase = RNG.uniform(0, 2 * np.pi, (3, 2))
+    act = oracle.act_bank_fwd(T, dt, freq, amp, phase)
+    # closed form of one entry: a single sinusoid at t = n dt
+    n, j = 17, 1
+    assert abs(act[n, j] - sum(amp[j, k] * np.sin(2 * np.pi * freq[k] * n * dt + phase[j, k])
+                               for k in range(2))) < 1e-15
+    g = RNG.normal(size=act.shape)
+    ga, gp = oracle.act_bank_bwd(T, dt, freq, amp, phase, g)
+    h = 1e-6
+    for (arr, gr) in ((amp, ga), (phase, gp)):
+        u = RNG.normal(size=arr.shape)
+        ap = arr + h * u
+        am = arr - h * u
+        if arr is amp:
+            fp = oracle.act_bank_fwd(T, dt, freq, ap, phase)
+            fm = oracle.act_bank_fwd(T, dt, freq, am, phase)
+        else:
+            fp = oracle.act_bank_fwd(T, dt, freq, amp, ap)
+            fm = oracle.act_bank_fwd(T, dt, freq, amp, am)
+        fd = ((fp - fm) * g).sum() / (2 * h)
+        assert abs(fd - (gr * u).sum()) < 1e-7 * abs(fd) + 1e-10
+
+
+# --------------------------------------------------------------------------
+# error codes the GPU path must reproduce
+# --------------------------------------------------------------------------
+
+def test_error_codes():
+    sc = S.tiny_2d()
+    os_ = oscene(sc)
+    x, v, C, F = [a.copy() for a in f64(sc.state)]
+    xb = x.copy(); xb[0, 3] = 0.2 / sc.n_grid          # base -1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.step_fwd(os_, (xb, v, C, F), sc.act_id)
+    assert e.value.code == -3
+    Fb = F.copy(); Fb[0, 5] = -1.0; Fb[1, 5] = 0; Fb[2, 5] = 0; Fb[3, 5] = 1.0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.step_fwd(os_, (x, v, C, Fb), sc.act_id)
+    assert e.value.code == -4
+    vb = v.copy(); vb[1, 2] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.step_fwd(os_, (x, vb, C, F), sc.act_id)
+    assert e.value.code == -5
