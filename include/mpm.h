@@ -1,0 +1,203 @@
+/*
+ * mpm.h -- C ABI of libmpm, an MI355X (gfx950) implementation of the
+ * differentiable MLS-MPM substep of ChainQueen (Hu et al., arXiv 1810.01054):
+ * particle-to-grid transfer, grid operations and grid-to-particle transfer
+ * (section III, steps 1-3) and their reverse pass (supplement: backward P2G
+ * (A)-(C), backward grid operations (D)-(E), backward G2P (F)-(K)).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers marked DEVICE are device (HBM) addresses owned by the caller; the
+ * library reads/writes them only during the call's stream-ordered work and
+ * never frees or keeps them.  Pointers marked HOST are host memory, read
+ * during the call only.  All floating-point data are FP32.
+ *
+ * A context holds one or more scenes of the same dimension d (2 or 3).  The
+ * particles of all scenes are concatenated: scene s owns particles
+ * [off_s, off_s + N_s) with off_s = N_0 + ... + N_{s-1}; N_tot is the total.
+ * A particle state (Table I: x_p, v_p, C_p, F_p) is four DEVICE arrays in
+ * structure-of-arrays layout:
+ *     x, v : [d][N_tot]     component a of particle p at a*N_tot + p
+ *     C, F : [d*d][N_tot]   entry (a,b) of particle p at (a*d+b)*N_tot + p
+ * The adjoint of a state (dL/dx, dL/dv, dL/dC, dL/dF) uses the same struct
+ * and layout.  Actuators are numbered per scene; actuator j of scene s has
+ * the global index act_off_s + j with act_off_s = n_act_0 + ... + n_act_{s-1};
+ * n_act_tot is the total.  Per-step actuation scalars s_j (the sigma_pa =
+ * s_j diag(axis) of the actuation model) are FP32 [n_act_tot] per step.
+ *
+ * Grids are library-owned: scene s has n_s^d nodes at x_i = i/n_s, node
+ * (i0,i1[,i2]) at linear index ((i0*n)+i1)*n+i2 (last axis fastest).
+ *
+ * Every call is asynchronous on the context's stream unless stated
+ * otherwise.  Errors: calls return 0 (MPM_OK) or a negative MPM_ERR_* code.
+ * Argument errors are detected on the host before any work is queued.
+ * Errors detected by the kernels (MPM_ERR_DOMAIN, MPM_ERR_INVERTED,
+ * MPM_ERR_NONFINITE) set a sticky device error word; they are reported by
+ * mpm_sync_errors() and by the calls documented as synchronising, after
+ * which the context is poisoned: every later call returns that error until
+ * the context is destroyed.  Outputs of a call whose work raised a device
+ * error are unspecified.  A context is used by one host thread at a time.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPM_OK 0
+#define MPM_ERR_ARG (-1)       /* invalid argument (host-side check)        */
+#define MPM_ERR_OOM (-2)       /* library scratch allocation failed          */
+#define MPM_ERR_DOMAIN (-3)    /* a stencil base left [0, n-3] (or x not finite) */
+#define MPM_ERR_INVERTED (-4)  /* det F <= 0                                 */
+#define MPM_ERR_NONFINITE (-5) /* a non-finite value was produced            */
+#define MPM_ERR_HIP (-6)       /* a HIP runtime call failed                  */
+#define MPM_ERR_STATE (-7)     /* call out of order (e.g. no tape)           */
+
+typedef struct mpm_ctx mpm_ctx;
+
+/* One scene (HOST).  Physical meaning as in Table I: dt, E, nu, rho, V0 =
+ * V_p^0 (equal for all particles), particle mass m_p = rho * V0.  Nodes
+ * closer than `wall` to the box faces (index < wall or >= n - wall on any
+ * axis) are sticky walls: their velocity is set to zero after gravity. */
+typedef struct mpm_scene {
+  int32_t dim;         /* 2 or 3 (all scenes of a context alike)           */
+  int32_t n_grid;      /* n: nodes per axis, dx = 1/n; n >= 3               */
+  int32_t n_particles; /* N_s >= 0                                          */
+  int32_t n_act;       /* actuators of this scene, 0..MPM_MAX_ACT           */
+  int32_t wall;        /* sticky-wall thickness in nodes, >= 0              */
+  int32_t reserved;    /* must be 0                                         */
+  float dt, E, nu, rho, V0;
+  float gravity[3];    /* acceleration (only the first d entries are used)  */
+  float act_axis[3];   /* sigma_pa = s_j diag(act_axis)                     */
+} mpm_scene;
+
+#define MPM_MAX_ACT 4096
+
+/* Tuning options (HOST, nullable = defaults). */
+typedef struct mpm_opts {
+  int32_t tile;        /* cells per tile edge for binning; 0 = default
+                          (8 in 2D, 4 in 3D)                                 */
+  int32_t sort;        /* rollouts reorder particles by tile; 1 = yes
+                          (default), 0 = keep the caller's order             */
+  int32_t reserved[6]; /* must be 0                                         */
+} mpm_opts;
+
+/* Particle state or its adjoint (DEVICE pointers, layout above). */
+typedef struct mpm_state {
+  float *x, *v, *C, *F;
+} mpm_state;
+
+/* Create a context for `n_scenes` scenes (HOST array).  `act_id` (HOST,
+ * int32 [N_tot], nullable = all passive) gives each particle's actuator
+ * within its scene, -1 for passive particles; it is copied.  `stream` is a
+ * hipStream_t (NULL = the null stream) on which all work of the context is
+ * queued.  Allocates the grids and scratch; synchronises the stream once.
+ * Errors: MPM_ERR_ARG (bad scene or id), MPM_ERR_OOM, MPM_ERR_HIP. */
+int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
+             const int32_t *act_id, void *stream, const mpm_opts *opts);
+
+/* Release every library allocation (after synchronising the stream). */
+void mpm_destroy(mpm_ctx *ctx);
+
+/* Change the stream of later work (hipStream_t, NULL = null stream). */
+int mpm_set_stream(mpm_ctx *ctx, void *stream);
+
+/* Sizes of the context: N_tot, n_act_tot, total grid nodes. Any may be NULL. */
+int mpm_info(const mpm_ctx *ctx, int64_t *n_particles, int32_t *n_act,
+             int64_t *n_nodes);
+
+/* One substep (section III, steps 1-3; gravity and walls as in mpm_scene):
+ *   P2G:  m_i = sum_p N m_p,  p_i = sum_p N [m_p v_p + G_p (x_i - x_p)],
+ *         G_p = -(4/dx^2) dt V0 (P(F_p) + F_p sigma_pa) F_p^T + m_p C_p;
+ *   grid: v_i = p_i/m_i + dt g (m_i > 0, else 0), 0 on wall nodes;
+ *   G2P:  v' = sum_i N v_i,  C' = (4/dx^2) sum_i N v_i (x_i - x_p)^T,
+ *         F' = (I + dt C') F,  x' = x + dt v'.
+ * P(F) is the compressible neo-Hookean PK1 stress with Lame parameters from
+ * (E, nu).  `act_n` is DEVICE [n_act_tot] (NULL when n_act_tot = 0).
+ * `s_np1` may equal `s_n` (in place).  The grid of this step stays readable
+ * through mpm_get_grid until the next call. */
+int mpm_step_forward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
+                     mpm_state *s_np1);
+
+/* Reverse of one substep (supplement (A)-(K)): given state n (`s_n`), its
+ * actuation and the adjoint of state n+1 (`g_np1`), writes the adjoint of
+ * state n to `g_n` (may equal `g_np1`) and ADDS dL/ds_j^n to `g_act_n`
+ * (DEVICE [n_act_tot], nullable).  The forward grid of step n is recomputed
+ * from `s_n`. */
+int mpm_step_backward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
+                      const mpm_state *g_np1, mpm_state *g_n, float *g_act_n);
+
+/* T substeps from s0 with per-step actuation `act` (DEVICE [T][n_act_tot],
+ * copied into the tape) writing the final state to sT.  The states needed by
+ * the reverse pass are kept in a library-owned tape (the paper's "memo"):
+ *   ckpt_k = 0  every state and grid is stored (no recompute);
+ *   ckpt_k >= 1 every k-th state is stored and each segment of k substeps is
+ *               recomputed from its checkpoint during the reverse pass.
+ * If `gT` is non-NULL the reverse pass runs at once and writes the adjoint
+ * of s0 to `g0` and dL/ds [T][n_act_tot] to `g_act` (DEVICE, overwritten,
+ * nullable); otherwise the tape is kept for mpm_rollout_backward.  The tape
+ * lives until the next mpm_rollout or mpm_destroy.  Synchronises once
+ * (after binning the particles) and returns device errors found up to then.
+ * Errors: MPM_ERR_ARG, MPM_ERR_OOM, the device errors. */
+int mpm_rollout(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
+                const float *act, mpm_state *sT, const mpm_state *gT,
+                mpm_state *g0, float *g_act);
+
+/* Reverse pass over the tape of the last mpm_rollout: chain rule across the
+ * T substeps from dL/ds^T (`gT`) to dL/ds^0 (`g0`) and dL/ds [T][n_act_tot]
+ * (`g_act`, overwritten, nullable).  MPM_ERR_STATE without a tape.  The tape
+ * stays valid (the reverse pass may be run again with another gT). */
+int mpm_rollout_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
+                         float *g_act);
+
+/* Copy the grid of the last mpm_step_forward (DEVICE, caller-owned,
+ * nullable): m [G], p [d][G], v [d][G] with G the total node count (scenes
+ * concatenated in order, each n_s^d nodes).  Stream-ordered copy. */
+int mpm_get_grid(mpm_ctx *ctx, float *m, float *p, float *v);
+
+/* Sinusoid actuation bank (the actuation schedule of the paper's
+ * controllers, open-loop form): act[n][j] = sum_k amp[j][k]
+ * sin(2 pi freq[k] n dt + phase[j][k]), n < T, j < n_act, k < n_freq.
+ * DEVICE arrays: freq [n_freq], amp/phase [n_act][n_freq], act [T][n_act].
+ * `stream` is a hipStream_t.  Stateless (no context). */
+int mpm_act_bank_forward(void *stream, int T, int n_act, int n_freq, float dt,
+                         const float *freq, const float *amp,
+                         const float *phase, float *act);
+
+/* Its reverse: g_amp, g_phase [n_act][n_freq] (DEVICE, overwritten) from
+ * g_act [T][n_act]. */
+int mpm_act_bank_backward(void *stream, int T, int n_act, int n_freq,
+                          float dt, const float *freq, const float *amp,
+                          const float *phase, const float *g_act,
+                          float *g_amp, float *g_phase);
+
+/* Synchronise the context's stream and return the first device-side error
+ * (MPM_OK if none).  A non-zero result poisons the context. */
+int mpm_sync_errors(mpm_ctx *ctx);
+
+/* Kernel timing with HIP events on the context's stream.  `mask` selects
+ * the kernels to bracket (bit k = kernel id k below; 0 = off).  Each
+ * selected launch records a start and a stop event; mpm_profile_read
+ * synchronises the stream, returns per-kernel launch counts and summed
+ * milliseconds (HOST arrays of MPM_NUM_KERNELS entries, nullable) and
+ * resets the accumulators.  Events add a small gap per bracketed launch. */
+#define MPM_K_P2G 0
+#define MPM_K_GRID 1
+#define MPM_K_G2P 2
+#define MPM_K_ADJ_SCATTER 3
+#define MPM_K_ADJ_GRID 4
+#define MPM_K_ADJ_GATHER 5
+#define MPM_NUM_KERNELS 6
+int mpm_profile(mpm_ctx *ctx, uint32_t mask);
+int mpm_profile_read(mpm_ctx *ctx, int64_t *count, double *ms);
+
+/* Static description of an error code. */
+const char *mpm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPM_H */

@@ -1,0 +1,65 @@
+"""torch.autograd wrappers over whole rollouts (the paper's memo-based
+gradient evaluation, here a library-owned tape with checkpoint + recompute).
+
+``rollout(sim, state0, act, T, ckpt_k)`` returns the final state; its
+backward runs ``mpm_rollout_backward`` over the tape of that same rollout.
+A context keeps one tape, so a second rollout on the same simulator makes
+the first one's backward raise instead of returning wrong gradients.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from .sim import Simulator, act_bank_backward, act_bank_forward
+
+
+class MPMRolloutFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, x0, v0, C0, F0, act):
+        sT = sim.rollout(tuple(t.contiguous() for t in (x0, v0, C0, F0)),
+                         act.contiguous() if act is not None else None, T, ckpt_k)
+        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
+        ctx.sim, ctx.T, ctx.gen = sim, T, sim._tape_gen
+        ctx.has_act = act is not None
+        return sT
+
+    @staticmethod
+    def backward(ctx, gx, gv, gC, gF):
+        sim = ctx.sim
+        if getattr(sim, "_tape_gen", None) != ctx.gen:
+            raise RuntimeError("the simulator ran another rollout since this one; "
+                               "its tape is gone (use one Simulator per live graph)")
+        ref = sim.empty_state()
+        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
+                  for t, r in zip((gx, gv, gC, gF), ref))
+        g0, g_act = sim.rollout_backward(g, ctx.T)
+        return (None, None, None, *g0, g_act if ctx.has_act else None)
+
+
+class ActBankFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, T: int, dt: float, freq, amp, phase):
+        ctx.save_for_backward(freq, amp, phase)
+        ctx.T, ctx.dt = T, dt
+        return act_bank_forward(T, dt, freq.contiguous(), amp.contiguous(),
+                                phase.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_act):
+        freq, amp, phase = ctx.saved_tensors
+        ga, gp = act_bank_backward(ctx.T, ctx.dt, freq, amp, phase, g_act.contiguous())
+        return None, None, None, ga, gp
+
+
+def rollout(sim: Simulator, state0, act: Optional[torch.Tensor], T: int,
+            ckpt_k: int = 32):
+    """Differentiable T-substep rollout: returns (xT, vT, CT, FT)."""
+    x0, v0, C0, F0 = state0
+    return MPMRolloutFn.apply(sim, T, ckpt_k, x0, v0, C0, F0, act)
+
+
+def act_bank(T: int, dt: float, freq, amp, phase):
+    """Differentiable sinusoid actuation schedule act[T][n_act]."""
+    return ActBankFn.apply(T, dt, freq, amp, phase)

@@ -1,0 +1,936 @@
+// mpm_api.hip -- host implementation of the libmpm C ABI (include/mpm.h).
+//
+// One context = a fixed batch of scenes of one dimension.  All kernels of a
+// substep cover every scene of the batch in one launch (chunks carry their
+// scene).  Rollouts bin the particles once (tile / rank / cell order), run on
+// library-owned sorted copies, keep a tape of checkpoints (or of every state
+// and grid), and un-permute results on the way out.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_internal.h"
+
+using namespace mpm;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct mpm_ctx {
+  int dim = 0;
+  int n_scenes = 0;
+  int64_t N = 0;        // total particles
+  int n_act = 0;        // total actuators
+  int64_t G = 0;        // total grid nodes
+  int tile = 0;
+  int sort = 1;
+  hipStream_t stream = nullptr;
+  int poisoned = 0;
+
+  std::vector<DevScene> h_scenes;
+  DevScene *d_scenes = nullptr;
+  std::vector<int> h_act_id;
+
+  // caller-order chunks (step calls, unsorted rollouts)
+  Chunk *d_chunks_user = nullptr;
+  int n_chunks_user = 0;
+  GridBlock *d_gblocks = nullptr;
+  int n_gblocks = 0;
+  int *d_act_id = nullptr;   // caller order
+  int *d_pscene = nullptr;   // scene of each particle (caller order)
+
+  // grids
+  float *gm = nullptr, *gp = nullptr, *gv = nullptr;
+  float *vbar = nullptr, *pbar = nullptr, *mbar = nullptr;
+  double *gact = nullptr;    // [gact_cap] FP64 accumulators for dL/ds
+  int64_t gact_cap = 0;
+  unsigned *d_err = nullptr;
+
+  // step_backward scratch: one state (for C^{n+1})
+  float *scratch = nullptr;
+
+  // binning
+  int n_tiles = 0;
+  int *d_tile_scene = nullptr, *d_tile_cnt = nullptr, *d_cell_cnt = nullptr;
+  int *d_ptile = nullptr, *d_pcell = nullptr, *d_prank = nullptr;
+  int *d_tile_start = nullptr, *d_nch = nullptr, *d_chunk_start = nullptr;
+  int *d_perm = nullptr, *d_act_sorted = nullptr;
+  Chunk *d_chunks_sorted = nullptr;
+  int n_chunks_sorted = 0;
+
+  // tape
+  struct Tape {
+    int valid = 0, T = 0, k = 0, memo = 0, sorted = 0;
+    float *states = nullptr;  // slots of one state each
+    int64_t state_cap = 0;    // slots allocated
+    float *grids = nullptr;   // slots of (1 + d) * G floats (m, p)
+    int64_t grid_cap = 0;
+    float *act = nullptr;     // [T][n_act]
+    int64_t act_cap = 0;
+    float *pp = nullptr;      // two ping-pong states
+    float *adj = nullptr;     // two adjoint states
+  } tape;
+
+  // kernel timing (mpm_profile)
+  struct Prof {
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;  // start/stop pairs
+    size_t used = 0;
+    std::vector<int> kid;          // kernel id of each pair
+    int64_t count[MPM_NUM_KERNELS] = {};
+    double ms[MPM_NUM_KERNELS] = {};
+  } prof;
+
+  int64_t state_floats() const {
+    return (int64_t)(2 * dim + 2 * dim * dim) * N;
+  }
+};
+
+namespace {
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
+
+template <typename T>
+int dmalloc(T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return MPM_ERR_OOM;
+  }
+  return MPM_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+#define RC(x)                  \
+  do {                         \
+    int _rc = (x);             \
+    if (_rc) return _rc;       \
+  } while (0)
+
+State state_at(const mpm_ctx *c, float *base) {
+  const int64_t N = c->N, d = c->dim;
+  State s;
+  s.x = base;
+  s.v = base + d * N;
+  s.C = base + 2 * d * N;
+  s.F = base + 2 * d * N + d * d * N;
+  return s;
+}
+
+CState cs(const State &s) { return CState{s.x, s.v, s.C, s.F}; }
+CState cs(const mpm_state &s) { return CState{s.x, s.v, s.C, s.F}; }
+State st(const mpm_state &s) { return State{s.x, s.v, s.C, s.F}; }
+
+bool state_ok(const mpm_ctx *c, const mpm_state *s) {
+  if (!s) return false;
+  if (c->N == 0) return true;
+  return s->x && s->v && s->C && s->F;
+}
+
+int check_ctx(mpm_ctx *c) {
+  if (!c) return MPM_ERR_ARG;
+  if (c->poisoned) return c->poisoned;
+  return MPM_OK;
+}
+
+// ---- kernel timing ---------------------------------------------------------
+
+constexpr size_t PROF_MAX_EVENTS = 1 << 20;
+
+hipEvent_t prof_event(mpm_ctx *c) {
+  auto &P = c->prof;
+  if (P.used == P.pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P.pool.push_back(e);
+  }
+  return P.pool[P.used++];
+}
+
+// Bracket one launch of kernel k with events (when selected by the mask).
+struct ProfScope {
+  mpm_ctx *c;
+  int k;
+  bool on;
+  ProfScope(mpm_ctx *c_, int k_) : c(c_), k(k_) {
+    on = (c->prof.mask >> k & 1u) && c->prof.used + 2 <= PROF_MAX_EVENTS;
+    if (on) {
+      hipEvent_t e = prof_event(c);
+      on = e && hipEventRecord(e, c->stream) == hipSuccess;
+    }
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEvent_t e = prof_event(c);
+    if (e && hipEventRecord(e, c->stream) == hipSuccess) c->prof.kid.push_back(k);
+    else c->prof.used -= e ? 2 : 1;
+  }
+};
+
+int decode_err(unsigned bits) {
+  if (bits & EB_DOMAIN) return MPM_ERR_DOMAIN;
+  if (bits & EB_INVERTED) return MPM_ERR_INVERTED;
+  if (bits & EB_NONFINITE) return MPM_ERR_NONFINITE;
+  return MPM_OK;
+}
+
+int read_err(mpm_ctx *c) {
+  unsigned bits = 0;
+  RC(hip_ok(hipMemcpyAsync(&bits, c->d_err, sizeof(unsigned),
+                           hipMemcpyDeviceToHost, c->stream)));
+  RC(hip_ok(hipStreamSynchronize(c->stream)));
+  int e = decode_err(bits);
+  if (e) c->poisoned = e;
+  return e;
+}
+
+// ---- the three kernels of one forward substep ------------------------------
+
+int fwd_p2g(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
+            const int *act_id, const float *act, float *gm, float *gp) {
+  P2GArgs a;
+  a.scenes = c->d_scenes;
+  a.chunks = chunks;
+  a.n_chunks = n_chunks;
+  a.s = s;
+  a.ld = (int)c->N;
+  a.act_id = act_id;
+  a.act = act;
+  a.gm = gm;
+  a.gp = gp;
+  a.G = c->G;
+  a.err = c->d_err;
+  ProfScope ps(c, MPM_K_P2G);
+  return launch_p2g(c->dim, a, c->stream);
+}
+
+int fwd_grid(mpm_ctx *c, float *gm, float *gp, float *gv, int zero_mp) {
+  GridArgs a;
+  a.scenes = c->d_scenes;
+  a.blocks = c->d_gblocks;
+  a.n_blocks = c->n_gblocks;
+  a.gm = gm;
+  a.gp = gp;
+  a.gv = gv;
+  a.G = c->G;
+  a.zero_mp = zero_mp;
+  ProfScope ps(c, MPM_K_GRID);
+  return launch_grid(c->dim, a, c->stream);
+}
+
+int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
+            State out, const float *gv) {
+  G2PArgs a;
+  a.scenes = c->d_scenes;
+  a.chunks = chunks;
+  a.n_chunks = n_chunks;
+  a.s = s;
+  a.out = out;
+  a.ld = (int)c->N;
+  a.gv = gv;
+  a.G = c->G;
+  a.err = c->d_err;
+  ProfScope ps(c, MPM_K_G2P);
+  return launch_g2p(c->dim, a, c->stream);
+}
+
+// ---- the three kernels of one reverse substep ------------------------------
+// gm/gp: forward grid of step n (m, p).  C1: C of state n+1.
+
+int bwd_step(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
+             const float *C1, const int *act_id, const float *act,
+             const float *gm, const float *gp, CState g1, State g0,
+             double *gact) {
+  AdjScatterArgs r1;
+  r1.scenes = c->d_scenes;
+  r1.chunks = chunks;
+  r1.n_chunks = n_chunks;
+  r1.s = s;
+  r1.g1 = g1;
+  r1.ld = (int)c->N;
+  r1.vbar = c->vbar;
+  r1.G = c->G;
+  {
+    ProfScope ps(c, MPM_K_ADJ_SCATTER);
+    RC(launch_adj_scatter(c->dim, r1, c->stream));
+  }
+
+  AdjGridArgs r2;
+  r2.scenes = c->d_scenes;
+  r2.blocks = c->d_gblocks;
+  r2.n_blocks = c->n_gblocks;
+  r2.gm = gm;
+  r2.gp = gp;
+  r2.vbar = c->vbar;
+  r2.pbar = c->pbar;
+  r2.mbar = c->mbar;
+  r2.gv = c->gv;
+  r2.G = c->G;
+  {
+    ProfScope ps(c, MPM_K_ADJ_GRID);
+    RC(launch_adj_grid(c->dim, r2, c->stream));
+  }
+
+  AdjGatherArgs r3;
+  r3.scenes = c->d_scenes;
+  r3.chunks = chunks;
+  r3.n_chunks = n_chunks;
+  r3.s = s;
+  r3.C1 = C1;
+  r3.g1 = g1;
+  r3.g0 = g0;
+  r3.ld = (int)c->N;
+  r3.act_id = act_id;
+  r3.act = act;
+  r3.pbar = c->pbar;
+  r3.mbar = c->mbar;
+  r3.gv = c->gv;
+  r3.G = c->G;
+  r3.gact = gact;
+  r3.err = c->d_err;
+  ProfScope ps(c, MPM_K_ADJ_GATHER);
+  return launch_adj_gather(c->dim, r3, c->stream);
+}
+
+int ensure_gact(mpm_ctx *c, int64_t n) {
+  if (n <= c->gact_cap) return MPM_OK;
+  dfree(c->gact);
+  c->gact_cap = 0;
+  RC(dmalloc(&c->gact, n));
+  c->gact_cap = n;
+  return MPM_OK;
+}
+
+// ---- binning: sorted order, chunks per tile --------------------------------
+
+int bin_particles(mpm_ctx *c, const float *x) {
+  const int cpt = c->dim == 2 ? c->tile * c->tile : c->tile * c->tile * c->tile;
+  hipStream_t s = c->stream;
+  RC(launch_fill_i32(c->d_cell_cnt, (int64_t)c->n_tiles * cpt, s));
+  RC(launch_fill_i32(c->d_tile_cnt, c->n_tiles, s));
+  SortArgs a;
+  a.scenes = c->d_scenes;
+  a.pscene = c->d_pscene;
+  a.N = (int)c->N;
+  a.x = x;
+  a.ld = (int)c->N;
+  a.tile = c->tile;
+  a.cell_cnt = c->d_cell_cnt;
+  a.tile_cnt = c->d_tile_cnt;
+  a.ptile = c->d_ptile;
+  a.pcell = c->d_pcell;
+  a.prank = c->d_prank;
+  a.err = c->d_err;
+  RC(launch_sort_count(c->dim, a, s));
+  RC(launch_scan_i32(c->d_tile_cnt, c->d_tile_start, c->n_tiles, s));
+  RC(launch_sort_place(c->dim, a, c->d_tile_start, c->d_perm, s));
+  RC(launch_chunk_count(c->d_tile_cnt, c->n_tiles, c->d_nch, s));
+  RC(launch_scan_i32(c->d_nch, c->d_chunk_start, c->n_tiles, s));
+  RC(launch_build_chunks(c->d_tile_cnt, c->d_tile_start, c->d_chunk_start,
+                         c->d_tile_scene, c->n_tiles, c->d_chunks_sorted, s));
+  RC(launch_permute_i32(c->d_act_id, c->d_act_sorted, c->d_perm, (int)c->N, s));
+  int nch = 0;
+  RC(hip_ok(hipMemcpyAsync(&nch, c->d_chunk_start + c->n_tiles, sizeof(int),
+                           hipMemcpyDeviceToHost, s)));
+  RC(read_err(c));  // synchronises
+  c->n_chunks_sorted = nch;
+  return MPM_OK;
+}
+
+int permute_state(mpm_ctx *c, const mpm_state &src, State dst, int scatter) {
+  // gather: dst[i] = src[perm[i]];  scatter: dst[perm[i]] = src[i]
+  const int d = c->dim, N = (int)c->N;
+  RC(launch_permute_rows(src.x, dst.x, c->d_perm, N, N, d, scatter, c->stream));
+  RC(launch_permute_rows(src.v, dst.v, c->d_perm, N, N, d, scatter, c->stream));
+  RC(launch_permute_rows(src.C, dst.C, c->d_perm, N, N, d * d, scatter,
+                         c->stream));
+  RC(launch_permute_rows(src.F, dst.F, c->d_perm, N, N, d * d, scatter,
+                         c->stream));
+  return MPM_OK;
+}
+
+int copy_state(mpm_ctx *c, const mpm_state &src, State dst) {
+  const size_t vb = sizeof(float) * c->dim * c->N;
+  const size_t mb = sizeof(float) * c->dim * c->dim * c->N;
+  RC(hip_ok(hipMemcpyAsync(dst.x, src.x, vb, hipMemcpyDeviceToDevice, c->stream)));
+  RC(hip_ok(hipMemcpyAsync(dst.v, src.v, vb, hipMemcpyDeviceToDevice, c->stream)));
+  RC(hip_ok(hipMemcpyAsync(dst.C, src.C, mb, hipMemcpyDeviceToDevice, c->stream)));
+  RC(hip_ok(hipMemcpyAsync(dst.F, src.F, mb, hipMemcpyDeviceToDevice, c->stream)));
+  return MPM_OK;
+}
+
+mpm_state ms(const State &s) { return mpm_state{s.x, s.v, s.C, s.F}; }
+
+// ---- tape ------------------------------------------------------------------
+
+int ensure_tape(mpm_ctx *c, int64_t states, int64_t grids, int64_t act) {
+  auto &t = c->tape;
+  const int64_t sf = c->state_floats();
+  const int64_t gf = (int64_t)(1 + c->dim) * c->G;
+  if (states > t.state_cap) {
+    dfree(t.states);
+    t.state_cap = 0;
+    RC(dmalloc(&t.states, states * sf));
+    t.state_cap = states;
+  }
+  if (grids > t.grid_cap) {
+    dfree(t.grids);
+    t.grid_cap = 0;
+    RC(dmalloc(&t.grids, grids * gf));
+    t.grid_cap = grids;
+  }
+  if (act > t.act_cap) {
+    dfree(t.act);
+    t.act_cap = 0;
+    RC(dmalloc(&t.act, act));
+    t.act_cap = act;
+  }
+  if (!t.pp) RC(dmalloc(&t.pp, 2 * sf));
+  if (!t.adj) RC(dmalloc(&t.adj, 2 * sf));
+  return MPM_OK;
+}
+
+// Slot layout:
+//   memo:  states[n] = S^n (n = 0..T), grids[n] = grid of step n (n < T)
+//   ckpt:  states[j] = S^{min(j k, T)} (j = 0..ceil(T/k)), then k segment
+//          slots; grids[0..k) = grids of the segment being reversed.
+struct Layout {
+  int T, k, memo, ncp;
+};
+
+float *slot_state(mpm_ctx *c, int64_t i) {
+  return c->tape.states + i * c->state_floats();
+}
+float *slot_grid(mpm_ctx *c, int64_t i) {
+  return c->tape.grids + i * (int64_t)(1 + c->dim) * c->G;
+}
+
+const Chunk *cur_chunks(mpm_ctx *c, int *n) {
+  if (c->tape.sorted) {
+    *n = c->n_chunks_sorted;
+    return c->d_chunks_sorted;
+  }
+  *n = c->n_chunks_user;
+  return c->d_chunks_user;
+}
+
+const int *cur_act_id(mpm_ctx *c) {
+  return c->tape.sorted ? c->d_act_sorted : c->d_act_id;
+}
+
+// forward state S^n for the rollout (ckpt mode; n is a checkpoint or lives in
+// the ping-pong pair)
+float *fwd_slot(mpm_ctx *c, const Layout &L, int n) {
+  if (L.memo) return slot_state(c, n);
+  if (n % L.k == 0) return slot_state(c, n / L.k);
+  if (n == L.T) return slot_state(c, L.ncp - 1);
+  return c->tape.pp + (int64_t)(n & 1) * c->state_floats();
+}
+
+int rollout_forward(mpm_ctx *c, const Layout &L) {
+  int nch = 0;
+  const Chunk *chunks = cur_chunks(c, &nch);
+  const int *ids = cur_act_id(c);
+  for (int n = 0; n < L.T; ++n) {
+    const State s = state_at(c, fwd_slot(c, L, n));
+    const State o = state_at(c, fwd_slot(c, L, n + 1));
+    const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
+    if (L.memo) {
+      float *g = slot_grid(c, n);
+      RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, g, g + c->G));
+      RC(fwd_grid(c, g, g + c->G, c->gv, 0));
+    } else {
+      RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+      RC(fwd_grid(c, c->gm, c->gp, c->gv, 1));
+    }
+    RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
+  }
+  return MPM_OK;
+}
+
+int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
+                     float *g_act) {
+  auto &t = c->tape;
+  const Layout L{t.T, t.k, t.memo, t.memo ? t.T + 1 : (t.T + t.k - 1) / t.k + 1};
+  int nch = 0;
+  const Chunk *chunks = cur_chunks(c, &nch);
+  const int *ids = cur_act_id(c);
+  const int64_t sf = c->state_floats();
+  State A1 = state_at(c, t.adj), A0 = state_at(c, t.adj + sf);
+  if (t.sorted) RC(permute_state(c, *gT, A1, 0));
+  else RC(copy_state(c, *gT, A1));
+  const int64_t nga = (int64_t)t.T * c->n_act;
+  if (nga > 0) {
+    RC(ensure_gact(c, nga));
+    RC(launch_fill_f64(c->gact, nga, c->stream));
+  }
+  const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
+  const int seglen = t.memo ? 1 : t.k;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
+    // state n and the C of state n+1 for n in [n0, n1)
+    auto S = [&](int n) -> float * {
+      if (t.memo) return slot_state(c, n);
+      if (n == n0) return slot_state(c, j);
+      if (n == n1) return slot_state(c, j + 1);
+      return slot_state(c, L.ncp + (n - n0));
+    };
+    auto Gr = [&](int n) -> float * {
+      return t.memo ? slot_grid(c, n) : slot_grid(c, n - n0);
+    };
+    if (!t.memo) {
+      // recompute the segment from its checkpoint, keeping states and grids
+      RC(launch_fill_f32(slot_grid(c, 0), (int64_t)(n1 - n0) * (1 + c->dim) * c->G,
+                         c->stream));
+      for (int n = n0; n < n1; ++n) {
+        const State s = state_at(c, S(n));
+        const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
+        float *g = Gr(n);
+        RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, g, g + c->G));
+        if (n + 1 < n1) {
+          RC(fwd_grid(c, g, g + c->G, c->gv, 0));
+          RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(n + 1)), c->gv));
+        }
+      }
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const State s = state_at(c, S(n));
+      const State s1 = state_at(c, S(n + 1));
+      const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
+      const float *g = Gr(n);
+      RC(bwd_step(c, chunks, nch, cs(s), s1.C, ids, act, g, g + c->G, cs(A1),
+                  A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
+      std::swap(A0, A1);
+    }
+  }
+  if (t.sorted) RC(permute_state(c, ms(A1), st(*g0), 1));
+  else RC(copy_state(c, ms(A1), st(*g0)));
+  if (g_act && nga > 0)
+    RC(launch_gact_store(c->gact, g_act, nga, 0, c->stream));
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpm_strerror(int code) {
+  switch (code) {
+    case MPM_OK: return "ok";
+    case MPM_ERR_ARG: return "invalid argument";
+    case MPM_ERR_OOM: return "out of device memory";
+    case MPM_ERR_DOMAIN: return "particle stencil outside the grid";
+    case MPM_ERR_INVERTED: return "deformation gradient with det F <= 0";
+    case MPM_ERR_NONFINITE: return "non-finite value produced";
+    case MPM_ERR_HIP: return "HIP runtime error";
+    case MPM_ERR_STATE: return "call out of order (no tape)";
+    default: return "unknown error";
+  }
+}
+
+void mpm_destroy(mpm_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  dfree(c->d_scenes);
+  dfree(c->d_chunks_user);
+  dfree(c->d_gblocks);
+  dfree(c->d_act_id);
+  dfree(c->d_pscene);
+  dfree(c->gm);
+  dfree(c->gp);
+  dfree(c->gv);
+  dfree(c->vbar);
+  dfree(c->pbar);
+  dfree(c->mbar);
+  dfree(c->gact);
+  dfree(c->d_err);
+  dfree(c->scratch);
+  dfree(c->d_tile_scene);
+  dfree(c->d_tile_cnt);
+  dfree(c->d_cell_cnt);
+  dfree(c->d_ptile);
+  dfree(c->d_pcell);
+  dfree(c->d_prank);
+  dfree(c->d_tile_start);
+  dfree(c->d_nch);
+  dfree(c->d_chunk_start);
+  dfree(c->d_perm);
+  dfree(c->d_act_sorted);
+  dfree(c->d_chunks_sorted);
+  dfree(c->tape.states);
+  dfree(c->tape.grids);
+  dfree(c->tape.act);
+  dfree(c->tape.pp);
+  dfree(c->tape.adj);
+  for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
+             const int32_t *act_id, void *stream, const mpm_opts *opts) {
+  if (!out) return MPM_ERR_ARG;
+  *out = nullptr;
+  if (!scenes || n_scenes <= 0) return MPM_ERR_ARG;
+  const int dim = scenes[0].dim;
+  if (dim != 2 && dim != 3) return MPM_ERR_ARG;
+  int tile = dim == 2 ? 8 : 4;
+  int sort = 1;
+  if (opts) {
+    for (int k = 0; k < 6; ++k)
+      if (opts->reserved[k]) return MPM_ERR_ARG;
+    if (opts->tile < 0 || opts->tile > 16) return MPM_ERR_ARG;
+    if (opts->tile) tile = opts->tile;
+    if (opts->sort != 0 && opts->sort != 1) return MPM_ERR_ARG;
+    sort = opts->sort;
+  }
+  int64_t N = 0, G = 0, n_tiles = 0;
+  int n_act = 0;
+  for (int s = 0; s < n_scenes; ++s) {
+    const mpm_scene &S = scenes[s];
+    if (S.dim != dim || S.n_grid < 3 || S.n_particles < 0 || S.n_act < 0 ||
+        S.n_act > MPM_MAX_ACT || S.wall < 0 || S.reserved != 0)
+      return MPM_ERR_ARG;
+    if (!(S.dt > 0.0f) || !(S.V0 > 0.0f) || !(S.rho > 0.0f) || !(S.E >= 0.0f) ||
+        !(S.nu > -1.0f && S.nu < 0.5f) || !std::isfinite(S.dt) ||
+        !std::isfinite(S.E))
+      return MPM_ERR_ARG;
+    const int64_t nn = dim == 2 ? (int64_t)S.n_grid * S.n_grid
+                                : (int64_t)S.n_grid * S.n_grid * S.n_grid;
+    const int64_t nt1 = (S.n_grid - 2 + tile - 1) / tile;
+    N += S.n_particles;
+    G += nn;
+    n_act += S.n_act;
+    n_tiles += dim == 2 ? nt1 * nt1 : nt1 * nt1 * nt1;
+  }
+  if (N > (int64_t)INT32_MAX / 16 || G > (int64_t)INT32_MAX / 4 ||
+      n_tiles > (int64_t)INT32_MAX / 4096)
+    return MPM_ERR_ARG;
+
+  mpm_ctx *c = new mpm_ctx();
+  c->dim = dim;
+  c->n_scenes = n_scenes;
+  c->N = N;
+  c->G = G;
+  c->n_act = n_act;
+  c->tile = tile;
+  c->sort = sort;
+  c->stream = (hipStream_t)stream;
+  c->n_tiles = (int)n_tiles;
+
+  std::vector<Chunk> chunks;
+  std::vector<GridBlock> gblocks;
+  std::vector<int> pscene(N), tile_scene;
+  c->h_act_id.assign(N, -1);
+  int64_t poff = 0, goff = 0, toff = 0;
+  int aoff = 0;
+  for (int s = 0; s < n_scenes; ++s) {
+    const mpm_scene &S = scenes[s];
+    DevScene d{};
+    d.n = S.n_grid;
+    d.np = S.n_particles;
+    d.p_off = (int)poff;
+    d.g_off = (int)goff;
+    d.n_act = S.n_act;
+    d.act_off = aoff;
+    d.wall = S.wall;
+    d.tile_off = (int)toff;
+    d.dt = S.dt;
+    d.dx = 1.0f / (float)S.n_grid;
+    d.inv_dx = (float)S.n_grid;
+    d.Dinv = 4.0f * (float)S.n_grid * (float)S.n_grid;
+    d.mu = S.E / (2.0f * (1.0f + S.nu));
+    d.la = S.E * S.nu / ((1.0f + S.nu) * (1.0f - 2.0f * S.nu));
+    d.mp = S.rho * S.V0;
+    d.V0 = S.V0;
+    d.kG = -d.Dinv * S.dt * S.V0;
+    for (int a = 0; a < 3; ++a) {
+      d.g[a] = S.gravity[a];
+      d.axis[a] = S.act_axis[a];
+    }
+    c->h_scenes.push_back(d);
+    for (int64_t k = 0; k < S.n_particles; k += CH) {
+      Chunk ch{s, (int)(poff + k), (int)std::min<int64_t>(CH, S.n_particles - k), 0};
+      chunks.push_back(ch);
+    }
+    const int64_t nn = dim == 2 ? (int64_t)S.n_grid * S.n_grid
+                                : (int64_t)S.n_grid * S.n_grid * S.n_grid;
+    for (int64_t k = 0; k < nn; k += 256) {
+      GridBlock gb{s, (int)k, (int)std::min<int64_t>(256, nn - k), 0};
+      gblocks.push_back(gb);
+    }
+    for (int64_t p = 0; p < S.n_particles; ++p) {
+      pscene[poff + p] = s;
+      if (act_id) {
+        const int j = act_id[poff + p];
+        if (j < -1 || j >= S.n_act) {
+          delete c;
+          return MPM_ERR_ARG;
+        }
+        c->h_act_id[poff + p] = j;
+      }
+    }
+    const int64_t nt1 = (S.n_grid - 2 + tile - 1) / tile;
+    const int64_t nts = dim == 2 ? nt1 * nt1 : nt1 * nt1 * nt1;
+    for (int64_t k = 0; k < nts; ++k) tile_scene.push_back(s);
+    poff += S.n_particles;
+    goff += nn;
+    toff += nts;
+    aoff += S.n_act;
+  }
+  c->n_chunks_user = (int)chunks.size();
+  c->n_gblocks = (int)gblocks.size();
+  const int64_t cpt = dim == 2 ? tile * tile : tile * tile * tile;
+
+  int rc = MPM_OK;
+#define TRY(x)                      \
+  do {                              \
+    rc = (x);                       \
+    if (rc) {                       \
+      mpm_destroy(c);               \
+      return rc;                    \
+    }                               \
+  } while (0)
+  TRY(dmalloc(&c->d_scenes, n_scenes));
+  TRY(dmalloc(&c->d_chunks_user, c->n_chunks_user));
+  TRY(dmalloc(&c->d_gblocks, c->n_gblocks));
+  TRY(dmalloc(&c->d_act_id, N));
+  TRY(dmalloc(&c->d_pscene, N));
+  TRY(dmalloc(&c->gm, G));
+  TRY(dmalloc(&c->gp, dim * G));
+  TRY(dmalloc(&c->gv, dim * G));
+  TRY(dmalloc(&c->vbar, dim * G));
+  TRY(dmalloc(&c->pbar, dim * G));
+  TRY(dmalloc(&c->mbar, G));
+  TRY(dmalloc(&c->d_err, 1));
+  TRY(dmalloc(&c->scratch, c->state_floats()));
+  TRY(dmalloc(&c->d_tile_scene, n_tiles));
+  TRY(dmalloc(&c->d_tile_cnt, n_tiles));
+  TRY(dmalloc(&c->d_cell_cnt, n_tiles * cpt));
+  TRY(dmalloc(&c->d_ptile, N));
+  TRY(dmalloc(&c->d_pcell, N));
+  TRY(dmalloc(&c->d_prank, N));
+  TRY(dmalloc(&c->d_tile_start, n_tiles + 1));
+  TRY(dmalloc(&c->d_nch, n_tiles));
+  TRY(dmalloc(&c->d_chunk_start, n_tiles + 1));
+  TRY(dmalloc(&c->d_perm, N));
+  TRY(dmalloc(&c->d_act_sorted, N));
+  TRY(dmalloc(&c->d_chunks_sorted, N / CH + n_tiles + 1));
+  if (n_act > 0) TRY(ensure_gact(c, n_act));
+
+  hipStream_t s = c->stream;
+  TRY(hip_ok(hipMemcpyAsync(c->d_scenes, c->h_scenes.data(),
+                            sizeof(DevScene) * n_scenes, hipMemcpyHostToDevice, s)));
+  TRY(hip_ok(hipMemcpyAsync(c->d_chunks_user, chunks.data(),
+                            sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, s)));
+  TRY(hip_ok(hipMemcpyAsync(c->d_gblocks, gblocks.data(),
+                            sizeof(GridBlock) * gblocks.size(), hipMemcpyHostToDevice, s)));
+  if (N > 0) {
+    TRY(hip_ok(hipMemcpyAsync(c->d_act_id, c->h_act_id.data(), sizeof(int) * N,
+                              hipMemcpyHostToDevice, s)));
+    TRY(hip_ok(hipMemcpyAsync(c->d_pscene, pscene.data(), sizeof(int) * N,
+                              hipMemcpyHostToDevice, s)));
+  }
+  TRY(hip_ok(hipMemcpyAsync(c->d_tile_scene, tile_scene.data(),
+                            sizeof(int) * tile_scene.size(), hipMemcpyHostToDevice, s)));
+  TRY(launch_fill_f32(c->gm, G, s));
+  TRY(launch_fill_f32(c->gp, dim * G, s));
+  TRY(launch_fill_f32(c->gv, dim * G, s));
+  TRY(launch_fill_f32(c->vbar, dim * G, s));
+  TRY(launch_fill_i32((int *)c->d_err, 1, s));
+  TRY(hip_ok(hipStreamSynchronize(s)));
+#undef TRY
+  *out = c;
+  return MPM_OK;
+}
+
+int mpm_set_stream(mpm_ctx *c, void *stream) {
+  if (!c) return MPM_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return MPM_OK;
+}
+
+int mpm_info(const mpm_ctx *c, int64_t *n_particles, int32_t *n_act,
+             int64_t *n_nodes) {
+  if (!c) return MPM_ERR_ARG;
+  if (n_particles) *n_particles = c->N;
+  if (n_act) *n_act = c->n_act;
+  if (n_nodes) *n_nodes = c->G;
+  return MPM_OK;
+}
+
+int mpm_sync_errors(mpm_ctx *c) {
+  if (!c) return MPM_ERR_ARG;
+  if (c->poisoned) return c->poisoned;
+  return read_err(c);
+}
+
+int mpm_step_forward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
+                     mpm_state *s_np1) {
+  RC(check_ctx(c));
+  if (!state_ok(c, s_n) || !state_ok(c, s_np1) || (c->n_act && !act_n))
+    return MPM_ERR_ARG;
+  RC(launch_fill_f32(c->gm, c->G, c->stream));
+  RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
+  RC(fwd_p2g(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), c->d_act_id,
+             act_n, c->gm, c->gp));
+  RC(fwd_grid(c, c->gm, c->gp, c->gv, 0));
+  RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), st(*s_np1),
+             c->gv));
+  return MPM_OK;
+}
+
+int mpm_get_grid(mpm_ctx *c, float *m, float *p, float *v) {
+  if (!c) return MPM_ERR_ARG;
+  const size_t g = sizeof(float) * c->G;
+  if (m) RC(hip_ok(hipMemcpyAsync(m, c->gm, g, hipMemcpyDeviceToDevice, c->stream)));
+  if (p)
+    RC(hip_ok(hipMemcpyAsync(p, c->gp, g * c->dim, hipMemcpyDeviceToDevice, c->stream)));
+  if (v)
+    RC(hip_ok(hipMemcpyAsync(v, c->gv, g * c->dim, hipMemcpyDeviceToDevice, c->stream)));
+  return MPM_OK;
+}
+
+int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
+                      const mpm_state *g_np1, mpm_state *g_n, float *g_act_n) {
+  RC(check_ctx(c));
+  if (!state_ok(c, s_n) || !state_ok(c, g_np1) || !state_ok(c, g_n) ||
+      (c->n_act && !act_n))
+    return MPM_ERR_ARG;
+  // forward grid of step n and C of state n+1
+  RC(launch_fill_f32(c->gm, c->G, c->stream));
+  RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
+  RC(fwd_p2g(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), c->d_act_id,
+             act_n, c->gm, c->gp));
+  RC(fwd_grid(c, c->gm, c->gp, c->gv, 0));
+  const State s1 = state_at(c, c->scratch);
+  RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1, c->gv));
+  double *gact = nullptr;
+  if (g_act_n && c->n_act > 0) {
+    RC(ensure_gact(c, c->n_act));
+    RC(launch_fill_f64(c->gact, c->n_act, c->stream));
+    gact = c->gact;
+  }
+  RC(bwd_step(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1.C,
+              c->d_act_id, act_n, c->gm, c->gp, cs(*g_np1), st(*g_n), gact));
+  if (gact) RC(launch_gact_store(gact, g_act_n, c->n_act, 1, c->stream));
+  return MPM_OK;
+}
+
+int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
+                const float *act, mpm_state *sT, const mpm_state *gT,
+                mpm_state *g0, float *g_act) {
+  RC(check_ctx(c));
+  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) ||
+      (c->n_act && T > 0 && !act) || (gT && !state_ok(c, gT)) ||
+      (gT && !state_ok(c, g0)))
+    return MPM_ERR_ARG;
+  auto &t = c->tape;
+  t.valid = 0;
+  const int memo = ckpt_k == 0;
+  const int k = memo ? 1 : std::min(ckpt_k, std::max(T, 1));
+  const int ncp = memo ? T + 1 : (T + k - 1) / k + 1;
+  const int64_t nstates = memo ? T + 1 : ncp + k;
+  const int64_t ngrids = memo ? T : k;
+  RC(ensure_tape(c, nstates, ngrids, (int64_t)T * c->n_act));
+  t.T = T;
+  t.k = k;
+  t.memo = memo;
+  t.sorted = c->sort && c->N > 0;
+  if (c->n_act && T > 0)
+    RC(hip_ok(hipMemcpyAsync(t.act, act, sizeof(float) * T * c->n_act,
+                             hipMemcpyDeviceToDevice, c->stream)));
+  const Layout L{T, k, memo, ncp};
+  const State S0 = state_at(c, slot_state(c, 0));
+  if (t.sorted) {
+    RC(bin_particles(c, s0->x));
+    RC(permute_state(c, *s0, S0, 0));
+  } else {
+    RC(copy_state(c, *s0, S0));
+  }
+  if (memo && T > 0)
+    RC(launch_fill_f32(slot_grid(c, 0), (int64_t)T * (1 + c->dim) * c->G,
+                       c->stream));
+  RC(rollout_forward(c, L));
+  const State ST = state_at(c, fwd_slot(c, L, T));
+  if (t.sorted) RC(permute_state(c, ms(ST), st(*sT), 1));
+  else RC(copy_state(c, ms(ST), st(*sT)));
+  t.valid = 1;
+  if (gT) return rollout_backward(c, gT, g0, g_act);
+  return MPM_OK;
+}
+
+int mpm_rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
+                         float *g_act) {
+  RC(check_ctx(c));
+  if (!c->tape.valid) return MPM_ERR_STATE;
+  if (!state_ok(c, gT) || !state_ok(c, g0)) return MPM_ERR_ARG;
+  return rollout_backward(c, gT, g0, g_act);
+}
+
+int mpm_profile(mpm_ctx *c, uint32_t mask) {
+  if (!c || (mask >> MPM_NUM_KERNELS)) return MPM_ERR_ARG;
+  c->prof.mask = mask;
+  return MPM_OK;
+}
+
+int mpm_profile_read(mpm_ctx *c, int64_t *count, double *ms) {
+  if (!c) return MPM_ERR_ARG;
+  auto &P = c->prof;
+  RC(hip_ok(hipStreamSynchronize(c->stream)));
+  for (size_t i = 0; i < P.kid.size(); ++i) {
+    float t = 0.0f;
+    RC(hip_ok(hipEventElapsedTime(&t, P.pool[2 * i], P.pool[2 * i + 1])));
+    P.count[P.kid[i]] += 1;
+    P.ms[P.kid[i]] += t;
+  }
+  for (int k = 0; k < MPM_NUM_KERNELS; ++k) {
+    if (count) count[k] = P.count[k];
+    if (ms) ms[k] = P.ms[k];
+    P.count[k] = 0;
+    P.ms[k] = 0.0;
+  }
+  P.kid.clear();
+  P.used = 0;
+  return MPM_OK;
+}
+
+int mpm_act_bank_forward(void *stream, int T, int n_act, int n_freq, float dt,
+                         const float *freq, const float *amp,
+                         const float *phase, float *act) {
+  if (T < 0 || n_act < 0 || n_freq < 0) return MPM_ERR_ARG;
+  if ((int64_t)T * n_act == 0) return MPM_OK;
+  if (!act || (n_freq > 0 && (!freq || !amp || !phase))) return MPM_ERR_ARG;
+  return launch_act_bank_fwd(T, n_act, n_freq, dt, freq, amp, phase, act,
+                             (hipStream_t)stream);
+}
+
+int mpm_act_bank_backward(void *stream, int T, int n_act, int n_freq,
+                          float dt, const float *freq, const float *amp,
+                          const float *phase, const float *g_act,
+                          float *g_amp, float *g_phase) {
+  if (T < 0 || n_act < 0 || n_freq < 0) return MPM_ERR_ARG;
+  if (n_act * n_freq == 0) return MPM_OK;
+  if (!freq || !amp || !phase || !g_amp || !g_phase || (T > 0 && !g_act))
+    return MPM_ERR_ARG;
+  return launch_act_bank_bwd(T, n_act, n_freq, dt, freq, amp, phase, g_act,
+                             g_amp, g_phase, (hipStream_t)stream);
+}
+
+}  // extern "C"

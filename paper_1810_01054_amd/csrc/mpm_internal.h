@@ -1,0 +1,184 @@
+// mpm_internal.h -- device-side data structures shared by the gfx950 kernels
+// (mpm_kernels.hip) and the host implementation of the C ABI (mpm_api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpm {
+
+// Particles handled by one workgroup (one particle per lane, 4 waves).
+constexpr int CH = 256;
+// Largest bounding box of grid nodes a workgroup stages in LDS; chunks whose
+// stencil box is larger fall back to global atomics / global loads.
+constexpr int LDS_NODES = 1024;
+// Per-scene actuators reduced in LDS by the adjoint gather; scenes with more
+// actuators add straight to global memory.
+constexpr int LDS_ACT = 64;
+
+// Sticky device error bits (ORed into the context's error word).
+enum : unsigned { EB_DOMAIN = 1u, EB_INVERTED = 2u, EB_NONFINITE = 4u };
+
+// Per-scene constants, precomputed on the host in FP32.
+struct DevScene {
+  int n;        // nodes per axis
+  int np;       // particles of the scene
+  int p_off;    // first particle (in the concatenated arrays)
+  int g_off;    // first grid node (in the concatenated grids)
+  int n_act;    // actuators of the scene
+  int act_off;  // first actuator (in the concatenated actuation vector)
+  int wall;     // sticky-wall thickness in nodes
+  int tile_off; // first tile of the scene (binning)
+  float dt, dx, inv_dx, Dinv;  // Dinv = 4 / dx^2
+  float mu, la, mp, V0;        // Lame parameters, particle mass and volume
+  float kG;                    // -Dinv * dt * V0 (stress part of G_p)
+  float g[3];                  // gravity
+  float axis[3];               // actuation axis
+};
+
+// A run of consecutive particles handled by one workgroup.
+struct Chunk {
+  int scene, start, count, pad;
+};
+
+// A run of consecutive grid nodes of one scene handled by one workgroup.
+struct GridBlock {
+  int scene, start, count, pad;
+};
+
+// Particle state (or its adjoint) in structure-of-arrays layout with leading
+// dimension ld: component a of particle p at a*ld + p.
+struct State {
+  float *x, *v, *C, *F;
+};
+struct CState {
+  const float *x, *v, *C, *F;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (mpm_kernels.hip)
+// ---------------------------------------------------------------------------
+
+struct P2GArgs {
+  const DevScene *scenes;
+  const Chunk *chunks;
+  int n_chunks;
+  CState s;
+  int ld;
+  const int *act_id;  // scene-local actuator of each particle (-1 passive)
+  const float *act;   // [n_act_tot] for this step
+  float *gm, *gp;     // grid mass [G], momentum [d][G]
+  int64_t G;
+  unsigned *err;
+};
+
+struct GridArgs {
+  const DevScene *scenes;
+  const GridBlock *blocks;
+  int n_blocks;
+  float *gm, *gp, *gv;
+  int64_t G;
+  int zero_mp;  // clear m and p after reading them (next P2G starts at 0)
+};
+
+struct G2PArgs {
+  const DevScene *scenes;
+  const Chunk *chunks;
+  int n_chunks;
+  CState s;     // reads x, F
+  State out;    // writes x, v, C, F (may alias s)
+  int ld;
+  const float *gv;
+  int64_t G;
+  unsigned *err;
+};
+
+struct AdjScatterArgs {
+  const DevScene *scenes;
+  const Chunk *chunks;
+  int n_chunks;
+  CState s;     // state n: x, F
+  CState g1;    // adjoint of state n+1
+  int ld;
+  float *vbar;  // [d][G] accumulated
+  int64_t G;
+};
+
+struct AdjGridArgs {
+  const DevScene *scenes;
+  const GridBlock *blocks;
+  int n_blocks;
+  const float *gm, *gp;  // forward grid of step n
+  float *vbar;           // read, then cleared
+  float *pbar, *mbar, *gv;  // written: dL/dp, dL/dm, forward v
+  int64_t G;
+};
+
+struct AdjGatherArgs {
+  const DevScene *scenes;
+  const Chunk *chunks;
+  int n_chunks;
+  CState s;          // state n
+  const float *C1;   // C of state n+1 ([d*d][ld])
+  CState g1;         // adjoint of state n+1
+  State g0;          // adjoint of state n (may alias g1)
+  int ld;
+  const int *act_id;
+  const float *act;  // [n_act_tot]
+  const float *pbar, *mbar, *gv;
+  int64_t G;
+  double *gact;      // [n_act_tot] accumulated dL/ds
+  unsigned *err;
+};
+
+struct SortArgs {
+  const DevScene *scenes;
+  const int *pscene;  // scene of each particle (caller order)
+  int N;
+  const float *x;
+  int ld;
+  int tile;           // cells per tile edge
+  int *cell_cnt;      // [n_tiles * tile^d], zeroed
+  int *tile_cnt;      // [n_tiles], zeroed
+  int *ptile, *pcell, *prank;
+  unsigned *err;
+};
+
+int launch_p2g(int dim, const P2GArgs &a, hipStream_t st);
+int launch_grid(int dim, const GridArgs &a, hipStream_t st);
+int launch_g2p(int dim, const G2PArgs &a, hipStream_t st);
+int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st);
+int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st);
+int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st);
+
+int launch_fill_f32(float *p, int64_t n, hipStream_t st);
+int launch_fill_f64(double *p, int64_t n, hipStream_t st);
+int launch_fill_i32(int *p, int64_t n, hipStream_t st);
+
+int launch_sort_count(int dim, const SortArgs &a, hipStream_t st);
+// Exclusive scan of in[0..n) into out[0..n] (out[n] = total), one workgroup.
+int launch_scan_i32(const int *in, int *out, int n, hipStream_t st);
+int launch_sort_place(int dim, const SortArgs &a, const int *tile_start,
+                      int *perm, hipStream_t st);
+int launch_chunk_count(const int *tile_cnt, int n_tiles, int *nch,
+                       hipStream_t st);
+int launch_build_chunks(const int *tile_cnt, const int *tile_start,
+                        const int *chunk_start, const int *tile_scene,
+                        int n_tiles, Chunk *chunks, hipStream_t st);
+// out = in[perm] (gather) or out[perm] = in (scatter) over every component
+// of a state with `ncomp` rows of length N (stride ld).
+int launch_permute_rows(const float *in, float *out, const int *perm, int N,
+                        int ld, int ncomp, int scatter, hipStream_t st);
+int launch_permute_i32(const int *in, int *out, const int *perm, int N,
+                       hipStream_t st);
+int launch_gact_store(const double *src, float *dst, int64_t n, int accumulate,
+                      hipStream_t st);
+int launch_act_bank_fwd(int T, int n_act, int n_freq, float dt,
+                        const float *freq, const float *amp,
+                        const float *phase, float *act, hipStream_t st);
+int launch_act_bank_bwd(int T, int n_act, int n_freq, float dt,
+                        const float *freq, const float *amp,
+                        const float *phase, const float *g_act, float *g_amp,
+                        float *g_phase, hipStream_t st);
+
+}  // namespace mpm

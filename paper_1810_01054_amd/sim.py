@@ -1,0 +1,217 @@
+"""Python face of libmpm: a context over a batch of scenes, with torch tensors
+for device memory and the current torch stream for ordering.
+
+Every method marshals arguments into one C-ABI call; no arithmetic of the
+method runs here.  Particle state tensors are FP32, contiguous, on the GPU,
+shaped like the C layout: x, v [d, N_tot], C, F [d*d, N_tot].
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+StateT = Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor]
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t: torch.Tensor, shape, name):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+
+
+def scene_struct(p: dict) -> _lib.Scene:
+    s = _lib.Scene()
+    s.dim, s.n_grid, s.n_particles = p["dim"], p["n_grid"], p["n_particles"]
+    s.n_act, s.wall, s.reserved = p.get("n_act", 0), p.get("wall", 3), 0
+    s.dt, s.E, s.nu = p["dt"], p["E"], p["nu"]
+    s.rho, s.V0 = p["rho"], p["V0"]
+    g = p.get("gravity", (0.0, -9.8, 0.0))
+    ax = p.get("act_axis", (0.0, 1.0, 0.0))
+    for k in range(3):
+        s.gravity[k] = g[k]
+        s.act_axis[k] = ax[k]
+    return s
+
+
+class Simulator:
+    """A libmpm context over ``scenes`` (dicts with the mpm_scene fields, e.g.
+    ``paper_1810_01054_amd.scenes.Scene.params()``)."""
+
+    def __init__(self, scenes: Sequence[dict], act_id: Optional[np.ndarray] = None,
+                 tile: int = 0, sort: bool = True, stream=None):
+        self.L = _lib.lib()
+        self.scenes = [dict(s) for s in scenes]
+        self.dim = self.scenes[0]["dim"]
+        arr = (_lib.Scene * len(scenes))(*[scene_struct(s) for s in self.scenes])
+        ids = None
+        if act_id is not None:
+            ids_np = np.ascontiguousarray(act_id, dtype=np.int32)
+            self._ids = ids_np
+            ids = ids_np.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        opts = _lib.Opts()
+        opts.tile, opts.sort = tile, int(bool(sort))
+        self.ctx = ctypes.c_void_p()
+        self._stream = stream
+        check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,
+                              _stream_ptr(stream), ctypes.byref(opts)), "mpm_init")
+        n, na, g = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        check(self.L.mpm_info(self.ctx, ctypes.byref(n), ctypes.byref(na), ctypes.byref(g)))
+        self.N, self.n_act, self.G = n.value, na.value, g.value
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.L.mpm_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        check(self.L.mpm_set_stream(self.ctx, _stream_ptr(self._stream)))
+
+    # -- helpers -------------------------------------------------------------
+    def empty_state(self, device="cuda") -> StateT:
+        d, N = self.dim, self.N
+        return (torch.empty(d, N, device=device), torch.empty(d, N, device=device),
+                torch.empty(d * d, N, device=device), torch.empty(d * d, N, device=device))
+
+    def zeros_state(self, device="cuda") -> StateT:
+        return tuple(torch.zeros_like(t) for t in self.empty_state(device))
+
+    def _state(self, s: StateT, name: str) -> _lib.State:
+        d, N = self.dim, self.N
+        shapes = [(d, N), (d, N), (d * d, N), (d * d, N)]
+        for t, sh, nm in zip(s, shapes, "xvCF"):
+            _check_tensor(t, sh, f"{name}.{nm}")
+        return _lib.State(*[t.data_ptr() for t in s])
+
+    def _act(self, act: Optional[torch.Tensor], rows: Optional[int]):
+        if self.n_act == 0:
+            return None
+        shape = (self.n_act,) if rows is None else (rows, self.n_act)
+        _check_tensor(act, shape, "act")
+        return _ptr(act)
+
+    # -- C ABI ---------------------------------------------------------------
+    def step_forward(self, s: StateT, act: Optional[torch.Tensor] = None,
+                     out: Optional[StateT] = None) -> StateT:
+        self._sync_stream()
+        out = out if out is not None else self.empty_state()
+        a, o = self._state(s, "s_n"), self._state(out, "s_np1")
+        check(self.L.mpm_step_forward(self.ctx, ctypes.byref(a), self._act(act, None),
+                                      ctypes.byref(o)), "mpm_step_forward")
+        return out
+
+    def step_backward(self, s: StateT, act: Optional[torch.Tensor], g_next: StateT,
+                      g_act: Optional[torch.Tensor] = None,
+                      out: Optional[StateT] = None) -> StateT:
+        self._sync_stream()
+        out = out if out is not None else self.empty_state()
+        a, g1, g0 = (self._state(s, "s_n"), self._state(g_next, "g_np1"),
+                     self._state(out, "g_n"))
+        if g_act is not None:
+            _check_tensor(g_act, (self.n_act,), "g_act")
+        check(self.L.mpm_step_backward(self.ctx, ctypes.byref(a), self._act(act, None),
+                                       ctypes.byref(g1), ctypes.byref(g0), _ptr(g_act)),
+              "mpm_step_backward")
+        return out
+
+    def rollout(self, s0: StateT, act: Optional[torch.Tensor], T: int, ckpt_k: int = 0,
+                gT: Optional[StateT] = None):
+        """Forward T substeps (tape kept).  With gT also the reverse pass:
+        returns (sT, g0, g_act)."""
+        self._sync_stream()
+        sT = self.empty_state()
+        a0, aT = self._state(s0, "s0"), self._state(sT, "sT")
+        act_p = self._act(act, T) if T > 0 else None
+        if gT is None:
+            check(self.L.mpm_rollout(self.ctx, T, ckpt_k, ctypes.byref(a0), act_p,
+                                     ctypes.byref(aT), None, None, None), "mpm_rollout")
+            return sT
+        g0 = self.empty_state()
+        g_act = torch.empty(T, self.n_act, device="cuda") if self.n_act else None
+        gg, g00 = self._state(gT, "gT"), self._state(g0, "g0")
+        check(self.L.mpm_rollout(self.ctx, T, ckpt_k, ctypes.byref(a0), act_p,
+                                 ctypes.byref(aT), ctypes.byref(gg), ctypes.byref(g00),
+                                 _ptr(g_act)), "mpm_rollout")
+        return sT, g0, g_act
+
+    def rollout_backward(self, gT: StateT, T: int):
+        self._sync_stream()
+        g0 = self.empty_state()
+        g_act = torch.empty(T, self.n_act, device="cuda") if self.n_act else None
+        gg, g00 = self._state(gT, "gT"), self._state(g0, "g0")
+        check(self.L.mpm_rollout_backward(self.ctx, ctypes.byref(gg), ctypes.byref(g00),
+                                          _ptr(g_act)), "mpm_rollout_backward")
+        return g0, g_act
+
+    def get_grid(self):
+        self._sync_stream()
+        m = torch.empty(self.G, device="cuda")
+        p = torch.empty(self.dim, self.G, device="cuda")
+        v = torch.empty(self.dim, self.G, device="cuda")
+        check(self.L.mpm_get_grid(self.ctx, _ptr(m), _ptr(p), _ptr(v)), "mpm_get_grid")
+        return m, p, v
+
+    def profile(self, kernels=()):
+        """Bracket the named kernels (see _lib.KERNELS) with HIP events."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << _lib.KERNELS.index(k)
+        check(self.L.mpm_profile(self.ctx, mask))
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total ms)} since the last read (synchronises)."""
+        n = len(_lib.KERNELS)
+        cnt = (ctypes.c_int64 * n)()
+        ms = (ctypes.c_double * n)()
+        check(self.L.mpm_profile_read(self.ctx, cnt, ms))
+        return {k: (cnt[i], ms[i]) for i, k in enumerate(_lib.KERNELS)}
+
+    def sync_errors(self):
+        check(self.L.mpm_sync_errors(self.ctx), "device error")
+
+
+def act_bank_forward(T: int, dt: float, freq: torch.Tensor, amp: torch.Tensor,
+                     phase: torch.Tensor, stream=None) -> torch.Tensor:
+    L = _lib.lib()
+    n_act, n_freq = amp.shape
+    act = torch.empty(T, n_act, device=amp.device)
+    for t, nm, sh in ((freq, "freq", (n_freq,)), (amp, "amp", (n_act, n_freq)),
+                      (phase, "phase", (n_act, n_freq))):
+        _check_tensor(t, sh, nm)
+    check(L.mpm_act_bank_forward(_stream_ptr(stream), T, n_act, n_freq, dt, _ptr(freq),
+                                 _ptr(amp), _ptr(phase), _ptr(act)), "act_bank_forward")
+    return act
+
+
+def act_bank_backward(T: int, dt: float, freq, amp, phase, g_act, stream=None):
+    L = _lib.lib()
+    n_act, n_freq = amp.shape
+    _check_tensor(g_act, (T, n_act), "g_act")
+    ga = torch.empty_like(amp)
+    gp = torch.empty_like(phase)
+    check(L.mpm_act_bank_backward(_stream_ptr(stream), T, n_act, n_freq, dt, _ptr(freq),
+                                  _ptr(amp), _ptr(phase), _ptr(g_act), _ptr(ga), _ptr(gp)),
+          "act_bank_backward")
+    return ga, gp
