@@ -87,6 +87,9 @@ def main():
                     help="checkpoint interval (0 = store every state)")
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="substeps of the oracle sample (0 = skip)")
+    ap.add_argument("--scatter", type=int, default=0,
+                    help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
+                         "2 per-cell in bin order, 3 per-cell after an LDS sort")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -113,7 +116,7 @@ def main():
     sc = S.config_3()
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
-    sim = Simulator([sc.params()], act_id=sc.act_id)
+    sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter)
     t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
     x0, v0, C0, F0 = (t(a) for a in sc.state)
     v0.requires_grad_(True)
@@ -130,6 +133,7 @@ def main():
 
     # warm-up; the first warm-up step also finds the dominant kernel
     dominant = "adj_gather"
+    warm_prof = None
     for w in range(max(args.warmup, 1)):
         if w == 0 and not args.no_profile:
             sim.profile(["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather"])
@@ -138,6 +142,8 @@ def main():
             prof = sim.profile_read()
             sim.profile([])
             dominant = max(prof, key=lambda kk: prof[kk][1])
+            warm_prof = {kk: round(ms * 1e3 / max(n, 1), 2)
+                         for kk, (n, ms) in prof.items() if n}
     sim.sync_errors()
     torch.cuda.synchronize()
 
@@ -191,11 +197,13 @@ def main():
                                f"16 actuators, T={T} substeps fwd+bwd, checkpoint k={k} "
                                f"with recompute, torch.autograd.Function",
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
+                   "scatter_mode": args.scatter,
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),
         "rollout_latency_ms": {"p50": round(percentile(lat, 0.5), 3),
                                "p99": round(percentile(lat, 0.99), 3)},
         "roofline": roof,
+        "kernel_avg_us": warm_prof,
         "cpu_baseline": None,
     }
     if args.cpu_sample > 0:

@@ -82,7 +82,12 @@ typedef struct mpm_opts {
                           (8 in 2D, 4 in 3D)                                 */
   int32_t sort;        /* rollouts reorder particles by tile; 1 = yes
                           (default), 0 = keep the caller's order             */
-  int32_t reserved[6]; /* must be 0                                         */
+  int32_t scatter;     /* binned scatters: 0 = default (3 when a tile has
+                          64 cells, else 1); 1 = per-particle LDS atomics;
+                          2 = per-cell register accumulation in bin order;
+                          3 = per-cell accumulation after an in-LDS sort of
+                          each tile by current cell (insensitive to drift)  */
+  int32_t reserved[5]; /* must be 0                                         */
 } mpm_opts;
 
 /* Particle state or its adjoint (DEVICE pointers, layout above). */

@@ -34,7 +34,7 @@ class Scene(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("sort", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("scatter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class State(ctypes.Structure):

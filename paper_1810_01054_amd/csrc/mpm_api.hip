@@ -33,6 +33,7 @@ struct mpm_ctx {
   int64_t G = 0;        // total grid nodes
   int tile = 0;
   int sort = 1;
+  int scatter_mode = 1;  // binned scatters: 1 atomics, 2 per-cell, 3 sorted per-cell
   hipStream_t stream = nullptr;
   int poisoned = 0;
 
@@ -66,6 +67,7 @@ struct mpm_ctx {
   int *d_perm = nullptr, *d_act_sorted = nullptr;
   Chunk *d_chunks_sorted = nullptr;
   int n_chunks_sorted = 0;
+  float *d_part = nullptr;   // tile boxes [n_tiles][d+1][S^d]
 
   // tape
   struct Tape {
@@ -203,8 +205,20 @@ int read_err(mpm_ctx *c) {
 
 // ---- the three kernels of one forward substep ------------------------------
 
-int fwd_p2g(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
-            const int *act_id, const float *act, float *gm, float *gp) {
+TileInfo tile_info(mpm_ctx *c) {
+  TileInfo t;
+  t.cnt = c->d_tile_cnt;
+  t.start = c->d_tile_start;
+  t.scene = c->d_tile_scene;
+  t.part = c->d_part;
+  t.B = c->tile;
+  return t;
+}
+
+// `tiles`: particles are binned (rollouts); scatters go through tile boxes.
+int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
+            CState s, const int *act_id, const float *act, float *gm,
+            float *gp) {
   P2GArgs a;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
@@ -217,11 +231,18 @@ int fwd_p2g(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   a.gp = gp;
   a.G = c->G;
   a.err = c->d_err;
+  a.tiles = tile_info(c);
   ProfScope ps(c, MPM_K_P2G);
+  if (tiles && c->scatter_mode == 3)
+    return launch_p2g_sorted(c->dim, a, c->n_tiles, c->stream);
+  if (tiles && c->scatter_mode == 2)
+    return launch_p2g_cell(c->dim, a, c->d_cell_cnt, c->n_tiles, c->stream);
+  if (tiles) return launch_p2g_tile(c->dim, a, c->n_tiles, c->stream);
   return launch_p2g(c->dim, a, c->stream);
 }
 
-int fwd_grid(mpm_ctx *c, float *gm, float *gp, float *gv, int zero_mp) {
+int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
+             int zero_mp) {
   GridArgs a;
   a.scenes = c->d_scenes;
   a.blocks = c->d_gblocks;
@@ -231,6 +252,9 @@ int fwd_grid(mpm_ctx *c, float *gm, float *gp, float *gv, int zero_mp) {
   a.gv = gv;
   a.G = c->G;
   a.zero_mp = zero_mp;
+  a.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
+  a.part = tiles ? c->d_part : nullptr;
+  a.B = c->tile;
   ProfScope ps(c, MPM_K_GRID);
   return launch_grid(c->dim, a, c->stream);
 }
@@ -254,7 +278,8 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
 // ---- the three kernels of one reverse substep ------------------------------
 // gm/gp: forward grid of step n (m, p).  C1: C of state n+1.
 
-int bwd_step(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
+int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
+             CState s,
              const float *C1, const int *act_id, const float *act,
              const float *gm, const float *gp, CState g1, State g0,
              double *gact) {
@@ -267,9 +292,16 @@ int bwd_step(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   r1.ld = (int)c->N;
   r1.vbar = c->vbar;
   r1.G = c->G;
+  r1.err = c->d_err;
+  r1.tiles = tile_info(c);
   {
     ProfScope ps(c, MPM_K_ADJ_SCATTER);
-    RC(launch_adj_scatter(c->dim, r1, c->stream));
+    if (tiles && c->scatter_mode == 3)
+      RC(launch_adj_scatter_sorted(c->dim, r1, c->n_tiles, c->stream));
+    else if (tiles && c->scatter_mode == 2)
+      RC(launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream));
+    else if (tiles) RC(launch_adj_scatter_tile(c->dim, r1, c->n_tiles, c->stream));
+    else RC(launch_adj_scatter(c->dim, r1, c->stream));
   }
 
   AdjGridArgs r2;
@@ -283,6 +315,9 @@ int bwd_step(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   r2.mbar = c->mbar;
   r2.gv = c->gv;
   r2.G = c->G;
+  r2.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
+  r2.part = tiles ? c->d_part : nullptr;
+  r2.B = c->tile;
   {
     ProfScope ps(c, MPM_K_ADJ_GRID);
     RC(launch_adj_grid(c->dim, r2, c->stream));
@@ -448,17 +483,18 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   int nch = 0;
   const Chunk *chunks = cur_chunks(c, &nch);
   const int *ids = cur_act_id(c);
+  const bool tiles = c->tape.sorted;
   for (int n = 0; n < L.T; ++n) {
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
     const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
     if (L.memo) {
       float *g = slot_grid(c, n);
-      RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, g, g + c->G));
-      RC(fwd_grid(c, g, g + c->G, c->gv, 0));
+      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G));
+      RC(fwd_grid(c, tiles, g, g + c->G, c->gv, 0));
     } else {
-      RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, c->gm, c->gp));
-      RC(fwd_grid(c, c->gm, c->gp, c->gv, 1));
+      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+      RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
     RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
   }
@@ -472,6 +508,7 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   int nch = 0;
   const Chunk *chunks = cur_chunks(c, &nch);
   const int *ids = cur_act_id(c);
+  const bool tiles = t.sorted;
   const int64_t sf = c->state_floats();
   State A1 = state_at(c, t.adj), A0 = state_at(c, t.adj + sf);
   if (t.sorted) RC(permute_state(c, *gT, A1, 0));
@@ -503,11 +540,11 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
         const State s = state_at(c, S(n));
         const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
         float *g = Gr(n);
-        RC(fwd_p2g(c, chunks, nch, cs(s), ids, act, g, g + c->G));
-        if (n + 1 < n1) {
-          RC(fwd_grid(c, g, g + c->G, c->gv, 0));
+        RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G));
+        // sums the tile boxes into the slot (and gives v for the next G2P)
+        RC(fwd_grid(c, tiles, g, g + c->G, c->gv, 0));
+        if (n + 1 < n1)
           RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(n + 1)), c->gv));
-        }
       }
     }
     for (int n = n1 - 1; n >= n0; --n) {
@@ -515,7 +552,7 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
       const State s1 = state_at(c, S(n + 1));
       const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
       const float *g = Gr(n);
-      RC(bwd_step(c, chunks, nch, cs(s), s1.C, ids, act, g, g + c->G, cs(A1),
+      RC(bwd_step(c, tiles, chunks, nch, cs(s), s1.C, ids, act, g, g + c->G, cs(A1),
                   A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
       std::swap(A0, A1);
     }
@@ -574,6 +611,7 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_perm);
   dfree(c->d_act_sorted);
   dfree(c->d_chunks_sorted);
+  dfree(c->d_part);
   dfree(c->tape.states);
   dfree(c->tape.grids);
   dfree(c->tape.act);
@@ -592,10 +630,13 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   if (dim != 2 && dim != 3) return MPM_ERR_ARG;
   int tile = dim == 2 ? 8 : 4;
   int sort = 1;
+  int scatter = 0;
   if (opts) {
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 5; ++k)
       if (opts->reserved[k]) return MPM_ERR_ARG;
-    if (opts->tile < 0 || opts->tile > 16) return MPM_ERR_ARG;
+    if (opts->scatter < 0 || opts->scatter > 3) return MPM_ERR_ARG;
+    scatter = opts->scatter;
+    if (opts->tile && !tile_supported(dim, opts->tile)) return MPM_ERR_ARG;
     if (opts->tile) tile = opts->tile;
     if (opts->sort != 0 && opts->sort != 1) return MPM_ERR_ARG;
     sort = opts->sort;
@@ -631,6 +672,14 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   c->n_act = n_act;
   c->tile = tile;
   c->sort = sort;
+  {
+    const int cells = dim == 2 ? tile * tile : tile * tile * tile;
+    if ((scatter == 2 || scatter == 3) && cells != 64) {
+      delete c;
+      return MPM_ERR_ARG;
+    }
+    c->scatter_mode = scatter == 0 ? (cells == 64 ? 3 : 1) : scatter;
+  }
   c->stream = (hipStream_t)stream;
   c->n_tiles = (int)n_tiles;
 
@@ -651,6 +700,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
     d.act_off = aoff;
     d.wall = S.wall;
     d.tile_off = (int)toff;
+    d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
     d.dt = S.dt;
     d.dx = 1.0f / (float)S.n_grid;
     d.inv_dx = (float)S.n_grid;
@@ -732,6 +782,10 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   TRY(dmalloc(&c->d_perm, N));
   TRY(dmalloc(&c->d_act_sorted, N));
   TRY(dmalloc(&c->d_chunks_sorted, N / CH + n_tiles + 1));
+  {
+    const int64_t S = tile + 4;
+    TRY(dmalloc(&c->d_part, n_tiles * (dim + 1) * (dim == 2 ? S * S : S * S * S)));
+  }
   if (n_act > 0) TRY(ensure_gact(c, n_act));
 
   hipStream_t s = c->stream;
@@ -788,9 +842,9 @@ int mpm_step_forward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
     return MPM_ERR_ARG;
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
-  RC(fwd_p2g(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), c->d_act_id,
-             act_n, c->gm, c->gp));
-  RC(fwd_grid(c, c->gm, c->gp, c->gv, 0));
+  RC(fwd_p2g(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n),
+             c->d_act_id, act_n, c->gm, c->gp));
+  RC(fwd_grid(c, false, c->gm, c->gp, c->gv, 0));
   RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), st(*s_np1),
              c->gv));
   return MPM_OK;
@@ -816,9 +870,9 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
   // forward grid of step n and C of state n+1
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
-  RC(fwd_p2g(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), c->d_act_id,
-             act_n, c->gm, c->gp));
-  RC(fwd_grid(c, c->gm, c->gp, c->gv, 0));
+  RC(fwd_p2g(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n),
+             c->d_act_id, act_n, c->gm, c->gp));
+  RC(fwd_grid(c, false, c->gm, c->gp, c->gv, 0));
   const State s1 = state_at(c, c->scratch);
   RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1, c->gv));
   double *gact = nullptr;
@@ -827,7 +881,7 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
     RC(launch_fill_f64(c->gact, c->n_act, c->stream));
     gact = c->gact;
   }
-  RC(bwd_step(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1.C,
+  RC(bwd_step(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1.C,
               c->d_act_id, act_n, c->gm, c->gp, cs(*g_np1), st(*g_n), gact));
   if (gact) RC(launch_gact_store(gact, g_act_n, c->n_act, 1, c->stream));
   return MPM_OK;
@@ -867,6 +921,9 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   if (memo && T > 0)
     RC(launch_fill_f32(slot_grid(c, 0), (int64_t)T * (1 + c->dim) * c->G,
                        c->stream));
+  // the step calls leave their grid in gm/gp; rollouts start from zero
+  RC(launch_fill_f32(c->gm, c->G, c->stream));
+  RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   RC(rollout_forward(c, L));
   const State ST = state_at(c, fwd_slot(c, L, T));
   if (t.sorted) RC(permute_state(c, ms(ST), st(*sT), 1));

@@ -29,6 +29,8 @@ struct DevScene {
   int act_off;  // first actuator (in the concatenated actuation vector)
   int wall;     // sticky-wall thickness in nodes
   int tile_off; // first tile of the scene (binning)
+  int nt;       // tiles per axis (binning)
+  int pad_[3];
   float dt, dx, inv_dx, Dinv;  // Dinv = 4 / dx^2
   float mu, la, mp, V0;        // Lame parameters, particle mass and volume
   float kG;                    // -Dinv * dt * V0 (stress part of G_p)
@@ -59,6 +61,25 @@ struct CState {
 // kernel launchers (mpm_kernels.hip)
 // ---------------------------------------------------------------------------
 
+// Tiles of binned particles.  A tile owns the particles whose stencil base
+// lies in a B^d block of cells; its workgroup accumulates their scatter into
+// an LDS box of S^d nodes (S = B + 4: the block, the 2-node stencil reach and
+// one cell of drift on every side) and stores the whole box, so the grid
+// kernels can sum the (at most 2 per axis) boxes covering each node without
+// global atomics.  Particles that drifted further add to the grid directly.
+template <int B>
+struct TileBox {
+  static constexpr int S = B + 4;
+};
+
+struct TileInfo {
+  const int *cnt;    // particles per tile [n_tiles]
+  const int *start;  // first (sorted) particle of each tile
+  const int *scene;  // scene of each tile
+  float *part;       // partial boxes [n_tiles][d+1][S^d]
+  int B;             // cells per tile edge
+};
+
 struct P2GArgs {
   const DevScene *scenes;
   const Chunk *chunks;
@@ -70,6 +91,7 @@ struct P2GArgs {
   float *gm, *gp;     // grid mass [G], momentum [d][G]
   int64_t G;
   unsigned *err;
+  TileInfo tiles;     // tile path only
 };
 
 struct GridArgs {
@@ -78,7 +100,11 @@ struct GridArgs {
   int n_blocks;
   float *gm, *gp, *gv;
   int64_t G;
-  int zero_mp;  // clear m and p after reading them (next P2G starts at 0)
+  int zero_mp;  // clear m and p after reading them (next P2G starts at 0);
+                // otherwise store the summed m and p back
+  const int *tile_cnt;  // non-null: add the tile boxes in `part`
+  const float *part;
+  int B;
 };
 
 struct G2PArgs {
@@ -102,6 +128,8 @@ struct AdjScatterArgs {
   int ld;
   float *vbar;  // [d][G] accumulated
   int64_t G;
+  unsigned *err;
+  TileInfo tiles;  // tile path only
 };
 
 struct AdjGridArgs {
@@ -112,6 +140,9 @@ struct AdjGridArgs {
   float *vbar;           // read, then cleared
   float *pbar, *mbar, *gv;  // written: dL/dp, dL/dm, forward v
   int64_t G;
+  const int *tile_cnt;  // non-null: add the tile boxes in `part` to vbar
+  const float *part;
+  int B;
 };
 
 struct AdjGatherArgs {
@@ -145,6 +176,24 @@ struct SortArgs {
 };
 
 int launch_p2g(int dim, const P2GArgs &a, hipStream_t st);
+// One workgroup per tile (n_tiles of them, empty tiles exit at once).
+int launch_p2g_tile(int dim, const P2GArgs &a, int n_tiles, hipStream_t st);
+int launch_adj_scatter_tile(int dim, const AdjScatterArgs &a, int n_tiles,
+                            hipStream_t st);
+// Per-cell variants (tiles of 64 cells: 8x8 in 2D, 4x4x4 in 3D): one wave
+// per tile, lane = cell, register accumulation over the cell's particles.
+// cell_cnt is the binning's per-cell particle count [n_tiles][64].
+int launch_p2g_cell(int dim, const P2GArgs &a, const int *cell_cnt,
+                    int n_tiles, hipStream_t st);
+int launch_adj_scatter_cell(int dim, const AdjScatterArgs &a,
+                            const int *cell_cnt, int n_tiles, hipStream_t st);
+// Sorted per-cell variants (same tiles): each launch re-sorts a tile's
+// particles by their current cell in LDS, so drift does not matter.
+int launch_p2g_sorted(int dim, const P2GArgs &a, int n_tiles, hipStream_t st);
+int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_tiles,
+                              hipStream_t st);
+// Tile edges (cells) with compiled kernels for each dimension.
+bool tile_supported(int dim, int B);
 int launch_grid(int dim, const GridArgs &a, hipStream_t st);
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st);
 int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st);

@@ -321,6 +321,148 @@ __device__ __forceinline__ int chunk_id() { return blockIdx.x; }
 // step 1: P2G scatter
 // ---------------------------------------------------------------------------
 
+// Scatter the 3^d stencil of one particle.  Channel values at offset o are
+//   val_c = N(o) * (c0[c] + sum_b L[c][b] o_b)   (affine in o),
+// plus, when HAS_MASS, channel "mass" N(o) * m0 emitted first.  `sink(o0,
+// o1, o2, vals)` receives NCH = D (+1 with mass) values per node.
+template <int D, bool HAS_MASS, typename Sink>
+__device__ __forceinline__ void scatter_stencil(const float (&w)[D][3],
+                                                float m0, const float *c0,
+                                                const float (&L)[D][D],
+                                                Sink &&sink) {
+  constexpr int M = HAS_MASS ? 1 : 0;
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+      for (int o1 = 0; o1 < 3; ++o1) {
+        const float N = w[0][o0] * w[1][o1];
+        float val[D + M];
+        if constexpr (HAS_MASS) val[0] = N * m0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          val[M + a] = N * (c0[a] + L[a][0] * o0 + L[a][1] * o1);
+        sink(o0, o1, 0, val);
+      }
+  } else {
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+      for (int o1 = 0; o1 < 3; ++o1) {
+        const float w01 = w[0][o0] * w[1][o1];
+#pragma unroll
+        for (int o2 = 0; o2 < 3; ++o2) {
+          const float N = w01 * w[2][o2];
+          float val[D + M];
+          if constexpr (HAS_MASS) val[0] = N * m0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            val[M + a] =
+                N * (c0[a] + L[a][0] * o0 + L[a][1] * o1 + L[a][2] * o2);
+          sink(o0, o1, o2, val);
+        }
+      }
+  }
+}
+
+// Per-particle P2G quantities (section III, P2G): B-spline weights and the
+// affine form of m_p v_p + G_p (x_i - x_p) = c0 + sum_b Gdx[.][b] o_b.
+// Returns false (with eb set) for an invalid particle.
+template <int D>
+__device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
+                                             const DevScene &sc, int p,
+                                             const float *xp, const float *f,
+                                             float (&w)[D][3], float *c0,
+                                             float (&Gdx)[D][D],
+                                             unsigned &eb) {
+  float F[D * D], C[D * D], v[D], G[D * D];
+  load_mat<D>(A.s.F, A.ld, p, F);
+  load_mat<D>(A.s.C, A.ld, p, C);
+  load_vec<D>(A.s.v, A.ld, p, v);
+  const int j = A.act_id[p];
+  const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
+  Stress<D> S;
+  if (!stress<D>(sc, F, s_act, j >= 0, S, eb)) return false;
+  affine_G<D>(sc, S.Pt, F, C, G);
+#pragma unroll
+  for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float s = sc.mp * v[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      Gdx[a][b] = G[a * D + b] * sc.dx;
+      s -= Gdx[a][b] * f[b];
+    }
+    c0[a] = s;
+  }
+  return true;
+}
+
+// Per-particle adjoint-scatter quantities (supplement (A)-(C)):
+// vt + (4/dx^2) Ct (x_i - x_p) = c0 + sum_b Cdx[.][b] o_b.
+template <int D>
+__device__ __forceinline__ void adj_scatter_particle(const AdjScatterArgs &A,
+                                                     const DevScene &sc,
+                                                     int p, const float *f,
+                                                     float (&w)[D][3],
+                                                     float *c0,
+                                                     float (&Cdx)[D][D]) {
+  float F[D * D], gx[D], gv[D], gC[D * D], gF[D * D];
+  load_mat<D>(A.s.F, A.ld, p, F);
+  load_vec<D>(A.g1.x, A.ld, p, gx);
+  load_vec<D>(A.g1.v, A.ld, p, gv);
+  load_mat<D>(A.g1.C, A.ld, p, gC);
+  load_mat<D>(A.g1.F, A.ld, p, gF);
+  float vt[D], Ct[D * D];
+  // (A): dL/dv^{n+1} total = carried + dt dL/dx^{n+1}
+#pragma unroll
+  for (int a = 0; a < D; ++a) vt[a] = gv[a] + sc.dt * gx[a];
+  // (B): dL/dC^{n+1} total = carried + dt dL/dF^{n+1} F^{nT}
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += gF[a * D + g] * F[b * D + g];
+      Ct[a * D + b] = gC[a * D + b] + sc.dt * s;
+    }
+#pragma unroll
+  for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
+  // (C): vt + (4/dx^2) Ct (x_i - x_p), x_i - x_p = (o - f) dx
+  const float cs = sc.Dinv * sc.dx;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float s = vt[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      Cdx[a][b] = cs * Ct[a * D + b];
+      s -= Cdx[a][b] * f[b];
+    }
+    c0[a] = s;
+  }
+}
+
+// Global-memory sink: one atomic per channel and node.
+template <int D, int M>
+__device__ __forceinline__ void add_global(float *m, float *p, int64_t G,
+                                           int64_t gi, const float *val) {
+  if constexpr (M == 1) gmem_add(&m[gi], val[0]);
+#pragma unroll
+  for (int a = 0; a < D; ++a) gmem_add(&p[a * G + gi], val[M + a]);
+}
+
+template <int D>
+__device__ __forceinline__ int64_t stencil_gindex(int64_t gbase, int n, int o0,
+                                                  int o1, int o2) {
+  if constexpr (D == 2) return gbase + o0 * n + o1;
+  else return gbase + ((int64_t)o0 * n + o1) * n + o2;
+}
+
+// Chunk version (caller-ordered particles): LDS box when the chunk's stencil
+// box fits, global atomics otherwise; the LDS box is flushed with one global
+// atomic per non-empty node.
 template <int D>
 __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
   __shared__ float s_grid[(D + 1) * LDS_NODES];
@@ -338,96 +480,29 @@ __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
   const Box<D> box = chunk_box<D>(ok, base);
-
-  float G[D * D], mv[D];
-  if (ok) {
-    float F[D * D], C[D * D], v[D];
-    load_mat<D>(A.s.F, A.ld, p, F);
-    load_mat<D>(A.s.C, A.ld, p, C);
-    load_vec<D>(A.s.v, A.ld, p, v);
-    const int j = A.act_id[p];
-    const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
-    Stress<D> S;
-    ok = stress<D>(sc, F, s_act, j >= 0, S, eb);
-    if (ok) {
-      affine_G<D>(sc, S.Pt, F, C, G);
-#pragma unroll
-      for (int a = 0; a < D; ++a) mv[a] = sc.mp * v[a];
-    }
-  }
+  float w[D][3], c0[D], Gdx[D][D];
+  if (ok) ok = p2g_particle<D>(A, sc, p, xp, f, w, c0, Gdx, eb);
   if (box.lds) {
     for (int i = t; i < (D + 1) * LDS_NODES; i += CH) s_grid[i] = 0.0f;
     __syncthreads();
   }
   if (ok) {
-    float w[D][3];
+    if (box.lds) {
+      const int lbase = box_index<D>(box, base);
+      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+                               [&](int o0, int o1, int o2, const float *val) {
+        const int li = D == 2 ? lbase + o0 * box.e[1] + o1
+                              : lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
 #pragma unroll
-    for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
-    // m_p v_p + G (x_i - x_p) is affine in the offset o: c0 + sum_b o_b Gb_b
-    float c0[D], Gdx[D][D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float s = mv[a];
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        Gdx[a][b] = G[a * D + b] * sc.dx;
-        s -= Gdx[a][b] * f[b];
-      }
-      c0[a] = s;
-    }
-    const int lbase = box.lds ? box_index<D>(box, base) : 0;
-    const int gbase = sc.g_off + node_index<D>(base, sc.n);
-    if constexpr (D == 2) {
-#pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float N = w[0][o0] * w[1][o1];
-          float val[2];
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-            val[a] = N * (c0[a] + Gdx[a][0] * o0 + Gdx[a][1] * o1);
-          if (box.lds) {
-            const int li = lbase + o0 * box.e[1] + o1;
-            lds_add(&s_grid[li], N * sc.mp);
-            lds_add(&s_grid[LDS_NODES + li], val[0]);
-            lds_add(&s_grid[2 * LDS_NODES + li], val[1]);
-          } else {
-            const int64_t gi = gbase + o0 * sc.n + o1;
-            gmem_add(&A.gm[gi], N * sc.mp);
-            gmem_add(&A.gp[gi], val[0]);
-            gmem_add(&A.gp[A.G + gi], val[1]);
-          }
-        }
+        for (int c = 0; c <= D; ++c) lds_add(&s_grid[c * LDS_NODES + li], val[c]);
+      });
     } else {
-#pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float w01 = w[0][o0] * w[1][o1];
-#pragma unroll
-          for (int o2 = 0; o2 < 3; ++o2) {
-            const float N = w01 * w[2][o2];
-            float val[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-              val[a] = N * (c0[a] + Gdx[a][0] * o0 + Gdx[a][1] * o1 +
-                            Gdx[a][2] * o2);
-            if (box.lds) {
-              const int li = lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
-              lds_add(&s_grid[li], N * sc.mp);
-              lds_add(&s_grid[LDS_NODES + li], val[0]);
-              lds_add(&s_grid[2 * LDS_NODES + li], val[1]);
-              lds_add(&s_grid[3 * LDS_NODES + li], val[2]);
-            } else {
-              const int64_t gi = gbase + (o0 * sc.n + o1) * sc.n + o2;
-              gmem_add(&A.gm[gi], N * sc.mp);
-              gmem_add(&A.gp[gi], val[0]);
-              gmem_add(&A.gp[A.G + gi], val[1]);
-              gmem_add(&A.gp[2 * A.G + gi], val[2]);
-            }
-          }
-        }
+      const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+                               [&](int o0, int o1, int o2, const float *val) {
+        add_global<D, 1>(A.gm, A.gp, A.G,
+                         stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+      });
     }
   }
   if (eb) atomicOr(A.err, eb);
@@ -443,6 +518,520 @@ __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
           gmem_add(&A.gp[a * A.G + gi], s_grid[(a + 1) * LDS_NODES + i]);
       }
     }
+  }
+}
+
+// Node origin (scene-local node coordinates) of tile `lt`'s box.
+template <int D, int B>
+__device__ __forceinline__ void tile_origin(int lt, int nt, int *org) {
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    org[a] = (lt % nt) * B - 1;
+    lt /= nt;
+  }
+}
+
+// Tile version (binned particles): one workgroup per tile, LDS accumulation,
+// whole box stored with plain coalesced stores; particles whose stencil left
+// the box add to the grid with global atomics.
+template <int D, int B>
+__global__ __launch_bounds__(256) void k_p2g_tile(P2GArgs A) {
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  __shared__ float s_grid[(D + 1) * SV];
+  const int tile = blockIdx.x;
+  const int cnt = A.tiles.cnt[tile];
+  if (cnt == 0) return;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  const int t = threadIdx.x;
+  for (int i = t; i < (D + 1) * SV; i += 256) s_grid[i] = 0.0f;
+  __syncthreads();
+  unsigned eb = 0;
+  const int start = A.tiles.start[tile];
+  for (int j = t; j < cnt; j += 256) {
+    const int p = start + j;
+    float xp[D], f[D];
+    int base[D];
+    load_vec<D>(A.s.x, A.ld, p, xp);
+    if (!stencil_base<D>(xp, sc, base, f, eb)) continue;
+    float w[D][3], c0[D], Gdx[D][D];
+    if (!p2g_particle<D>(A, sc, p, xp, f, w, c0, Gdx, eb)) continue;
+    int l[D];
+    bool inbox = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      l[a] = base[a] - org[a];
+      inbox = inbox && l[a] >= 0 && l[a] <= S - 3;
+    }
+    if (inbox) {
+      const int lbase = D == 2 ? l[0] * S + l[1] : (l[0] * S + l[1]) * S + l[2];
+      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+                               [&](int o0, int o1, int o2, const float *val) {
+        const int li = D == 2 ? lbase + o0 * S + o1 : lbase + (o0 * S + o1) * S + o2;
+#pragma unroll
+        for (int c = 0; c <= D; ++c) lds_add(&s_grid[c * SV + li], val[c]);
+      });
+    } else {
+      const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+                               [&](int o0, int o1, int o2, const float *val) {
+        add_global<D, 1>(A.gm, A.gp, A.G,
+                         stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+      });
+    }
+  }
+  if (eb) atomicOr(A.err, eb);
+  __syncthreads();
+  float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
+  for (int i = t; i < (D + 1) * SV; i += 256) dst[i] = s_grid[i];
+}
+
+// ---------------------------------------------------------------------------
+// per-cell scatter: one wave per tile of 64 cells, lane = cell
+// ---------------------------------------------------------------------------
+//
+// Binned order is tile, then rank within the cell, then cell, so the r-th
+// particles of the 64 cells are contiguous: in round r lane c reads particle
+// start + sum_c' min(n_c', r) + #{c' < c : n_c' > r} (a ballot prefix count).
+// A lane accumulates the 3^d x NCH contributions of its cell's particles in
+// registers (all of them share the cell's stencil base), then adds them into
+// its wave's LDS box with plain read-add-write, one stencil offset at a time:
+// for a fixed offset the 64 lanes touch 64 distinct nodes, and the LDS
+// executes one wave's operations in issue order (the empty asm statements
+// keep the compiler from reordering those LDS accesses across offsets).
+// Particles that drifted out of their cell add to the box with LDS atomics
+// (or to the grid with global atomics when they left the box).
+
+__device__ __forceinline__ int lanes_before(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+#define MPM_LDS_ORDER() asm volatile("" ::: "memory")
+
+// Shared driver.  PART(p, xp, base, f, w, c0, L, eb) -> bool computes one
+// particle's affine stencil values; NCH channels, HAS_MASS as in
+// scatter_stencil.
+template <int D, int NCH, bool HAS_MASS, typename Args, typename Part>
+__device__ __forceinline__ void cell_scatter_wave(const Args &A,
+                                                  const int *cell_cnt,
+                                                  int tile, float *box,
+                                                  float *gm, float *gp,
+                                                  Part &&part) {
+  constexpr int B = D == 2 ? 8 : 4;
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  constexpr int NO = D == 2 ? 9 : 27;
+  const int lane = threadIdx.x & 63;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  for (int i = lane; i < NCH * SV; i += 64) box[i] = 0.0f;
+  MPM_LDS_ORDER();
+  int cc[D];
+  {
+    int l = lane;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      cc[a] = l % B;
+      l /= B;
+    }
+  }
+  const int n_l = cell_cnt[tile * 64 + lane];
+  const int maxr = wave_max(n_l);
+  const int start = A.tiles.start[tile];
+  // local box index of this cell's stencil base (cell + 1 cell of slack)
+  const int lcell = D == 2 ? (cc[0] + 1) * S + (cc[1] + 1)
+                           : ((cc[0] + 1) * S + (cc[1] + 1)) * S + (cc[2] + 1);
+  float acc[NO * NCH];
+#pragma unroll
+  for (int k = 0; k < NO * NCH; ++k) acc[k] = 0.0f;
+  unsigned eb = 0;
+  int R = 0;
+  for (int r = 0; r < maxr; ++r) {
+    const bool act = n_l > r;
+    const uint64_t mask = __ballot(act);
+    if (act) {
+      const int p = start + R + lanes_before(mask);
+      float xp[D], f[D];
+      int base[D];
+      load_vec<D>(A.s.x, A.ld, p, xp);
+      float w[D][3], c0[D], L[D][D];
+      if (stencil_base<D>(xp, sc, base, f, eb) &&
+          part(p, xp, base, f, w, c0, L, eb)) {
+        bool home = true, inbox = true;
+        int l[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          l[a] = base[a] - org[a];
+          home = home && l[a] == cc[a] + 1;
+          inbox = inbox && l[a] >= 0 && l[a] <= S - 3;
+        }
+        if (home) {
+          int o = 0;
+          scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                       [&](int, int, int, const float *val) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) acc[o * NCH + c] += val[c];
+            ++o;
+          });
+        } else if (inbox) {
+          const int lb = D == 2 ? l[0] * S + l[1] : (l[0] * S + l[1]) * S + l[2];
+          scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                       [&](int o0, int o1, int o2, const float *val) {
+            const int li = D == 2 ? lb + o0 * S + o1 : lb + (o0 * S + o1) * S + o2;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) lds_add(&box[c * SV + li], val[c]);
+          });
+        } else {
+          const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+          scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                       [&](int o0, int o1, int o2, const float *val) {
+            add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
+                                            stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+          });
+        }
+      }
+    }
+    R += __popcll(mask);
+  }
+  if (eb) atomicOr(A.err, eb);
+  MPM_LDS_ORDER();
+  // read-add-write, one stencil offset at a time
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int o0 = D == 2 ? o / 3 : o / 9;
+    const int o1 = D == 2 ? o % 3 : (o / 3) % 3;
+    const int o2 = D == 2 ? 0 : o % 3;
+    const int li = D == 2 ? lcell + o0 * S + o1 : lcell + (o0 * S + o1) * S + o2;
+    float cur[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) cur[c] = box[c * SV + li];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) box[c * SV + li] = cur[c] + acc[o * NCH + c];
+    MPM_LDS_ORDER();
+  }
+  float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
+  for (int i = lane; i < NCH * SV; i += 64) dst[i] = box[i];
+}
+
+// Sorted per-cell scatter (drift-proof).  One workgroup (4 waves) per tile.
+// The tile's particles are processed in batches of 256 (one per thread):
+//  1. each thread computes its particle's affine stencil record (f, c0, L)
+//     and its current cell in the tile box's (B+2)^d cell grid (one cell of
+//     drift per side), and takes a rank in that cell (integer LDS atomic);
+//  2. an exclusive scan over the cells gives each cell a range; each thread
+//     stores its record at its cell's range + rank;
+//  3. thread c (< (B+2)^d) walks cell c's records and accumulates the
+//     3^d x NCH contributions in registers (one stencil base per cell).
+// After the last batch each wave adds its lanes' accumulators into its own
+// LDS box (plain read-add-write: for a fixed offset a wave's lanes touch
+// distinct nodes), the four boxes are summed and the tile box is stored.
+// Particles outside the slack ring add to the grid with global atomics.
+template <int D>
+struct SortedCell {
+  static constexpr int B = D == 2 ? 8 : 4;
+  static constexpr int S = TileBox<B>::S;
+  static constexpr int SV = D == 2 ? S * S : S * S * S;
+  static constexpr int BC = B + 2;  // box cells per axis
+  static constexpr int NBC = D == 2 ? BC * BC : BC * BC * BC;
+  static constexpr int REC = D + D + D * D;  // f, c0, L
+};
+
+template <int D, int NCH>
+struct SortedCellSmem {
+  float box[4][NCH * SortedCell<D>::SV];
+  float rec[256 * SortedCell<D>::REC];
+  int cnt[256];
+  int off[256];
+  int wsum[4];
+};
+
+// Exclusive scan of cnt[0..256) into off (256 threads).
+__device__ __forceinline__ void block_scan_256(const int *cnt, int *off,
+                                               int *wsum) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int v = cnt[t];
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int pre = 0;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  off[t] = pre + x - v;
+}
+
+template <int D, int NCH, bool HAS_MASS, typename Args, typename Part>
+__device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
+                                                    SortedCellSmem<D, NCH> &sm,
+                                                    float *gm, float *gp,
+                                                    Part &&part) {
+  using SC = SortedCell<D>;
+  constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
+                REC = SC::REC, B = SC::B;
+  constexpr int NO = D == 2 ? 9 : 27;
+  const int t = threadIdx.x, wave = t >> 6;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  const int cnt = A.tiles.cnt[tile];
+  const int start = A.tiles.start[tile];
+  float *mybox = sm.box[wave];
+  for (int i = t & 63; i < NCH * SV; i += 64) mybox[i] = 0.0f;
+  sm.cnt[t] = 0;
+  // this thread's cell in phase 3 (t < NBC): box-cell coordinates
+  int cc[D];
+  {
+    int l = t;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      cc[a] = l % BC;
+      l /= BC;
+    }
+  }
+  float acc[NO * NCH];
+#pragma unroll
+  for (int k = 0; k < NO * NCH; ++k) acc[k] = 0.0f;
+  unsigned eb = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < cnt; b0 += 256) {
+    // 1. record + cell + rank
+    const int j = b0 + t;
+    int lc = -1, rank = 0;
+    float rec[REC];
+    if (j < cnt) {
+      const int p = start + j;
+      float xp[D], f[D], w[D][3], c0[D], L[D][D];
+      int base[D];
+      load_vec<D>(A.s.x, A.ld, p, xp);
+      if (stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb)) {
+        int l[D];
+        bool inbox = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          l[a] = base[a] - org[a];
+          inbox = inbox && l[a] >= 0 && l[a] < BC;
+        }
+        if (inbox) {
+          lc = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            rec[a] = f[a];
+            rec[D + a] = c0[a];
+#pragma unroll
+            for (int b = 0; b < D; ++b) rec[2 * D + a * D + b] = L[a][b];
+          }
+          rank = atomicAdd(&sm.cnt[lc], 1);
+        } else {
+          const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+          scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                       [&](int o0, int o1, int o2, const float *val) {
+            add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
+                                            stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+          });
+        }
+      }
+    }
+    __syncthreads();
+    // 2. cell ranges, records to their sorted slots
+    block_scan_256(sm.cnt, sm.off, sm.wsum);
+    __syncthreads();
+    if (lc >= 0) {
+      float *dst = sm.rec + (sm.off[lc] + rank) * REC;
+#pragma unroll
+      for (int k = 0; k < REC; ++k) dst[k] = rec[k];
+    }
+    __syncthreads();
+    // 3. per-cell accumulation in registers
+    if (t < NBC) {
+      const int n = sm.cnt[t], o = sm.off[t];
+      for (int k = 0; k < n; ++k) {
+        const float *r = sm.rec + (o + k) * REC;
+        float w[D][3], c0[D], L[D][D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          bspline_w(r[a], w[a]);
+          c0[a] = r[D + a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) L[a][b] = r[2 * D + a * D + b];
+        }
+        int oi = 0;
+        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                     [&](int, int, int, const float *val) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) acc[oi * NCH + c] += val[c];
+          ++oi;
+        });
+      }
+    }
+    __syncthreads();
+    sm.cnt[t] = 0;
+    __syncthreads();
+  }
+  if (eb) atomicOr(A.err, eb);
+  // 4. per-wave read-add-write of the accumulators into the wave's box
+  if (t < NBC) {
+    const int lcell = D == 2 ? cc[0] * S + cc[1] : (cc[0] * S + cc[1]) * S + cc[2];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const int o0 = D == 2 ? o / 3 : o / 9;
+      const int o1 = D == 2 ? o % 3 : (o / 3) % 3;
+      const int o2 = D == 2 ? 0 : o % 3;
+      const int li = D == 2 ? lcell + o0 * S + o1 : lcell + (o0 * S + o1) * S + o2;
+      float cur[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) cur[c] = mybox[c * SV + li];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) mybox[c * SV + li] = cur[c] + acc[o * NCH + c];
+      MPM_LDS_ORDER();
+    }
+  }
+  __syncthreads();
+  // 5. sum the four wave boxes, store the tile box
+  float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
+  for (int i = t; i < NCH * SV; i += 256)
+    dst[i] = (sm.box[0][i] + sm.box[1][i]) + (sm.box[2][i] + sm.box[3][i]);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
+  __shared__ SortedCellSmem<D, D + 1> sm;
+  const int tile = blockIdx.x;
+  if (A.tiles.cnt[tile] == 0) return;
+  sorted_cell_scatter<D, D + 1, true>(
+      A, tile, sm, A.gm, A.gp,
+      [&](int p, const float *xp, const float *f, float (&w)[D][3], float *c0,
+          float (&L)[D][D], unsigned &eb) {
+        const DevScene sc = A.scenes[A.tiles.scene[tile]];
+        return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+      });
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
+  __shared__ SortedCellSmem<D, D> sm;
+  const int tile = blockIdx.x;
+  if (A.tiles.cnt[tile] == 0) return;
+  sorted_cell_scatter<D, D, false>(
+      A, tile, sm, nullptr, A.vbar,
+      [&](int p, const float *, const float *f, float (&w)[D][3], float *c0,
+          float (&L)[D][D], unsigned &) {
+        const DevScene sc = A.scenes[A.tiles.scene[tile]];
+        adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+        return true;
+      });
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_p2g_cell(P2GArgs A, const int *cell_cnt,
+                                                  int n_tiles) {
+  constexpr int B = D == 2 ? 8 : 4;
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  __shared__ float s_box[4][(D + 1) * SV];
+  const int wave = threadIdx.x >> 6;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= n_tiles || A.tiles.cnt[tile] == 0) return;  // per wave
+  cell_scatter_wave<D, D + 1, true>(
+      A, cell_cnt, tile, s_box[wave], A.gm, A.gp,
+      [&](int p, const float *xp, const int *, const float *f, float (&w)[D][3],
+          float *c0, float (&L)[D][D], unsigned &eb) {
+        const DevScene sc = A.scenes[A.tiles.scene[tile]];
+        return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+      });
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_adj_scatter_cell(AdjScatterArgs A,
+                                                          const int *cell_cnt,
+                                                          int n_tiles) {
+  constexpr int B = D == 2 ? 8 : 4;
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  __shared__ float s_box[4][D * SV];
+  const int wave = threadIdx.x >> 6;
+  const int tile = blockIdx.x * 4 + wave;
+  if (tile >= n_tiles || A.tiles.cnt[tile] == 0) return;  // per wave
+  cell_scatter_wave<D, D, false>(
+      A, cell_cnt, tile, s_box[wave], nullptr, A.vbar,
+      [&](int p, const float *, const int *, const float *f, float (&w)[D][3],
+          float *c0, float (&L)[D][D], unsigned &) {
+        const DevScene sc = A.scenes[A.tiles.scene[tile]];
+        adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+        return true;
+      });
+}
+
+// Sum over the tile boxes covering scene-local node `li` (coordinates g) of
+// channels [c_lo, c_lo + NC) into acc.
+template <int D, int B, int NC>
+__device__ __forceinline__ void add_tile_boxes(const DevScene &sc, int li,
+                                               const int *tile_cnt,
+                                               const float *part, int nch,
+                                               int c_lo, float *acc) {
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  int g[D], tlo[D], thi[D];
+  int r = li;
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    g[a] = r % sc.n;
+    r /= sc.n;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    // tile t's box spans nodes [t B - 1, t B + B + 2]
+    thi[a] = min((g[a] + 1) / B, sc.nt - 1);
+    tlo[a] = g[a] >= 3 ? (g[a] - 3) / B : 0;
+  }
+  if constexpr (D == 2) {
+    for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+      for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
+        const int tile = sc.tile_off + t0 * sc.nt + t1;
+        if (tile_cnt[tile] == 0) continue;
+        const int l = (g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1));
+        const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += bx[c * SV];
+      }
+  } else {
+    for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+      for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+        for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+          const int tile = sc.tile_off + (t0 * sc.nt + t1) * sc.nt + t2;
+          if (tile_cnt[tile] == 0) continue;
+          const int l = ((g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1))) * S +
+                        (g[2] - (t2 * B - 1));
+          const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] += bx[c * SV];
+        }
+  }
+}
+
+template <int D, int NC>
+__device__ __forceinline__ void add_tile_boxes_any(int B, const DevScene &sc,
+                                                   int li, const int *tile_cnt,
+                                                   const float *part, int nch,
+                                                   int c_lo, float *acc) {
+  if constexpr (D == 2) {
+    if (B == 8) add_tile_boxes<2, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    else add_tile_boxes<2, 16, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+  } else {
+    if (B == 4) add_tile_boxes<3, 4, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    else add_tile_boxes<3, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
   }
 }
 
@@ -469,21 +1058,33 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
   const DevScene sc = A.scenes[gb.scene];
   const int li = gb.start + threadIdx.x;
   const int64_t gi = sc.g_off + li;
-  const float m = A.gm[gi];
+  float mp[D + 1];  // m, p (direct adds + tile boxes)
+  mp[0] = A.gm[gi];
+#pragma unroll
+  for (int a = 0; a < D; ++a) mp[1 + a] = A.gp[a * A.G + gi];
+  const bool direct = mp[0] != 0.0f;
+  if (A.part) add_tile_boxes_any<D, D + 1>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, mp);
+  const float m = mp[0];
   const bool wall = is_wall<D>(li, sc.n, sc.wall);
   float v[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     float va = 0.0f;
-    if (m > 0.0f) va = A.gp[a * A.G + gi] / m + sc.dt * sc.g[a];
+    if (m > 0.0f) va = mp[1 + a] / m + sc.dt * sc.g[a];
     v[a] = wall ? 0.0f : va;
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) A.gv[a * A.G + gi] = v[a];
-  if (A.zero_mp && m != 0.0f) {
-    A.gm[gi] = 0.0f;
+  if (A.zero_mp) {
+    if (direct) {
+      A.gm[gi] = 0.0f;
 #pragma unroll
-    for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = 0.0f;
+      for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = 0.0f;
+    }
+  } else if (A.part) {
+    A.gm[gi] = m;
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = mp[1 + a];
   }
 }
 
@@ -644,98 +1245,29 @@ __global__ __launch_bounds__(CH) void k_adj_scatter(AdjScatterArgs A) {
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
   const Box<D> box = chunk_box<D>(ok, base);
-  float vt[D], Ct[D * D];
-  if (ok) {
-    float F[D * D], gx[D], gv[D], gC[D * D], gF[D * D];
-    load_mat<D>(A.s.F, A.ld, p, F);
-    load_vec<D>(A.g1.x, A.ld, p, gx);
-    load_vec<D>(A.g1.v, A.ld, p, gv);
-    load_mat<D>(A.g1.C, A.ld, p, gC);
-    load_mat<D>(A.g1.F, A.ld, p, gF);
-    // (A): dL/dv^{n+1} total = carried + dt dL/dx^{n+1}
-#pragma unroll
-    for (int a = 0; a < D; ++a) vt[a] = gv[a] + sc.dt * gx[a];
-    // (B): dL/dC^{n+1} total = carried + dt dL/dF^{n+1} F^{nT}
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = 0.0f;
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += gF[a * D + g] * F[b * D + g];
-        Ct[a * D + b] = gC[a * D + b] + sc.dt * s;
-      }
-  }
+  float w[D][3], c0[D], Cdx[D][D];
+  if (ok) adj_scatter_particle<D>(A, sc, p, f, w, c0, Cdx);
   if (box.lds) {
     for (int i = t; i < D * LDS_NODES; i += CH) s_grid[i] = 0.0f;
     __syncthreads();
   }
   if (ok) {
-    float w[D][3];
+    if (box.lds) {
+      const int lbase = box_index<D>(box, base);
+      scatter_stencil<D, false>(w, 0.0f, c0, Cdx,
+                                [&](int o0, int o1, int o2, const float *val) {
+        const int li = D == 2 ? lbase + o0 * box.e[1] + o1
+                              : lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
 #pragma unroll
-    for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
-    // (C): vt + (4/dx^2) Ct (x_i - x_p) is affine in o
-    float c0[D], Cdx[D][D];
-    const float cs = sc.Dinv * sc.dx;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      float s = vt[a];
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        Cdx[a][b] = cs * Ct[a * D + b];
-        s -= Cdx[a][b] * f[b];
-      }
-      c0[a] = s;
-    }
-    const int lbase = box.lds ? box_index<D>(box, base) : 0;
-    const int gbase = sc.g_off + node_index<D>(base, sc.n);
-    if constexpr (D == 2) {
-#pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float N = w[0][o0] * w[1][o1];
-          float val[2];
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-            val[a] = N * (c0[a] + Cdx[a][0] * o0 + Cdx[a][1] * o1);
-          if (box.lds) {
-            const int li = lbase + o0 * box.e[1] + o1;
-            lds_add(&s_grid[li], val[0]);
-            lds_add(&s_grid[LDS_NODES + li], val[1]);
-          } else {
-            const int64_t gi = gbase + o0 * sc.n + o1;
-            gmem_add(&A.vbar[gi], val[0]);
-            gmem_add(&A.vbar[A.G + gi], val[1]);
-          }
-        }
+        for (int c = 0; c < D; ++c) lds_add(&s_grid[c * LDS_NODES + li], val[c]);
+      });
     } else {
-#pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float w01 = w[0][o0] * w[1][o1];
-#pragma unroll
-          for (int o2 = 0; o2 < 3; ++o2) {
-            const float N = w01 * w[2][o2];
-            float val[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-              val[a] = N * (c0[a] + Cdx[a][0] * o0 + Cdx[a][1] * o1 +
-                            Cdx[a][2] * o2);
-            if (box.lds) {
-              const int li = lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
-              lds_add(&s_grid[li], val[0]);
-              lds_add(&s_grid[LDS_NODES + li], val[1]);
-              lds_add(&s_grid[2 * LDS_NODES + li], val[2]);
-            } else {
-              const int64_t gi = gbase + (o0 * sc.n + o1) * sc.n + o2;
-              gmem_add(&A.vbar[gi], val[0]);
-              gmem_add(&A.vbar[A.G + gi], val[1]);
-              gmem_add(&A.vbar[2 * A.G + gi], val[2]);
-            }
-          }
-        }
+      const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+      scatter_stencil<D, false>(w, 0.0f, c0, Cdx,
+                                [&](int o0, int o1, int o2, const float *val) {
+        add_global<D, 0>(nullptr, A.vbar, A.G,
+                         stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+      });
     }
   }
   if (box.lds) {
@@ -755,6 +1287,62 @@ __global__ __launch_bounds__(CH) void k_adj_scatter(AdjScatterArgs A) {
       }
     }
   }
+}
+
+// Tile version of the adjoint scatter (binned particles); boxes carry d
+// channels in slots 0..d-1 of the (d+1)-channel partial buffer.
+template <int D, int B>
+__global__ __launch_bounds__(256) void k_adj_scatter_tile(AdjScatterArgs A) {
+  constexpr int S = TileBox<B>::S;
+  constexpr int SV = D == 2 ? S * S : S * S * S;
+  __shared__ float s_grid[D * SV];
+  const int tile = blockIdx.x;
+  const int cnt = A.tiles.cnt[tile];
+  if (cnt == 0) return;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  const int t = threadIdx.x;
+  for (int i = t; i < D * SV; i += 256) s_grid[i] = 0.0f;
+  __syncthreads();
+  unsigned eb = 0;
+  const int start = A.tiles.start[tile];
+  for (int j = t; j < cnt; j += 256) {
+    const int p = start + j;
+    float xp[D], f[D];
+    int base[D];
+    load_vec<D>(A.s.x, A.ld, p, xp);
+    if (!stencil_base<D>(xp, sc, base, f, eb)) continue;
+    float w[D][3], c0[D], Cdx[D][D];
+    adj_scatter_particle<D>(A, sc, p, f, w, c0, Cdx);
+    int l[D];
+    bool inbox = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      l[a] = base[a] - org[a];
+      inbox = inbox && l[a] >= 0 && l[a] <= S - 3;
+    }
+    if (inbox) {
+      const int lbase = D == 2 ? l[0] * S + l[1] : (l[0] * S + l[1]) * S + l[2];
+      scatter_stencil<D, false>(w, 0.0f, c0, Cdx,
+                                [&](int o0, int o1, int o2, const float *val) {
+        const int li = D == 2 ? lbase + o0 * S + o1 : lbase + (o0 * S + o1) * S + o2;
+#pragma unroll
+        for (int c = 0; c < D; ++c) lds_add(&s_grid[c * SV + li], val[c]);
+      });
+    } else {
+      const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+      scatter_stencil<D, false>(w, 0.0f, c0, Cdx,
+                                [&](int o0, int o1, int o2, const float *val) {
+        add_global<D, 0>(nullptr, A.vbar, A.G,
+                         stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+      });
+    }
+  }
+  if (eb) atomicOr(A.err, eb);
+  __syncthreads();
+  float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
+  for (int i = t; i < D * SV; i += 256) dst[i] = s_grid[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +1365,7 @@ __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
     vb[a] = A.vbar[a * A.G + gi];
     nz = nz || vb[a] != 0.0f;
   }
+  if (A.part) add_tile_boxes_any<D, D>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, vb);
   float mb = 0.0f;
   if (m > 0.0f) {
     const float im = 1.0f / m;
@@ -810,10 +1399,31 @@ __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
 // gather (supplement F-K)
 // ---------------------------------------------------------------------------
 
+// Node record staged in LDS for the adjoint gather: dL/dp (d), dL/dm, v (d),
+// padded to 8 floats so a node is two 16-byte LDS reads.
+struct __align__(16) AdjNode {
+  float4 a;  // pbar0, pbar1, pbar2 (or 0), mbar      (2D: pbar0, pbar1, 0, mbar)
+  float4 b;  // v0, v1, v2 (or 0), unused
+};
+
+template <int D>
+__device__ __forceinline__ AdjNode adj_node_global(const AdjGatherArgs &A,
+                                                   int64_t gi) {
+  AdjNode r;
+  r.a.x = A.pbar[gi];
+  r.a.y = A.pbar[A.G + gi];
+  r.a.z = D == 3 ? A.pbar[2 * A.G + gi] : 0.0f;
+  r.a.w = A.mbar[gi];
+  r.b.x = A.gv[gi];
+  r.b.y = A.gv[A.G + gi];
+  r.b.z = D == 3 ? A.gv[2 * A.G + gi] : 0.0f;
+  r.b.w = 0.0f;
+  return r;
+}
+
 template <int D>
 __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
-  constexpr int NCH = 2 * D + 1;  // staged channels: pbar[D], mbar, v[D]
-  __shared__ float s_n[NCH * LDS_NODES];
+  __shared__ AdjNode s_n[LDS_NODES];
   __shared__ double s_act[LDS_ACT];
   const Chunk ch = A.chunks[chunk_id()];
   const DevScene sc = A.scenes[ch.scene];
@@ -833,30 +1443,28 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
   if (act_lds)
     for (int i = t; i < sc.n_act; i += CH) s_act[i] = 0.0;
   if (box.lds) {
-    for (int i = t; i < box.vol; i += CH) {
-      const int64_t gi = sc.g_off + box_node<D>(box, i, sc.n);
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        s_n[a * LDS_NODES + i] = A.pbar[a * A.G + gi];
-        s_n[(D + 1 + a) * LDS_NODES + i] = A.gv[a * A.G + gi];
-      }
-      s_n[D * LDS_NODES + i] = A.mbar[gi];
-    }
+    for (int i = t; i < box.vol; i += CH)
+      s_n[i] = adj_node_global<D>(A, sc.g_off + box_node<D>(box, i, sc.n));
   }
   __syncthreads();
 
   float sb_act = 0.0f;
   int j_act = -1;
   if (ok) {
-    float v[D], C[D * D], F[D * D];
-    load_vec<D>(A.s.v, A.ld, p, v);
-    load_mat<D>(A.s.C, A.ld, p, C);
-    load_mat<D>(A.s.F, A.ld, p, F);
     j_act = A.act_id[p];
     const float s_act = j_act >= 0 ? A.act[sc.act_off + j_act] : 0.0f;
-    Stress<D> S;
-    ok = stress<D>(sc, F, s_act, j_act >= 0, S, eb);
-    if (ok) {
+    // --- quantities live across the stencil loop -------------------------
+    float w[D][3], dw[D][3];
+    float cC[D], Cdx[D][D];  // (4/dx^2)-free C-tilde (x_i - x_p) = cC + Cdx o
+    float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
+    float vt[D];
+    {
+      float v[D], C[D * D], F[D * D];
+      load_vec<D>(A.s.v, A.ld, p, v);
+      load_mat<D>(A.s.C, A.ld, p, C);
+      load_mat<D>(A.s.F, A.ld, p, F);
+      Stress<D> S;
+      ok = stress<D>(sc, F, s_act, j_act >= 0, S, eb);
       float G[D * D];
       affine_G<D>(sc, S.Pt, F, C, G);
       float gx1[D], gv1[D], gC1[D * D], gF1[D * D];
@@ -864,32 +1472,17 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
       load_vec<D>(A.g1.v, A.ld, p, gv1);
       load_mat<D>(A.g1.C, A.ld, p, gC1);
       load_mat<D>(A.g1.F, A.ld, p, gF1);
-      float vt[D], Ct[D * D];
 #pragma unroll
       for (int a = 0; a < D; ++a) vt[a] = gv1[a] + sc.dt * gx1[a];  // (A)
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {  // (B)
-          float s = 0.0f;
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += gF1[a * D + g] * F[b * D + g];
-          Ct[a * D + b] = gC1[a * D + b] + sc.dt * s;
-        }
-      float w[D][3], dw[D][3];
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        bspline_w(f[a], w[a]);
-        bspline_dw(f[a], sc.inv_dx, dw[a]);
-      }
-      // affine-in-o pieces:  Ct (x_i - x_p) and m v + G (x_i - x_p)
-      float cC[D], Cdx[D][D], cq[D], Gdx[D][D];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         float s1 = 0.0f, s2 = sc.mp * v[a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-          Cdx[a][b] = Ct[a * D + b] * sc.dx;
+          float ct = 0.0f;  // (B) Ct = gC1 + dt gF1 F^T
+#pragma unroll
+          for (int g = 0; g < D; ++g) ct += gF1[a * D + g] * F[b * D + g];
+          Cdx[a][b] = (gC1[a * D + b] + sc.dt * ct) * sc.dx;
           Gdx[a][b] = G[a * D + b] * sc.dx;
           s1 -= Cdx[a][b] * f[b];
           s2 -= Gdx[a][b] * f[b];
@@ -897,169 +1490,170 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
         cC[a] = s1;
         cq[a] = s2;
       }
-      float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {};
+    }
 #pragma unroll
-      for (int a = 0; a < D; ++a) xb[a] = gx1[a];  // (J) direct term
-      const int lbase = box.lds ? box_index<D>(box, base) : 0;
-      const int gbase = sc.g_off + node_index<D>(base, sc.n);
+    for (int a = 0; a < D; ++a) {
+      bspline_w(f[a], w[a]);
+      bspline_dw(f[a], sc.inv_dx, dw[a]);
+    }
+    float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {};
+    load_vec<D>(A.g1.x, A.ld, p, xb);  // (J) direct term dL/dx^{n+1}
+    const int lbase = box.lds ? box_index<D>(box, base) : 0;
+    const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
 
-      auto node = [&](int li, int64_t gi, float N, const float *gN,
-                      const float *dl) {
-        float pb[D], vi[D], mb;
-        if (box.lds) {
+    auto node = [&](const AdjNode &nd, float N, const float *gN, const float *o) {
+      const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
+      const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
+      float s_all = sc.mp * nd.a.w;  // (J) m-term
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            pb[a] = s_n[a * LDS_NODES + li];
-            vi[a] = s_n[(D + 1 + a) * LDS_NODES + li];
-          }
-          mb = s_n[D * LDS_NODES + li];
-        } else {
+      for (int a = 0; a < D; ++a) {
+        float Cd = cC[a], q = cq[a];
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            pb[a] = A.pbar[a * A.G + gi];
-            vi[a] = A.gv[a * A.G + gi];
-          }
-          mb = A.mbar[gi];
+        for (int b = 0; b < D; ++b) {
+          Cd += Cdx[a][b] * o[b];
+          q += Gdx[a][b] * o[b];
         }
-        float s_all = sc.mp * mb;  // (J) m-term
+        // (J) v-term, C-term (N part), p-term (N part)
+        s_all += vt[a] * vi[a] + sc.Dinv * vi[a] * Cd + pb[a] * q;
+        const float Npb = N * pb[a];
+        Spb[a] += Npb;       // (F), and the delta part of the (J) p-term
+        Sv[a] += N * vi[a];  // delta part of the (J) C-term
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          float Cd = cC[a], q = cq[a];
-#pragma unroll
-          for (int b = 0; b < D; ++b) {
-            Cd += Cdx[a][b] * dl[b];
-            q += Gdx[a][b] * dl[b];
-          }
-          // (J) v-term, C-term (N part), p-term (N part)
-          s_all += vt[a] * vi[a] + sc.Dinv * vi[a] * Cd + pb[a] * q;
-          const float Npb = N * pb[a];
-          Spb[a] += Npb;          // (F), and the delta-part of (J)
-          Sv[a] += N * vi[a];     // delta-part of the (J) C-term
-#pragma unroll
-          for (int b = 0; b < D; ++b)
-            Gb[a * D + b] += Npb * (dl[b] - f[b]);  // dL/dG, in units of dx
-        }
-#pragma unroll
-        for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
-      };
-
-      if constexpr (D == 2) {
-#pragma unroll
-        for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-          for (int o1 = 0; o1 < 3; ++o1) {
-            const float N = w[0][o0] * w[1][o1];
-            const float gN[2] = {dw[0][o0] * w[1][o1], w[0][o0] * dw[1][o1]};
-            const float dl[2] = {(float)o0, (float)o1};
-            node(lbase + o0 * box.e[1] + o1, gbase + o0 * sc.n + o1, N, gN,
-                 dl);
-          }
-      } else {
-#pragma unroll
-        for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-          for (int o1 = 0; o1 < 3; ++o1) {
-            const float w01 = w[0][o0] * w[1][o1];
-            const float d01 = dw[0][o0] * w[1][o1];
-            const float w0d1 = w[0][o0] * dw[1][o1];
-#pragma unroll
-            for (int o2 = 0; o2 < 3; ++o2) {
-              const float N = w01 * w[2][o2];
-              const float gN[3] = {d01 * w[2][o2], w0d1 * w[2][o2],
-                                   w01 * dw[2][o2]};
-              const float dl[3] = {(float)o0, (float)o1, (float)o2};
-              node(lbase + (o0 * box.e[1] + o1) * box.e[2] + o2,
-                   gbase + (o0 * sc.n + o1) * sc.n + o2, N, gN, dl);
-            }
-          }
+        for (int b = 0; b < D; ++b) Gb[a * D + b] += Npb * (o[b] - f[b]);
       }
-      // (J) delta-parts: -sum N [ (4/dx^2) Ct^T v_i + G^T p_i ]
 #pragma unroll
-      for (int c = 0; c < D; ++c) {
+      for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
+    };
+
+    if constexpr (D == 2) {
+#pragma unroll
+      for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1) {
+          const float N = w[0][o0] * w[1][o1];
+          const float gN[2] = {dw[0][o0] * w[1][o1], w[0][o0] * dw[1][o1]};
+          const float o[2] = {(float)o0, (float)o1};
+          const AdjNode nd = box.lds ? s_n[lbase + o0 * box.e[1] + o1]
+                                     : adj_node_global<D>(A, gbase + o0 * sc.n + o1);
+          node(nd, N, gN, o);
+        }
+    } else {
+#pragma unroll 1
+      for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1) {
+          const float w01 = w[0][o0] * w[1][o1];
+          const float d01 = dw[0][o0] * w[1][o1];
+          const float w0d1 = w[0][o0] * dw[1][o1];
+#pragma unroll
+          for (int o2 = 0; o2 < 3; ++o2) {
+            const float N = w01 * w[2][o2];
+            const float gN[3] = {d01 * w[2][o2], w0d1 * w[2][o2], w01 * dw[2][o2]};
+            const float o[3] = {(float)o0, (float)o1, (float)o2};
+            const AdjNode nd =
+                box.lds ? s_n[lbase + (o0 * box.e[1] + o1) * box.e[2] + o2]
+                        : adj_node_global<D>(A, gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
+            node(nd, N, gN, o);
+          }
+        }
+    }
+    // (J) delta parts: -sum N [ (4/dx^2) Ct^T v_i + G^T p_i ],
+    // with Ct = Cdx / dx and G = Gdx / dx
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      float s = 0.0f;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        s += sc.Dinv * Cdx[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
+      xb[c] -= s * sc.inv_dx;
+    }
+    // --- after the loop: reload F and dL/dF^{n+1}, recompute the stress ----
+    // (the compiler barrier keeps the pre-loop copies from staying live
+    // across the stencil loop: reloading is cheaper than the registers)
+    asm volatile("" ::: "memory");
+    float F[D * D], gF1[D * D], C1[D * D];
+    load_mat<D>(A.s.F, A.ld, p, F);
+    load_mat<D>(A.g1.F, A.ld, p, gF1);
+    load_mat<D>(A.C1, A.ld, p, C1);
+    Stress<D> S;
+    unsigned eb2 = 0;
+    stress<D>(sc, F, s_act, j_act >= 0, S, eb2);
+    float vb[D], Cb[D * D], Ptb[D * D], Fb[D * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) vb[a] = sc.mp * Spb[a];  // (F)
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      Gb[k] *= sc.dx;         // dL/dG = sum N p_i (x_i - x_p)^T
+      Cb[k] = sc.mp * Gb[k];  // (I)
+    }
+    // (G) dL/dP_t = kG dL/dG F
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
         float s = 0.0f;
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-          s += sc.Dinv * Ct[a * D + c] * Sv[a] + G[a * D + c] * Spb[a];
-        xb[c] -= s;
+        for (int g = 0; g < D; ++g) s += Gb[a * D + g] * F[g * D + b];
+        Ptb[a * D + b] = sc.kG * s;
       }
-      float vb[D], Cb[D * D], Ptb[D * D], Fb[D * D];
+    // (H) update term (I + dt C^{n+1})^T dL/dF^{n+1}
 #pragma unroll
-      for (int a = 0; a < D; ++a) vb[a] = sc.mp * Spb[a];  // (F)
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int k = 0; k < D * D; ++k) {
-        Gb[k] *= sc.dx;            // dL/dG = sum N p_i (x_i - x_p)^T
-        Cb[k] = sc.mp * Gb[k];     // (I)
+      for (int b = 0; b < D; ++b) {
+        float s = gF1[a * D + b];
+#pragma unroll
+        for (int g = 0; g < D; ++g) s += sc.dt * C1[g * D + a] * gF1[g * D + b];
+        Fb[a * D + b] = s;
       }
-      // (G) dL/dP_t = kG dL/dG F
+    // (H) G-term kG dL/dG^T P_t and actuation term dL/dP_t sigma^T
 #pragma unroll
-      for (int a = 0; a < D; ++a)
+    for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = 0.0f;
+      for (int b = 0; b < D; ++b) {
+        float s = 0.0f;
 #pragma unroll
-          for (int g = 0; g < D; ++g) s += Gb[a * D + g] * F[g * D + b];
-          Ptb[a * D + b] = sc.kG * s;
-        }
-      // (H) dL/dF: update term (I + dt C^{n+1})^T dL/dF^{n+1}
-      float C1[D * D];
-      load_mat<D>(A.C1, A.ld, p, C1);
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = gF1[a * D + b];
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += sc.dt * C1[g * D + a] * gF1[g * D + b];
-          Fb[a * D + b] = s;
-        }
-      // (H) G-term kG dL/dG^T P_t and actuation term dL/dP_t sigma^T
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = 0.0f;
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += Gb[g * D + a] * S.Pt[g * D + b];
-          Fb[a * D + b] += sc.kG * s + Ptb[a * D + b] * S.sigma[b];
-        }
-      // (H) elastic term: mu Ptb + (mu - la lnJ) F^-T Ptb^T F^-T
-      //                  + la <Ptb, F^-T> F^-T
-      float inner = 0.0f, T1[D * D];
-#pragma unroll
-      for (int k = 0; k < D * D; ++k) inner += Ptb[k] * S.FiT[k];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = 0.0f;  // (F^-T Ptb^T)_ab
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += S.FiT[a * D + g] * Ptb[b * D + g];
-          T1[a * D + b] = s;
-        }
-      const float cmu = sc.mu - sc.la * S.lnJ;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float s = 0.0f;
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += T1[a * D + g] * S.FiT[g * D + b];
-          Fb[a * D + b] +=
-              sc.mu * Ptb[a * D + b] + cmu * s + sc.la * inner * S.FiT[a * D + b];
-        }
-      // (K) dL/dsigma_aa = (F^T dL/dP_t)_aa;  s-bar = sum_a axis_a sigma-bar_aa
-      if (j_act >= 0) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          float s = 0.0f;
-#pragma unroll
-          for (int g = 0; g < D; ++g) s += F[g * D + a] * Ptb[g * D + a];
-          sb_act += sc.axis[a] * s;
-        }
+        for (int g = 0; g < D; ++g) s += Gb[g * D + a] * S.Pt[g * D + b];
+        Fb[a * D + b] += sc.kG * s + Ptb[a * D + b] * S.sigma[b];
       }
-      if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D) &&
-            finite_all(Fb, D * D)))
-        eb |= EB_NONFINITE;
+    // (H) elastic term: mu Ptb + (mu - la lnJ) F^-T Ptb^T F^-T
+    //                  + la <Ptb, F^-T> F^-T
+    float inner = 0.0f, T1[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) inner += Ptb[k] * S.FiT[k];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        float s = 0.0f;  // (F^-T Ptb^T)_ab
+#pragma unroll
+        for (int g = 0; g < D; ++g) s += S.FiT[a * D + g] * Ptb[b * D + g];
+        T1[a * D + b] = s;
+      }
+    const float cmu = sc.mu - sc.la * S.lnJ;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        float s = 0.0f;
+#pragma unroll
+        for (int g = 0; g < D; ++g) s += T1[a * D + g] * S.FiT[g * D + b];
+        Fb[a * D + b] += sc.mu * Ptb[a * D + b] + cmu * s + sc.la * inner * S.FiT[a * D + b];
+      }
+    // (K) dL/dsigma_aa = (F^T dL/dP_t)_aa;  s-bar = sum_a axis_a sigma-bar_aa
+    if (j_act >= 0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        float s = 0.0f;
+#pragma unroll
+        for (int g = 0; g < D; ++g) s += F[g * D + a] * Ptb[g * D + a];
+        sb_act += sc.axis[a] * s;
+      }
+    }
+    if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D) &&
+          finite_all(Fb, D * D)))
+      eb |= EB_NONFINITE;
+    if (ok) {
       store_vec<D>(A.g0.x, A.ld, p, xb);
       store_vec<D>(A.g0.v, A.ld, p, vb);
       store_mat<D>(A.g0.C, A.ld, p, Cb);
@@ -1313,6 +1907,52 @@ inline int blocks_for(int64_t n, int per = 256) {
 int launch_p2g(int dim, const P2GArgs &a, hipStream_t st) {
   if (dim == 2) MPM_LAUNCH(k_p2g<2>, a.n_chunks, CH, st, a);
   MPM_LAUNCH(k_p2g<3>, a.n_chunks, CH, st, a);
+}
+
+bool tile_supported(int dim, int B) {
+  return dim == 2 ? (B == 8 || B == 16) : (B == 4 || B == 8);
+}
+
+int launch_p2g_tile(int dim, const P2GArgs &a, int n_tiles, hipStream_t st) {
+  if (dim == 2 && a.tiles.B == 8) MPM_LAUNCH((k_p2g_tile<2, 8>), n_tiles, 256, st, a);
+  if (dim == 2 && a.tiles.B == 16) MPM_LAUNCH((k_p2g_tile<2, 16>), n_tiles, 256, st, a);
+  if (dim == 3 && a.tiles.B == 4) MPM_LAUNCH((k_p2g_tile<3, 4>), n_tiles, 256, st, a);
+  if (dim == 3 && a.tiles.B == 8) MPM_LAUNCH((k_p2g_tile<3, 8>), n_tiles, 256, st, a);
+  return -1;
+}
+
+int launch_adj_scatter_tile(int dim, const AdjScatterArgs &a, int n_tiles,
+                            hipStream_t st) {
+  if (dim == 2 && a.tiles.B == 8) MPM_LAUNCH((k_adj_scatter_tile<2, 8>), n_tiles, 256, st, a);
+  if (dim == 2 && a.tiles.B == 16) MPM_LAUNCH((k_adj_scatter_tile<2, 16>), n_tiles, 256, st, a);
+  if (dim == 3 && a.tiles.B == 4) MPM_LAUNCH((k_adj_scatter_tile<3, 4>), n_tiles, 256, st, a);
+  if (dim == 3 && a.tiles.B == 8) MPM_LAUNCH((k_adj_scatter_tile<3, 8>), n_tiles, 256, st, a);
+  return -1;
+}
+
+int launch_p2g_sorted(int dim, const P2GArgs &a, int n_tiles, hipStream_t st) {
+  if (dim == 2) MPM_LAUNCH(k_p2g_sorted<2>, n_tiles, 256, st, a);
+  MPM_LAUNCH(k_p2g_sorted<3>, n_tiles, 256, st, a);
+}
+
+int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_tiles,
+                              hipStream_t st) {
+  if (dim == 2) MPM_LAUNCH(k_adj_scatter_sorted<2>, n_tiles, 256, st, a);
+  MPM_LAUNCH(k_adj_scatter_sorted<3>, n_tiles, 256, st, a);
+}
+
+int launch_p2g_cell(int dim, const P2GArgs &a, const int *cell_cnt,
+                    int n_tiles, hipStream_t st) {
+  const int g = (n_tiles + 3) / 4;
+  if (dim == 2) MPM_LAUNCH(k_p2g_cell<2>, g, 256, st, a, cell_cnt, n_tiles);
+  MPM_LAUNCH(k_p2g_cell<3>, g, 256, st, a, cell_cnt, n_tiles);
+}
+
+int launch_adj_scatter_cell(int dim, const AdjScatterArgs &a,
+                            const int *cell_cnt, int n_tiles, hipStream_t st) {
+  const int g = (n_tiles + 3) / 4;
+  if (dim == 2) MPM_LAUNCH(k_adj_scatter_cell<2>, g, 256, st, a, cell_cnt, n_tiles);
+  MPM_LAUNCH(k_adj_scatter_cell<3>, g, 256, st, a, cell_cnt, n_tiles);
 }
 
 int launch_grid(int dim, const GridArgs &a, hipStream_t st) {

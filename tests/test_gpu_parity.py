@@ -119,7 +119,7 @@ def test_act_bank_matches_oracle():
     assert rel_err(gp.cpu().numpy(), rp) < 1e-5
 
 
-def _rollout_case(sc, T, ks, loss2_seed=21):
+def _rollout_case(sc, T, ks, loss2_seed=21, **sim_kw):
     os_ = oscene(sc)
     acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase)
     acts32 = acts.astype(np.float32)
@@ -134,9 +134,9 @@ def _rollout_case(sc, T, ks, loss2_seed=21):
     gT32 = [a.astype(np.float32) for a in gT]
     refT, ref0, ref_act = oracle.rollout(os_, f64(sc.state), T, sc.act_id,
                                          acts32.astype(np.float64), f64(gT32))
-    sim = sim_for(sc)
+    sim = sim_for(sc, **sim_kw)
     for k in ks:
-        say("rollout", sc.name, "T", T, "k", k)
+        say("rollout", sc.name, "T", T, "k", k, sim_kw)
         sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts32, device="cuda"),
                                    T, ckpt_k=k, gT=to_gpu(gT32))
         sim.sync_errors()
@@ -156,10 +156,29 @@ def test_rollout_c1b_100_steps():
     _rollout_case(S.config_1b(), 100, ks=[0, 32])
 
 
+@pytest.mark.parametrize("scatter", [1, 2, 3])
+def test_rollout_scatter_modes(scatter):
+    # both binned scatter implementations (per-particle LDS atomics, per-cell
+    # register accumulation) in 2D and 3D
+    _rollout_case(S.config_1b(), 50, ks=[10], scatter=scatter)
+    _rollout_case(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=32), 30, ks=[0], scatter=scatter)
+
+
 def test_rollout_3d_box_contact():
     # a 3D block dropped onto the floor: wall contact within the rollout
     sc = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=31)
     _rollout_case(sc, 60, ks=[0, 16])
+
+
+@pytest.mark.parametrize("scatter", [1, 2, 3])
+def test_rollout_fast_drift_uses_overflow_path(scatter):
+    # particles binned once per rollout drift ~4 cells here: out of their
+    # cell (per-cell mode: LDS atomics into the box) and beyond the one cell
+    # of slack of their tile box (global atomics); results must not change
+    sc = S.block_2d(64, (0.2, 0.3), (0.35, 0.45), seed=51)
+    sc.v[0, :] = 6.0
+    sc.v[1, :] = 2.0
+    _rollout_case(sc, 100, ks=[0, 25], scatter=scatter)
 
 
 def test_batched_scenes_match_per_scene_oracle():
