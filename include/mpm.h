@@ -87,7 +87,11 @@ typedef struct mpm_opts {
                           2 = per-cell register accumulation in bin order;
                           3 = per-cell accumulation after an in-LDS sort of
                           each tile by current cell (insensitive to drift)  */
-  int32_t reserved[5]; /* must be 0                                         */
+  int32_t recompute_grids; /* checkpointed rollouts: 0 = keep every
+                          substep's grid (m, p) on the tape so the reverse
+                          pass recomputes states with G2P only (default);
+                          1 = keep only states and recompute grids too      */
+  int32_t reserved[4]; /* must be 0                                         */
 } mpm_opts;
 
 /* Particle state or its adjoint (DEVICE pointers, layout above). */

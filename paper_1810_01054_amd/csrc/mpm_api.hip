@@ -34,6 +34,7 @@ struct mpm_ctx {
   int tile = 0;
   int sort = 1;
   int scatter_mode = 1;  // binned scatters: 1 atomics, 2 per-cell, 3 sorted per-cell
+  int keep_grids = 1;    // checkpointed tapes keep every substep's grid
   hipStream_t stream = nullptr;
   int poisoned = 0;
 
@@ -71,7 +72,7 @@ struct mpm_ctx {
 
   // tape
   struct Tape {
-    int valid = 0, T = 0, k = 0, memo = 0, sorted = 0;
+    int valid = 0, T = 0, k = 0, memo = 0, sorted = 0, grids_all = 0;
     float *states = nullptr;  // slots of one state each
     int64_t state_cap = 0;    // slots allocated
     float *grids = nullptr;   // slots of (1 + d) * G floats (m, p)
@@ -242,7 +243,7 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
 }
 
 int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
-             int zero_mp) {
+             int zero_mp, float *out_m = nullptr, float *out_p = nullptr) {
   GridArgs a;
   a.scenes = c->d_scenes;
   a.blocks = c->d_gblocks;
@@ -255,12 +256,15 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
   a.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
   a.part = tiles ? c->d_part : nullptr;
   a.B = c->tile;
+  a.out_m = out_m;
+  a.out_p = out_p;
   ProfScope ps(c, MPM_K_GRID);
   return launch_grid(c->dim, a, c->stream);
 }
 
 int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
-            State out, const float *gv) {
+            State out, const float *gv, const float *gm = nullptr,
+            const float *gp = nullptr) {
   G2PArgs a;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
@@ -269,6 +273,8 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   a.out = out;
   a.ld = (int)c->N;
   a.gv = gv;
+  a.gm = gm;
+  a.gp = gp;
   a.G = c->G;
   a.err = c->d_err;
   ProfScope ps(c, MPM_K_G2P);
@@ -488,12 +494,11 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
     const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
-    if (L.memo) {
-      float *g = slot_grid(c, n);
-      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G));
-      RC(fwd_grid(c, tiles, g, g + c->G, c->gv, 0));
+    RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+    if (c->tape.grids_all) {
+      float *g = slot_grid(c, n);  // keep this substep's grid on the tape
+      RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
     } else {
-      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
     RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
@@ -513,6 +518,9 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   State A1 = state_at(c, t.adj), A0 = state_at(c, t.adj + sf);
   if (t.sorted) RC(permute_state(c, *gT, A1, 0));
   else RC(copy_state(c, *gT, A1));
+  // step calls may have left their grid in gm/gp; recomputed P2Gs start at 0
+  RC(launch_fill_f32(c->gm, c->G, c->stream));
+  RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   const int64_t nga = (int64_t)t.T * c->n_act;
   if (nga > 0) {
     RC(ensure_gact(c, nga));
@@ -530,19 +538,24 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
       return slot_state(c, L.ncp + (n - n0));
     };
     auto Gr = [&](int n) -> float * {
-      return t.memo ? slot_grid(c, n) : slot_grid(c, n - n0);
+      return t.grids_all ? slot_grid(c, n) : slot_grid(c, n - n0);
     };
-    if (!t.memo) {
+    if (!t.memo && t.grids_all) {
+      // recompute the segment's states from its checkpoint with G2P alone,
+      // reading each substep's stored grid
+      for (int n = n0; n + 1 < n1; ++n) {
+        const float *g = Gr(n);
+        RC(fwd_g2p(c, chunks, nch, cs(state_at(c, S(n))), state_at(c, S(n + 1)),
+                   nullptr, g, g + c->G));
+      }
+    } else if (!t.memo) {
       // recompute the segment from its checkpoint, keeping states and grids
-      RC(launch_fill_f32(slot_grid(c, 0), (int64_t)(n1 - n0) * (1 + c->dim) * c->G,
-                         c->stream));
       for (int n = n0; n < n1; ++n) {
         const State s = state_at(c, S(n));
         const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
         float *g = Gr(n);
-        RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G));
-        // sums the tile boxes into the slot (and gives v for the next G2P)
-        RC(fwd_grid(c, tiles, g, g + c->G, c->gv, 0));
+        RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+        RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
         if (n + 1 < n1)
           RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(n + 1)), c->gv));
       }
@@ -631,9 +644,12 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int tile = dim == 2 ? 8 : 4;
   int sort = 1;
   int scatter = 0;
+  int recompute_grids = 0;
   if (opts) {
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 4; ++k)
       if (opts->reserved[k]) return MPM_ERR_ARG;
+    if (opts->recompute_grids != 0 && opts->recompute_grids != 1) return MPM_ERR_ARG;
+    recompute_grids = opts->recompute_grids;
     if (opts->scatter < 0 || opts->scatter > 3) return MPM_ERR_ARG;
     scatter = opts->scatter;
     if (opts->tile && !tile_supported(dim, opts->tile)) return MPM_ERR_ARG;
@@ -672,6 +688,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   c->n_act = n_act;
   c->tile = tile;
   c->sort = sort;
+  c->keep_grids = !recompute_grids;
   {
     const int cells = dim == 2 ? tile * tile : tile * tile * tile;
     if ((scatter == 2 || scatter == 3) && cells != 64) {
@@ -900,12 +917,14 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   const int memo = ckpt_k == 0;
   const int k = memo ? 1 : std::min(ckpt_k, std::max(T, 1));
   const int ncp = memo ? T + 1 : (T + k - 1) / k + 1;
+  const int grids_all = memo || c->keep_grids;
   const int64_t nstates = memo ? T + 1 : ncp + k;
-  const int64_t ngrids = memo ? T : k;
+  const int64_t ngrids = grids_all ? T : k;
   RC(ensure_tape(c, nstates, ngrids, (int64_t)T * c->n_act));
   t.T = T;
   t.k = k;
   t.memo = memo;
+  t.grids_all = grids_all;
   t.sorted = c->sort && c->N > 0;
   if (c->n_act && T > 0)
     RC(hip_ok(hipMemcpyAsync(t.act, act, sizeof(float) * T * c->n_act,
@@ -918,9 +937,6 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   } else {
     RC(copy_state(c, *s0, S0));
   }
-  if (memo && T > 0)
-    RC(launch_fill_f32(slot_grid(c, 0), (int64_t)T * (1 + c->dim) * c->G,
-                       c->stream));
   // the step calls leave their grid in gm/gp; rollouts start from zero
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));

@@ -100,11 +100,11 @@ struct GridArgs {
   int n_blocks;
   float *gm, *gp, *gv;
   int64_t G;
-  int zero_mp;  // clear m and p after reading them (next P2G starts at 0);
-                // otherwise store the summed m and p back
+  int zero_mp;  // clear m and p after reading them (next P2G starts at 0)
   const int *tile_cnt;  // non-null: add the tile boxes in `part`
   const float *part;
   int B;
+  float *out_m, *out_p;  // non-null: store the summed m and p here (may be gm/gp)
 };
 
 struct G2PArgs {
@@ -115,6 +115,7 @@ struct G2PArgs {
   State out;    // writes x, v, C, F (may alias s)
   int ld;
   const float *gv;
+  const float *gm, *gp;  // non-null: velocities from these m, p (not gv)
   int64_t G;
   unsigned *err;
 };

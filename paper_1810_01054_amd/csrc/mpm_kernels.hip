@@ -1051,6 +1051,21 @@ __device__ __forceinline__ bool is_wall(int li, int n, int wall) {
   return w;
 }
 
+// Grid operations at one node (section III step 2 with gravity and sticky
+// walls): v = p/m + dt g where m > 0, else 0; 0 on wall nodes.
+template <int D>
+__device__ __forceinline__ void node_velocity(const DevScene &sc, int li,
+                                              float m, const float *p,
+                                              float *v) {
+  const bool wall = is_wall<D>(li, sc.n, sc.wall);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    float va = 0.0f;
+    if (m > 0.0f) va = p[a] / m + sc.dt * sc.g[a];
+    v[a] = wall ? 0.0f : va;
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
   const GridBlock gb = A.blocks[blockIdx.x];
@@ -1064,27 +1079,19 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
   for (int a = 0; a < D; ++a) mp[1 + a] = A.gp[a * A.G + gi];
   const bool direct = mp[0] != 0.0f;
   if (A.part) add_tile_boxes_any<D, D + 1>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, mp);
-  const float m = mp[0];
-  const bool wall = is_wall<D>(li, sc.n, sc.wall);
   float v[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    float va = 0.0f;
-    if (m > 0.0f) va = mp[1 + a] / m + sc.dt * sc.g[a];
-    v[a] = wall ? 0.0f : va;
-  }
+  node_velocity<D>(sc, li, mp[0], mp + 1, v);
 #pragma unroll
   for (int a = 0; a < D; ++a) A.gv[a * A.G + gi] = v[a];
-  if (A.zero_mp) {
-    if (direct) {
-      A.gm[gi] = 0.0f;
+  if (A.zero_mp && direct) {
+    A.gm[gi] = 0.0f;
 #pragma unroll
-      for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = 0.0f;
-    }
-  } else if (A.part) {
-    A.gm[gi] = m;
+    for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = 0.0f;
+  }
+  if (A.out_m) {
+    A.out_m[gi] = mp[0];
 #pragma unroll
-    for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = mp[1 + a];
+    for (int a = 0; a < D; ++a) A.out_p[a * A.G + gi] = mp[1 + a];
   }
 }
 
@@ -1109,11 +1116,25 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
   const Box<D> box = chunk_box<D>(ok, base);
+  // grid velocity at scene-local node li (from v, or from stored m and p)
+  auto vel = [&](int li, float *v) {
+    const int64_t gi = sc.g_off + li;
+    if (A.gm) {
+      float pp[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) pp[a] = A.gp[a * A.G + gi];
+      node_velocity<D>(sc, li, A.gm[gi], pp, v);
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a) v[a] = A.gv[a * A.G + gi];
+    }
+  };
   if (box.lds) {
     for (int i = t; i < box.vol; i += CH) {
-      const int64_t gi = sc.g_off + box_node<D>(box, i, sc.n);
+      float v[D];
+      vel(box_node<D>(box, i, sc.n), v);
 #pragma unroll
-      for (int a = 0; a < D; ++a) s_v[a * LDS_NODES + i] = A.gv[a * A.G + gi];
+      for (int a = 0; a < D; ++a) s_v[a * LDS_NODES + i] = v[a];
     }
     __syncthreads();
   }
@@ -1150,9 +1171,7 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
           vi[0] = s_v[li];
           vi[1] = s_v[LDS_NODES + li];
         } else {
-          const int64_t gi = gbase + o0 * sc.n + o1;
-          vi[0] = A.gv[gi];
-          vi[1] = A.gv[A.G + gi];
+          vel((int)(gbase - sc.g_off) + o0 * sc.n + o1, vi);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -1180,10 +1199,7 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
             vi[1] = s_v[LDS_NODES + li];
             vi[2] = s_v[2 * LDS_NODES + li];
           } else {
-            const int64_t gi = gbase + (o0 * sc.n + o1) * sc.n + o2;
-            vi[0] = A.gv[gi];
-            vi[1] = A.gv[A.G + gi];
-            vi[2] = A.gv[2 * A.G + gi];
+            vel((int)(gbase - sc.g_off) + (o0 * sc.n + o1) * sc.n + o2, vi);
           }
 #pragma unroll
           for (int a = 0; a < 3; ++a) {

@@ -54,7 +54,8 @@ class Simulator:
     ``paper_1810_01054_amd.scenes.Scene.params()``)."""
 
     def __init__(self, scenes: Sequence[dict], act_id: Optional[np.ndarray] = None,
-                 tile: int = 0, sort: bool = True, scatter: int = 0, stream=None):
+                 tile: int = 0, sort: bool = True, scatter: int = 0,
+                 recompute_grids: bool = False, stream=None):
         self.L = _lib.lib()
         self.scenes = [dict(s) for s in scenes]
         self.dim = self.scenes[0]["dim"]
@@ -66,6 +67,7 @@ class Simulator:
             ids = ids_np.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         opts = _lib.Opts()
         opts.tile, opts.sort, opts.scatter = tile, int(bool(sort)), scatter
+        opts.recompute_grids = int(bool(recompute_grids))
         self.ctx = ctypes.c_void_p()
         self._stream = stream
         check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,

@@ -164,6 +164,36 @@ def test_rollout_scatter_modes(scatter):
     _rollout_case(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=32), 30, ks=[0], scatter=scatter)
 
 
+@pytest.mark.parametrize("recompute_grids", [False, True])
+def test_rollout_then_step_then_backward(recompute_grids):
+    # the tape survives step calls between a rollout and its reverse pass, for
+    # tapes with stored grids and for tapes that recompute them
+    sc = S.config_1b()
+    T, k = 40, 8
+    os_ = oscene(sc)
+    acts32 = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    N = sc.n_particles
+    gT = [np.zeros((2, N)), np.zeros((2, N)), np.zeros((4, N)), np.zeros((4, N))]
+    gT[0] += np.random.default_rng(3).normal(size=(2, N)) / N
+    gT32 = [a.astype(np.float32) for a in gT]
+    refT, ref0, ref_act = oracle.rollout(os_, f64(sc.state), T, sc.act_id,
+                                         acts32.astype(np.float64), f64(gT32))
+    say("rollout_then_step_then_backward", recompute_grids)
+    sim = sim_for(sc, recompute_grids=recompute_grids)
+    sT = sim.rollout(to_gpu(sc.state), torch.tensor(acts32, device="cuda"), T, ckpt_k=k)
+    sim.step_forward(to_gpu(sc.state), torch.ones(sc.n_act, device="cuda"))
+    g0, gact = sim.rollout_backward(to_gpu(gT32), T)
+    sim.sync_errors()
+    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    for c in range(4):
+        assert rel_err(to_np(g0)[c], ref0[c]) < GRAD_TOL
+    assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+    # the reverse pass can be run again on the same tape
+    g0b, _ = sim.rollout_backward(to_gpu(gT32), T)
+    sim.sync_errors()
+    assert rel_err(to_np(g0b)[0], to_np(g0)[0]) < 1e-6
+
+
 def test_rollout_3d_box_contact():
     # a 3D block dropped onto the floor: wall contact within the rollout
     sc = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=31)
