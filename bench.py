@@ -77,6 +77,133 @@ def cpu_baseline(sc, T_sample: int):
                       f"{dt:.1f} s"}
 
 
+def run_batched(args):
+    """64 uneven 2D scenes (N log-uniform in [2k, 60k], grids 64^2..256^2) in
+    one context: every kernel of a substep covers all scenes in one launch.
+    Compared with the same kernels run one scene at a time."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01054_amd import scenes as S
+    from paper_1810_01054_amd.autograd import rollout
+    from paper_1810_01054_amd.sim import Simulator, act_bank_forward
+
+    dev = "cuda:0"
+    scs = S.config_4()
+    T, k = args.T if args.T != 512 else 200, args.ckpt
+    t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
+
+    def acts_of(group):
+        return torch.cat([act_bank_forward(T, s.dt, t(s.freq), t(s.amp), t(s.phase))
+                          for s in group], dim=1).contiguous()
+
+    def state_of(group):
+        return tuple(t(np.concatenate([s.state[c] for s in group], axis=1)) for c in range(4))
+
+    def seed_of(group):
+        # L = sum over scenes of the centroid x of the final state
+        g = [np.zeros((2, sum(s.n_particles for s in group)), np.float32),
+             None, None, None]
+        off = 0
+        for s in group:
+            g[0][0, off:off + s.n_particles] = 1.0 / s.n_particles
+            off += s.n_particles
+        n = g[0].shape[1]
+        return (t(g[0]), torch.zeros(2, n, device=dev), torch.zeros(4, n, device=dev),
+                torch.zeros(4, n, device=dev))
+
+    def make(group, **opts):
+        ids = np.concatenate([s.act_id for s in group])
+        sim = Simulator([s.params() for s in group], act_id=ids, **opts)
+        return sim, state_of(group), acts_of(group), seed_of(group)
+
+    def run(setups, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for sim, s0, act, gT in setups:
+                sim.rollout(s0, act, T, k, gT)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    from paper_1810_01054_amd.autotune import tune
+    N = sum(s.n_particles for s in scs)
+    tuned = tune([s.params() for s in scs], np.concatenate([s.act_id for s in scs]),
+                 state_of(scs), acts_of(scs), use_cache=False)
+    batched = [make(scs, **tuned)]
+    run(batched, 1)
+    wb = run(batched, args.steps)
+    batched[0][0].sync_errors()
+    eager = [make(scs, **dict(tuned, graphs=False))]
+    run(eager, 1)
+    we = run(eager, args.steps)
+    eager[0][0].sync_errors()
+    del eager
+    loop = [make([s]) for s in scs]
+    run(loop, 1)
+    wl = run(loop, args.steps)
+    for sim, *_ in loop:
+        sim.sync_errors()
+    vb = N * T * args.steps / wb
+    ve = N * T * args.steps / we
+    vl = N * T * args.steps / wl
+    out = {"metric": "particle-substeps/s fwd+bwd, 64 batched 2D scenes",
+           "value": round(vb, 1), "unit": "particle-substeps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": round(wb / args.steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"64 2D scenes, {N} particles in total, grids "
+                                  f"{sorted(set(s.n_grid for s in scs))}, T={T} fwd+bwd, "
+                                  f"checkpoint k={k}, one launch per kernel per substep, "
+                                  f"autotuned options",
+                      "scenes": len(scs), "particles": N, "substeps": T, "ckpt_k": k,
+                      "autotuned": tuned},
+           "batched_without_graphs": {"value": round(ve, 1),
+                                      "ms_per_step": round(we / args.steps * 1e3, 3)},
+           "per_scene_loop": {"value": round(vl, 1), "ms_per_step": round(wl / args.steps * 1e3, 3)},
+           "speedup_vs_per_scene_loop": round(vb / vl, 3)}
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args):
+    """Poisson arrivals of forward+gradient rollout requests (half 2D, half
+    3D) served by the continuous-admission loop and, on the same trace, by
+    the plain one-at-a-time loop.  The arrival rate is swept at fractions of
+    the plain loop's measured capacity plus one overload point."""
+    import torch
+
+    from paper_1810_01054_amd import scenes as S
+    from paper_1810_01054_amd.serve import Server, summarize
+
+    n_req = args.requests
+    base = S.config_5(n_requests=n_req, rate=1.0, seed=1815)
+    warm = S.config_5(n_requests=6, rate=1.0, seed=1816)
+    Server(max_slots=4, ckpt_k=args.ckpt).run([S.Request(0.0, r.scene, r.T) for r in warm])
+    burst = [S.Request(0.0, r.scene, r.T) for r in base]
+    cap_res = Server(max_slots=1, ckpt_k=args.ckpt).run(burst, fifo=True)
+    cap = summarize(cap_res)["requests_per_s"]
+    points = []
+    for frac in (0.5, 0.8, 0.95, 1.5):
+        rate = frac * cap
+        reqs = [S.Request(r.arrival / rate, r.scene, r.T) for r in base]
+        mix = summarize(Server(max_slots=args.slots, ckpt_k=args.ckpt).run(reqs))
+        fifo = summarize(Server(max_slots=1, ckpt_k=args.ckpt).run(reqs, fifo=True))
+        points.append({"load": frac, "rate_per_s": round(rate, 3), "continuous": mix,
+                       "fifo": fifo})
+    top = points[2]["continuous"]
+    out = {"metric": "p99 rollout latency (serving, Poisson mix of 2D/3D fwd+grad requests)",
+           "value": top["latency_s"]["p99"], "unit": "s", "n_gpus": 1, "steps": n_req,
+           "warmup": len(warm), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n_req} requests, half 2D (4k-100k particles, 64-256^2) "
+                                  f"half 3D (50k-500k, 32-64^3), T 100-500, load 0.95 of "
+                                  f"the plain loop's capacity", "slots": args.slots,
+                      "ckpt_k": args.ckpt},
+           "plain_loop_capacity_req_per_s": round(cap, 3),
+           "points": points}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +217,11 @@ def main():
     ap.add_argument("--scatter", type=int, default=0,
                     help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
                          "2 per-cell in bin order, 3 per-cell after an LDS sort")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+                    help="c3: 3D quadruped (headline); c4: 64 batched 2D scenes; "
+                         "c5: serving a Poisson request mix")
+    ap.add_argument("--requests", type=int, default=60, help="c5: requests per load point")
+    ap.add_argument("--slots", type=int, default=8, help="c5: concurrent requests")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -112,6 +244,10 @@ def main():
         sys.exit(1)
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return run_batched(args)
+    if args.workload == "c5":
+        return run_serving(args)
 
     sc = S.config_3()
     T, k = args.T, args.ckpt

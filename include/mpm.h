@@ -91,7 +91,11 @@ typedef struct mpm_opts {
                           substep's grid (m, p) on the tape so the reverse
                           pass recomputes states with G2P only (default);
                           1 = keep only states and recompute grids too      */
-  int32_t reserved[4]; /* must be 0                                         */
+  int32_t graphs;      /* 1: rollouts replay hipGraphs of their inner loops
+                          (captured once per tape layout on a library-owned
+                          stream, launched on the context's stream); kernel
+                          timing (mpm_profile) turns them off; 0 = eager     */
+  int32_t reserved[3]; /* must be 0                                         */
 } mpm_opts;
 
 /* Particle state or its adjoint (DEVICE pointers, layout above). */

@@ -35,7 +35,7 @@ class Scene(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("sort", ctypes.c_int32),
                 ("scatter", ctypes.c_int32), ("recompute_grids", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class State(ctypes.Structure):

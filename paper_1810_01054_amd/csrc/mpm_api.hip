@@ -35,6 +35,27 @@ struct mpm_ctx {
   int sort = 1;
   int scatter_mode = 1;  // binned scatters: 1 atomics, 2 per-cell, 3 sorted per-cell
   int keep_grids = 1;    // checkpointed tapes keep every substep's grid
+  int use_graphs = 0;    // rollouts replay captured hipGraphs
+
+  // captured inner loops of rollouts (forward, reverse)
+  struct GraphKey {
+    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0;
+    const void *p[8] = {};
+    bool operator==(const GraphKey &o) const {
+      if (T != o.T || k != o.k || memo != o.memo || grids_all != o.grids_all ||
+          sorted != o.sorted || nch != o.nch)
+        return false;
+      for (int i = 0; i < 8; ++i)
+        if (p[i] != o.p[i]) return false;
+      return true;
+    }
+  };
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    GraphKey key;
+    bool valid = false;
+  } gfwd, gbwd;
+  hipStream_t cap_stream = nullptr;
   hipStream_t stream = nullptr;
   int poisoned = 0;
 
@@ -103,10 +124,12 @@ namespace {
 int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
 
 template <typename T>
-int dmalloc(T **p, int64_t count) {
+int dmalloc(T **p, int64_t count, hipStream_t st) {
+  // stream-ordered allocation: no device-wide synchronisation, so contexts
+  // can come and go while other contexts' work runs on other streams
   *p = nullptr;
   if (count <= 0) count = 1;
-  hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)count);
+  hipError_t e = hipMallocAsync((void **)p, sizeof(T) * (size_t)count, st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
@@ -116,8 +139,8 @@ int dmalloc(T **p, int64_t count) {
 }
 
 template <typename T>
-void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
+void dfree(T *&p, hipStream_t st) {
+  if (p) (void)hipFreeAsync((void *)p, st);
   p = nullptr;
 }
 
@@ -352,9 +375,9 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
 
 int ensure_gact(mpm_ctx *c, int64_t n) {
   if (n <= c->gact_cap) return MPM_OK;
-  dfree(c->gact);
+  dfree(c->gact, c->stream);
   c->gact_cap = 0;
-  RC(dmalloc(&c->gact, n));
+  RC(dmalloc(&c->gact, n, c->stream));
   c->gact_cap = n;
   return MPM_OK;
 }
@@ -426,25 +449,25 @@ int ensure_tape(mpm_ctx *c, int64_t states, int64_t grids, int64_t act) {
   const int64_t sf = c->state_floats();
   const int64_t gf = (int64_t)(1 + c->dim) * c->G;
   if (states > t.state_cap) {
-    dfree(t.states);
+    dfree(t.states, c->stream);
     t.state_cap = 0;
-    RC(dmalloc(&t.states, states * sf));
+    RC(dmalloc(&t.states, states * sf, c->stream));
     t.state_cap = states;
   }
   if (grids > t.grid_cap) {
-    dfree(t.grids);
+    dfree(t.grids, c->stream);
     t.grid_cap = 0;
-    RC(dmalloc(&t.grids, grids * gf));
+    RC(dmalloc(&t.grids, grids * gf, c->stream));
     t.grid_cap = grids;
   }
   if (act > t.act_cap) {
-    dfree(t.act);
+    dfree(t.act, c->stream);
     t.act_cap = 0;
-    RC(dmalloc(&t.act, act));
+    RC(dmalloc(&t.act, act, c->stream));
     t.act_cap = act;
   }
-  if (!t.pp) RC(dmalloc(&t.pp, 2 * sf));
-  if (!t.adj) RC(dmalloc(&t.adj, 2 * sf));
+  if (!t.pp) RC(dmalloc(&t.pp, 2 * sf, c->stream));
+  if (!t.adj) RC(dmalloc(&t.adj, 2 * sf, c->stream));
   return MPM_OK;
 }
 
@@ -485,6 +508,62 @@ float *fwd_slot(mpm_ctx *c, const Layout &L, int n) {
   return c->tape.pp + (int64_t)(n & 1) * c->state_floats();
 }
 
+// Run `body` (stream-ordered launches on c->stream only) directly, or as a
+// hipGraph captured once per key on a library-owned stream and replayed on
+// the context's stream.
+template <typename F>
+int run_maybe_graph(mpm_ctx *c, mpm_ctx::GraphSlot &slot,
+                    const mpm_ctx::GraphKey &key, F &&body) {
+  if (!c->use_graphs || c->prof.mask || c->tape.T == 0) return body();
+  if (!slot.valid || !(slot.key == key)) {
+    if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+    slot.exec = nullptr;
+    slot.valid = false;
+    if (!c->cap_stream)
+      RC(hip_ok(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    int rc = hip_ok(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    if (!rc) {
+      const int rb = body();
+      const hipError_t e = hipStreamEndCapture(c->stream, &g);
+      rc = rb ? rb : hip_ok(e);
+    }
+    c->stream = user;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    rc = hip_ok(hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    slot.key = key;
+    slot.valid = true;
+  }
+  return hip_ok(hipGraphLaunch(slot.exec, c->stream));
+}
+
+mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
+  mpm_ctx::GraphKey k;
+  const auto &t = c->tape;
+  k.T = t.T;
+  k.k = t.k;
+  k.memo = t.memo;
+  k.grids_all = t.grids_all;
+  k.sorted = t.sorted;
+  int nch = 0;
+  k.p[6] = cur_chunks(c, &nch);
+  k.nch = nch;
+  k.p[0] = t.states;
+  k.p[1] = t.grids;
+  k.p[2] = t.act;
+  k.p[3] = t.pp;
+  k.p[4] = t.adj;
+  k.p[5] = c->gact;
+  return k;
+}
+
 int rollout_forward(mpm_ctx *c, const Layout &L) {
   int nch = 0;
   const Chunk *chunks = cur_chunks(c, &nch);
@@ -506,8 +585,9 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   return MPM_OK;
 }
 
-int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
-                     float *g_act) {
+// Reverse pass over library-owned buffers only: reads the adjoint of S^T
+// from adj slot 0, leaves the adjoint of S^0 in adj slot (T & 1).
+int rollout_backward_core(mpm_ctx *c) {
   auto &t = c->tape;
   const Layout L{t.T, t.k, t.memo, t.memo ? t.T + 1 : (t.T + t.k - 1) / t.k + 1};
   int nch = 0;
@@ -516,16 +596,11 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   const bool tiles = t.sorted;
   const int64_t sf = c->state_floats();
   State A1 = state_at(c, t.adj), A0 = state_at(c, t.adj + sf);
-  if (t.sorted) RC(permute_state(c, *gT, A1, 0));
-  else RC(copy_state(c, *gT, A1));
   // step calls may have left their grid in gm/gp; recomputed P2Gs start at 0
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   const int64_t nga = (int64_t)t.T * c->n_act;
-  if (nga > 0) {
-    RC(ensure_gact(c, nga));
-    RC(launch_fill_f64(c->gact, nga, c->stream));
-  }
+  if (nga > 0) RC(launch_fill_f64(c->gact, nga, c->stream));
   const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
   const int seglen = t.memo ? 1 : t.k;
   for (int j = nseg - 1; j >= 0; --j) {
@@ -570,8 +645,22 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
       std::swap(A0, A1);
     }
   }
-  if (t.sorted) RC(permute_state(c, ms(A1), st(*g0), 1));
-  else RC(copy_state(c, ms(A1), st(*g0)));
+  return MPM_OK;
+}
+
+int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
+                     float *g_act) {
+  auto &t = c->tape;
+  const int64_t sf = c->state_floats();
+  const State A_in = state_at(c, t.adj);
+  if (t.sorted) RC(permute_state(c, *gT, A_in, 0));
+  else RC(copy_state(c, *gT, A_in));
+  const int64_t nga = (int64_t)t.T * c->n_act;
+  if (nga > 0) RC(ensure_gact(c, nga));
+  RC(run_maybe_graph(c, c->gbwd, graph_key(c), [&] { return rollout_backward_core(c); }));
+  const State A_out = state_at(c, t.adj + (t.T & 1) * sf);
+  if (t.sorted) RC(permute_state(c, ms(A_out), st(*g0), 1));
+  else RC(copy_state(c, ms(A_out), st(*g0)));
   if (g_act && nga > 0)
     RC(launch_gact_store(c->gact, g_act, nga, 0, c->stream));
   return MPM_OK;
@@ -598,39 +687,42 @@ const char *mpm_strerror(int code) {
 void mpm_destroy(mpm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  dfree(c->d_scenes);
-  dfree(c->d_chunks_user);
-  dfree(c->d_gblocks);
-  dfree(c->d_act_id);
-  dfree(c->d_pscene);
-  dfree(c->gm);
-  dfree(c->gp);
-  dfree(c->gv);
-  dfree(c->vbar);
-  dfree(c->pbar);
-  dfree(c->mbar);
-  dfree(c->gact);
-  dfree(c->d_err);
-  dfree(c->scratch);
-  dfree(c->d_tile_scene);
-  dfree(c->d_tile_cnt);
-  dfree(c->d_cell_cnt);
-  dfree(c->d_ptile);
-  dfree(c->d_pcell);
-  dfree(c->d_prank);
-  dfree(c->d_tile_start);
-  dfree(c->d_nch);
-  dfree(c->d_chunk_start);
-  dfree(c->d_perm);
-  dfree(c->d_act_sorted);
-  dfree(c->d_chunks_sorted);
-  dfree(c->d_part);
-  dfree(c->tape.states);
-  dfree(c->tape.grids);
-  dfree(c->tape.act);
-  dfree(c->tape.pp);
-  dfree(c->tape.adj);
+  dfree(c->d_scenes, c->stream);
+  dfree(c->d_chunks_user, c->stream);
+  dfree(c->d_gblocks, c->stream);
+  dfree(c->d_act_id, c->stream);
+  dfree(c->d_pscene, c->stream);
+  dfree(c->gm, c->stream);
+  dfree(c->gp, c->stream);
+  dfree(c->gv, c->stream);
+  dfree(c->vbar, c->stream);
+  dfree(c->pbar, c->stream);
+  dfree(c->mbar, c->stream);
+  dfree(c->gact, c->stream);
+  dfree(c->d_err, c->stream);
+  dfree(c->scratch, c->stream);
+  dfree(c->d_tile_scene, c->stream);
+  dfree(c->d_tile_cnt, c->stream);
+  dfree(c->d_cell_cnt, c->stream);
+  dfree(c->d_ptile, c->stream);
+  dfree(c->d_pcell, c->stream);
+  dfree(c->d_prank, c->stream);
+  dfree(c->d_tile_start, c->stream);
+  dfree(c->d_nch, c->stream);
+  dfree(c->d_chunk_start, c->stream);
+  dfree(c->d_perm, c->stream);
+  dfree(c->d_act_sorted, c->stream);
+  dfree(c->d_chunks_sorted, c->stream);
+  dfree(c->d_part, c->stream);
+  dfree(c->tape.states, c->stream);
+  dfree(c->tape.grids, c->stream);
+  dfree(c->tape.act, c->stream);
+  dfree(c->tape.pp, c->stream);
+  dfree(c->tape.adj, c->stream);
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->gfwd.exec) (void)hipGraphExecDestroy(c->gfwd.exec);
+  if (c->gbwd.exec) (void)hipGraphExecDestroy(c->gbwd.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -645,9 +737,12 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int sort = 1;
   int scatter = 0;
   int recompute_grids = 0;
+  int graphs = 0;
   if (opts) {
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 3; ++k)
       if (opts->reserved[k]) return MPM_ERR_ARG;
+    if (opts->graphs != 0 && opts->graphs != 1) return MPM_ERR_ARG;
+    graphs = opts->graphs;
     if (opts->recompute_grids != 0 && opts->recompute_grids != 1) return MPM_ERR_ARG;
     recompute_grids = opts->recompute_grids;
     if (opts->scatter < 0 || opts->scatter > 3) return MPM_ERR_ARG;
@@ -689,6 +784,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   c->tile = tile;
   c->sort = sort;
   c->keep_grids = !recompute_grids;
+  c->use_graphs = graphs;
   {
     const int cells = dim == 2 ? tile * tile : tile * tile * tile;
     if ((scatter == 2 || scatter == 3) && cells != 64) {
@@ -774,34 +870,34 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
       return rc;                    \
     }                               \
   } while (0)
-  TRY(dmalloc(&c->d_scenes, n_scenes));
-  TRY(dmalloc(&c->d_chunks_user, c->n_chunks_user));
-  TRY(dmalloc(&c->d_gblocks, c->n_gblocks));
-  TRY(dmalloc(&c->d_act_id, N));
-  TRY(dmalloc(&c->d_pscene, N));
-  TRY(dmalloc(&c->gm, G));
-  TRY(dmalloc(&c->gp, dim * G));
-  TRY(dmalloc(&c->gv, dim * G));
-  TRY(dmalloc(&c->vbar, dim * G));
-  TRY(dmalloc(&c->pbar, dim * G));
-  TRY(dmalloc(&c->mbar, G));
-  TRY(dmalloc(&c->d_err, 1));
-  TRY(dmalloc(&c->scratch, c->state_floats()));
-  TRY(dmalloc(&c->d_tile_scene, n_tiles));
-  TRY(dmalloc(&c->d_tile_cnt, n_tiles));
-  TRY(dmalloc(&c->d_cell_cnt, n_tiles * cpt));
-  TRY(dmalloc(&c->d_ptile, N));
-  TRY(dmalloc(&c->d_pcell, N));
-  TRY(dmalloc(&c->d_prank, N));
-  TRY(dmalloc(&c->d_tile_start, n_tiles + 1));
-  TRY(dmalloc(&c->d_nch, n_tiles));
-  TRY(dmalloc(&c->d_chunk_start, n_tiles + 1));
-  TRY(dmalloc(&c->d_perm, N));
-  TRY(dmalloc(&c->d_act_sorted, N));
-  TRY(dmalloc(&c->d_chunks_sorted, N / CH + n_tiles + 1));
+  TRY(dmalloc(&c->d_scenes, n_scenes, c->stream));
+  TRY(dmalloc(&c->d_chunks_user, c->n_chunks_user, c->stream));
+  TRY(dmalloc(&c->d_gblocks, c->n_gblocks, c->stream));
+  TRY(dmalloc(&c->d_act_id, N, c->stream));
+  TRY(dmalloc(&c->d_pscene, N, c->stream));
+  TRY(dmalloc(&c->gm, G, c->stream));
+  TRY(dmalloc(&c->gp, dim * G, c->stream));
+  TRY(dmalloc(&c->gv, dim * G, c->stream));
+  TRY(dmalloc(&c->vbar, dim * G, c->stream));
+  TRY(dmalloc(&c->pbar, dim * G, c->stream));
+  TRY(dmalloc(&c->mbar, G, c->stream));
+  TRY(dmalloc(&c->d_err, 1, c->stream));
+  TRY(dmalloc(&c->scratch, c->state_floats(), c->stream));
+  TRY(dmalloc(&c->d_tile_scene, n_tiles, c->stream));
+  TRY(dmalloc(&c->d_tile_cnt, n_tiles, c->stream));
+  TRY(dmalloc(&c->d_cell_cnt, n_tiles * cpt, c->stream));
+  TRY(dmalloc(&c->d_ptile, N, c->stream));
+  TRY(dmalloc(&c->d_pcell, N, c->stream));
+  TRY(dmalloc(&c->d_prank, N, c->stream));
+  TRY(dmalloc(&c->d_tile_start, n_tiles + 1, c->stream));
+  TRY(dmalloc(&c->d_nch, n_tiles, c->stream));
+  TRY(dmalloc(&c->d_chunk_start, n_tiles + 1, c->stream));
+  TRY(dmalloc(&c->d_perm, N, c->stream));
+  TRY(dmalloc(&c->d_act_sorted, N, c->stream));
+  TRY(dmalloc(&c->d_chunks_sorted, N / CH + n_tiles + 1, c->stream));
   {
     const int64_t S = tile + 4;
-    TRY(dmalloc(&c->d_part, n_tiles * (dim + 1) * (dim == 2 ? S * S : S * S * S)));
+    TRY(dmalloc(&c->d_part, n_tiles * (dim + 1) * (dim == 2 ? S * S : S * S * S), c->stream));
   }
   if (n_act > 0) TRY(ensure_gact(c, n_act));
 
@@ -940,7 +1036,7 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   // the step calls leave their grid in gm/gp; rollouts start from zero
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
-  RC(rollout_forward(c, L));
+  RC(run_maybe_graph(c, c->gfwd, graph_key(c), [&] { return rollout_forward(c, L); }));
   const State ST = state_at(c, fwd_slot(c, L, T));
   if (t.sorted) RC(permute_state(c, ms(ST), st(*sT), 1));
   else RC(copy_state(c, ms(ST), st(*sT)));

@@ -749,7 +749,7 @@ struct SortedCell {
 template <int D, int NCH>
 struct SortedCellSmem {
   float box[4][NCH * SortedCell<D>::SV];
-  float rec[256 * SortedCell<D>::REC];
+  float rec[512 * SortedCell<D>::REC];
   int cnt[256];
   int off[256];
   int wsum[4];
@@ -782,6 +782,7 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
                 REC = SC::REC, B = SC::B;
   constexpr int NO = D == 2 ? 9 : 27;
+  constexpr int PER = 2;  // particles prepared per thread and batch
   const int t = threadIdx.x, wave = t >> 6;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
   int org[D];
@@ -791,8 +792,7 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
   float *mybox = sm.box[wave];
   for (int i = t & 63; i < NCH * SV; i += 64) mybox[i] = 0.0f;
   sm.cnt[t] = 0;
-  // this thread's cell in phase 3 (t < NBC): box-cell coordinates
-  int cc[D];
+  int cc[D];  // this thread's box cell in phase 3 (t < NBC)
   {
     int l = t;
 #pragma unroll
@@ -806,52 +806,58 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
   for (int k = 0; k < NO * NCH; ++k) acc[k] = 0.0f;
   unsigned eb = 0;
   __syncthreads();
-  for (int b0 = 0; b0 < cnt; b0 += 256) {
-    // 1. record + cell + rank
-    const int j = b0 + t;
-    int lc = -1, rank = 0;
-    float rec[REC];
-    if (j < cnt) {
+  for (int b0 = 0; b0 < cnt; b0 += PER * 256) {
+    // 1. records, cells and ranks of up to 512 particles
+    int lc[PER], rank[PER];
+    float rec[PER][REC];
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      lc[h] = -1;
+      rank[h] = 0;
+      const int j = b0 + h * 256 + t;
+      if (j >= cnt) continue;
       const int p = start + j;
       float xp[D], f[D], w[D][3], c0[D], L[D][D];
       int base[D];
       load_vec<D>(A.s.x, A.ld, p, xp);
-      if (stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb)) {
-        int l[D];
-        bool inbox = true;
+      if (!(stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb)))
+        continue;
+      int l[D];
+      bool inbox = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        l[a] = base[a] - org[a];
+        inbox = inbox && l[a] >= 0 && l[a] < BC;
+      }
+      if (inbox) {
+        lc[h] = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          l[a] = base[a] - org[a];
-          inbox = inbox && l[a] >= 0 && l[a] < BC;
-        }
-        if (inbox) {
-          lc = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
+          rec[h][a] = f[a];
+          rec[h][D + a] = c0[a];
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            rec[a] = f[a];
-            rec[D + a] = c0[a];
-#pragma unroll
-            for (int b = 0; b < D; ++b) rec[2 * D + a * D + b] = L[a][b];
-          }
-          rank = atomicAdd(&sm.cnt[lc], 1);
-        } else {
-          const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-          scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
-                                       [&](int o0, int o1, int o2, const float *val) {
-            add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
-                                            stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
-          });
+          for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
         }
+        rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
+      } else {
+        const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                     [&](int o0, int o1, int o2, const float *val) {
+          add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
+                                          stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+        });
       }
     }
     __syncthreads();
-    // 2. cell ranges, records to their sorted slots
+    // 2. cell ranges; records to their sorted slots
     block_scan_256(sm.cnt, sm.off, sm.wsum);
     __syncthreads();
-    if (lc >= 0) {
-      float *dst = sm.rec + (sm.off[lc] + rank) * REC;
 #pragma unroll
-      for (int k = 0; k < REC; ++k) dst[k] = rec[k];
+    for (int h = 0; h < PER; ++h) {
+      if (lc[h] < 0) continue;
+      float *dst = sm.rec + (sm.off[lc[h]] + rank[h]) * REC;
+#pragma unroll
+      for (int k = 0; k < REC; ++k) dst[k] = rec[h][k];
     }
     __syncthreads();
     // 3. per-cell accumulation in registers
@@ -884,6 +890,7 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
   // 4. per-wave read-add-write of the accumulators into the wave's box
   if (t < NBC) {
     const int lcell = D == 2 ? cc[0] * S + cc[1] : (cc[0] * S + cc[1]) * S + cc[2];
+    MPM_LDS_ORDER();
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       const int o0 = D == 2 ? o / 3 : o / 9;
@@ -1554,9 +1561,11 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
           node(nd, N, gN, o);
         }
     } else {
+      // rows of the stencil are not unrolled: keeps the kernel at two waves
+      // per SIMD (one row of LDS records in flight instead of all 27)
 #pragma unroll 1
       for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
+#pragma unroll 1
         for (int o1 = 0; o1 < 3; ++o1) {
           const float w01 = w[0][o0] * w[1][o1];
           const float d01 = dw[0][o0] * w[1][o1];

@@ -55,7 +55,7 @@ class Simulator:
 
     def __init__(self, scenes: Sequence[dict], act_id: Optional[np.ndarray] = None,
                  tile: int = 0, sort: bool = True, scatter: int = 0,
-                 recompute_grids: bool = False, stream=None):
+                 recompute_grids: bool = False, graphs: bool = False, stream=None):
         self.L = _lib.lib()
         self.scenes = [dict(s) for s in scenes]
         self.dim = self.scenes[0]["dim"]
@@ -68,6 +68,7 @@ class Simulator:
         opts = _lib.Opts()
         opts.tile, opts.sort, opts.scatter = tile, int(bool(sort)), scatter
         opts.recompute_grids = int(bool(recompute_grids))
+        opts.graphs = int(bool(graphs))
         self.ctx = ctypes.c_void_p()
         self._stream = stream
         check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,

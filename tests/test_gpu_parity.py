@@ -194,6 +194,36 @@ def test_rollout_then_step_then_backward(recompute_grids):
     assert rel_err(to_np(g0b)[0], to_np(g0)[0]) < 1e-6
 
 
+def test_graph_replays_match_eager():
+    """Rollouts replayed from captured hipGraphs, several times, with eager
+    work and synchronisations between replays, each checked against the
+    eager context and the oracle."""
+    sc = S.config_1b()
+    T, k = 30, 8
+    acts32 = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    N = sc.n_particles
+    gT = [np.random.default_rng(8).normal(size=(2, N)).astype(np.float32) / N,
+          np.zeros((2, N), np.float32), np.zeros((4, N), np.float32), np.zeros((4, N), np.float32)]
+    refT, ref0, _ = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                   acts32.astype(np.float64), f64(gT))
+    eager = sim_for(sc, graphs=False)
+    graph = sim_for(sc, graphs=True)
+    act = torch.tensor(acts32, device="cuda")
+    for rep in range(4):
+        say("graph replay", rep)
+        e = eager.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
+        g = graph.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
+        graph.step_forward(to_gpu(sc.state), torch.ones(sc.n_act, device="cuda"))
+        torch.cuda.synchronize()
+        eager.sync_errors()
+        graph.sync_errors()
+        for a, b in zip(to_np(g[0]) + to_np(g[1]), to_np(e[0]) + to_np(e[1])):
+            assert rel_err(a, b) < 1e-6
+        assert rel_err(g[2].cpu().numpy(), e[2].cpu().numpy()) < 1e-6
+        assert rel_err(to_np(g[0])[0], refT[0]) < POS_TOL
+        assert rel_err(to_np(g[1])[1], ref0[1]) < GRAD_TOL
+
+
 def test_rollout_3d_box_contact():
     # a 3D block dropped onto the floor: wall contact within the rollout
     sc = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=31)
@@ -228,6 +258,37 @@ def test_batched_scenes_match_per_scene_oracle():
         for k in range(4):
             assert rel_err(out[k][:, off:off + s.n_particles], ref[k]) < STEP_TOL
         off += s.n_particles
+
+
+def test_batched_config4_spot_check():
+    """The 64-scene batched workload in one context; 4 seeded scenes checked
+    against the oracle (forward + reverse over 20 substeps)."""
+    scs = S.config_4()
+    pick = [int(i) for i in np.random.default_rng(1814).choice(len(scs), 4, replace=False)]
+    T = 20
+    say("batched_c4", sum(s.n_particles for s in scs), pick)
+    acts = [oracle.act_bank_fwd(T, s.dt, s.freq, s.amp, s.phase).astype(np.float32) for s in scs]
+    act = torch.tensor(np.concatenate(acts, axis=1), device="cuda")
+    Ntot = sum(s.n_particles for s in scs)
+    rng = np.random.default_rng(5)
+    gT = [rng.normal(size=(2, Ntot)).astype(np.float32) / 1000, np.zeros((2, Ntot), np.float32),
+          np.zeros((4, Ntot), np.float32), np.zeros((4, Ntot), np.float32)]
+    sim = sim_for(scs)
+    sT, g0, gact = sim.rollout(to_gpu(concat_state(scs)), act, T, ckpt_k=8, gT=to_gpu(gT))
+    sim.sync_errors()
+    sT, g0, gact = to_np(sT), to_np(g0), gact.cpu().numpy()
+    offs = np.cumsum([0] + [s.n_particles for s in scs])
+    aoffs = np.cumsum([0] + [s.n_act for s in scs])
+    for i in pick:
+        s = scs[i]
+        sl = slice(offs[i], offs[i + 1])
+        refT, ref0, ref_act = oracle.rollout(oscene(s), f64(s.state), T, s.act_id,
+                                             acts[i].astype(np.float64),
+                                             tuple(np.asarray(a[:, sl], np.float64) for a in gT))
+        assert rel_err(sT[0][:, sl], refT[0]) < POS_TOL
+        for c in range(4):
+            assert rel_err(g0[c][:, sl], ref0[c]) < GRAD_TOL, (i, c)
+        assert rel_err(gact[:, aoffs[i]:aoffs[i + 1]], ref_act) < GRAD_TOL
 
 
 def test_empty_scene_in_batch():
