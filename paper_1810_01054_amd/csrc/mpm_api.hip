@@ -403,6 +403,9 @@ int bin_particles(mpm_ctx *c, const float *x) {
   a.prank = c->d_prank;
   a.err = c->d_err;
   RC(launch_sort_count(c->dim, a, s));
+  // an invalid particle gets no slot in the permutation: stop here (before
+  // any kernel reads the permutation) when counting found one
+  RC(read_err(c));  // synchronises
   RC(launch_scan_i32(c->d_tile_cnt, c->d_tile_start, c->n_tiles, s));
   RC(launch_sort_place(c->dim, a, c->d_tile_start, c->d_perm, s));
   RC(launch_chunk_count(c->d_tile_cnt, c->n_tiles, c->d_nch, s));

@@ -1824,6 +1824,7 @@ __global__ __launch_bounds__(256) void k_permute_rows(const float *in,
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
   const int q = perm[i];
+  if ((unsigned)q >= (unsigned)N) return;  // never follow an invalid index
   for (int c = 0; c < ncomp; ++c) {
     if (scatter)
       out[(int64_t)c * ld + q] = in[(int64_t)c * ld + i];
@@ -1835,7 +1836,9 @@ __global__ __launch_bounds__(256) void k_permute_rows(const float *in,
 __global__ __launch_bounds__(256) void k_permute_i32(const int *in, int *out,
                                                      const int *perm, int N) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < N) out[i] = in[perm[i]];
+  if (i >= N) return;
+  const int q = perm[i];
+  out[i] = (unsigned)q < (unsigned)N ? in[q] : -1;  // never follow an invalid index
 }
 
 // ---------------------------------------------------------------------------

@@ -65,7 +65,10 @@ def test_c3_central_fd_on_8_actuation_parameters():
     gradient of the centroid x w.r.t. 8 random actuation parameters against
     central differences in FP32 with h in {1e-2, 3e-3, 1e-3} |theta|; the
     best step of each parameter must agree within 5 % (FP32 forward noise
-    bounds the FD accuracy), and the normwise error over the 8 within 2 %."""
+    bounds the FD accuracy: each parameter's error is allowed 5 % of its own
+    gradient plus 1 % of the largest gradient component, since components far
+    below the largest are under the FP32 FD noise), and the normwise error
+    over the 8 within 2 %."""
     sc = S.config_3()
     T, k = 512, 32
     say("c3 fd", sc.n_particles)
@@ -92,6 +95,7 @@ def test_c3_central_fd_on_8_actuation_parameters():
         return float(out[0][0].double().mean())
 
     fd, an = [], []
+    scale = float(np.abs(grad[pick]).max())
     for i in pick:
         best = None
         for hr in (1e-2, 3e-3, 1e-3):
@@ -100,11 +104,11 @@ def test_c3_central_fd_on_8_actuation_parameters():
             tp[i] += h
             tm[i] -= h
             d = (loss_at(tp) - loss_at(tm)) / (2 * h)
-            err = abs(d - grad[i]) / max(abs(grad[i]), 1e-12)
+            err = abs(d - grad[i])
             if best is None or err < best[0]:
                 best = (err, d)
-        say("param", int(i), "autograd", grad[i], "fd", best[1], "rel", best[0])
+        say("param", int(i), "autograd", grad[i], "fd", best[1], "abs err", best[0])
         fd.append(best[1])
         an.append(grad[i])
-        assert best[0] < 5e-2, (int(i), grad[i], best[1])
+        assert best[0] <= 5e-2 * abs(grad[i]) + 1e-2 * scale, (int(i), grad[i], best[1])
     assert rel_err(np.array(an), np.array(fd)) < 2e-2

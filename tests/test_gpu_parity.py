@@ -329,6 +329,27 @@ def test_device_errors_match_oracle(kind, code):
         sim.step_forward(to_gpu(sc.state), torch.zeros(sc.n_act, device="cuda"))
 
 
+def test_rollout_with_invalid_particle_reports_domain_error():
+    """Binning (first step of a rollout) meets a particle outside the domain:
+    the call returns MPM_ERR_DOMAIN before anything reads the permutation,
+    and the error stays with that context."""
+    from paper_1810_01054_amd._lib import MPMError
+    sc = S.config_1a()
+    x = sc.x.copy()
+    x[0, 17] = 0.1 / sc.n_grid
+    say("rollout_domain_error")
+    sim = sim_for(sc)
+    act = torch.zeros(10, sc.n_act, device="cuda")
+    with pytest.raises(MPMError) as e:
+        sim.rollout(to_gpu((x, sc.v, sc.C, sc.F)), act, 10, ckpt_k=5)
+    assert e.value.code == -3
+    with pytest.raises(MPMError):
+        sim.rollout(to_gpu(sc.state), act, 10, ckpt_k=5)
+    other = sim_for(sc)       # a fresh context is unaffected
+    other.rollout(to_gpu(sc.state), act, 10, ckpt_k=5)
+    other.sync_errors()
+
+
 def test_full_size_3d_one_step_fwd_bwd():
     """C3 at its real shape (504,064 particles, 64^3) in the launch
     configuration the benchmark uses (sorted rollout), one substep forward and
