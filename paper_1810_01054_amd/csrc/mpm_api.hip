@@ -39,11 +39,11 @@ struct mpm_ctx {
 
   // captured inner loops of rollouts (forward, reverse)
   struct GraphKey {
-    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0;
+    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0;
     const void *p[8] = {};
     bool operator==(const GraphKey &o) const {
       if (T != o.T || k != o.k || memo != o.memo || grids_all != o.grids_all ||
-          sorted != o.sorted || nch != o.nch)
+          sorted != o.sorted || nch != o.nch || nne != o.nne)
         return false;
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
@@ -90,6 +90,8 @@ struct mpm_ctx {
   Chunk *d_chunks_sorted = nullptr;
   int n_chunks_sorted = 0;
   float *d_part = nullptr;   // tile boxes [n_tiles][d+1][S^d]
+  int *d_tile_flag = nullptr, *d_tile_pos = nullptr, *d_tile_list = nullptr;
+  int n_tiles_ne = 0;        // non-empty tiles (binned rollouts)
 
   // tape
   struct Tape {
@@ -236,6 +238,7 @@ TileInfo tile_info(mpm_ctx *c) {
   t.scene = c->d_tile_scene;
   t.part = c->d_part;
   t.B = c->tile;
+  t.list = c->d_tile_list;
   return t;
 }
 
@@ -258,7 +261,8 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   a.tiles = tile_info(c);
   ProfScope ps(c, MPM_K_P2G);
   if (tiles && c->scatter_mode == 3)
-    return launch_p2g_sorted(c->dim, a, c->n_tiles, c->stream);
+    return launch_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
+  a.tiles.list = nullptr;  // the other binned modes launch one block per tile
   if (tiles && c->scatter_mode == 2)
     return launch_p2g_cell(c->dim, a, c->d_cell_cnt, c->n_tiles, c->stream);
   if (tiles) return launch_p2g_tile(c->dim, a, c->n_tiles, c->stream);
@@ -326,11 +330,14 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   {
     ProfScope ps(c, MPM_K_ADJ_SCATTER);
     if (tiles && c->scatter_mode == 3)
-      RC(launch_adj_scatter_sorted(c->dim, r1, c->n_tiles, c->stream));
-    else if (tiles && c->scatter_mode == 2)
-      RC(launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream));
-    else if (tiles) RC(launch_adj_scatter_tile(c->dim, r1, c->n_tiles, c->stream));
-    else RC(launch_adj_scatter(c->dim, r1, c->stream));
+      RC(launch_adj_scatter_sorted(c->dim, r1, c->n_tiles_ne, c->stream));
+    else {
+      r1.tiles.list = nullptr;
+      if (tiles && c->scatter_mode == 2)
+        RC(launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream));
+      else if (tiles) RC(launch_adj_scatter_tile(c->dim, r1, c->n_tiles, c->stream));
+      else RC(launch_adj_scatter(c->dim, r1, c->stream));
+    }
   }
 
   AdjGridArgs r2;
@@ -413,11 +420,17 @@ int bin_particles(mpm_ctx *c, const float *x) {
   RC(launch_build_chunks(c->d_tile_cnt, c->d_tile_start, c->d_chunk_start,
                          c->d_tile_scene, c->n_tiles, c->d_chunks_sorted, s));
   RC(launch_permute_i32(c->d_act_id, c->d_act_sorted, c->d_perm, (int)c->N, s));
-  int nch = 0;
+  RC(launch_nonempty_flag(c->d_tile_cnt, c->n_tiles, c->d_tile_flag, s));
+  RC(launch_scan_i32(c->d_tile_flag, c->d_tile_pos, c->n_tiles, s));
+  RC(launch_compact(c->d_tile_flag, c->d_tile_pos, c->n_tiles, c->d_tile_list, s));
+  int nch = 0, nne = 0;
   RC(hip_ok(hipMemcpyAsync(&nch, c->d_chunk_start + c->n_tiles, sizeof(int),
+                           hipMemcpyDeviceToHost, s)));
+  RC(hip_ok(hipMemcpyAsync(&nne, c->d_tile_pos + c->n_tiles, sizeof(int),
                            hipMemcpyDeviceToHost, s)));
   RC(read_err(c));  // synchronises
   c->n_chunks_sorted = nch;
+  c->n_tiles_ne = nne;
   return MPM_OK;
 }
 
@@ -461,6 +474,8 @@ int ensure_tape(mpm_ctx *c, int64_t states, int64_t grids, int64_t act) {
     dfree(t.grids, c->stream);
     t.grid_cap = 0;
     RC(dmalloc(&t.grids, grids * gf, c->stream));
+    // grid kernels skip nodes no particle reached; those keep these zeros
+    RC(launch_fill_f32(t.grids, grids * gf, c->stream));
     t.grid_cap = grids;
   }
   if (act > t.act_cap) {
@@ -558,6 +573,7 @@ mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
   int nch = 0;
   k.p[6] = cur_chunks(c, &nch);
   k.nch = nch;
+  k.nne = c->n_tiles_ne;
   k.p[0] = t.states;
   k.p[1] = t.grids;
   k.p[2] = t.act;
@@ -717,6 +733,9 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_act_sorted, c->stream);
   dfree(c->d_chunks_sorted, c->stream);
   dfree(c->d_part, c->stream);
+  dfree(c->d_tile_flag, c->stream);
+  dfree(c->d_tile_pos, c->stream);
+  dfree(c->d_tile_list, c->stream);
   dfree(c->tape.states, c->stream);
   dfree(c->tape.grids, c->stream);
   dfree(c->tape.act, c->stream);
@@ -898,6 +917,9 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   TRY(dmalloc(&c->d_perm, N, c->stream));
   TRY(dmalloc(&c->d_act_sorted, N, c->stream));
   TRY(dmalloc(&c->d_chunks_sorted, N / CH + n_tiles + 1, c->stream));
+  TRY(dmalloc(&c->d_tile_flag, n_tiles, c->stream));
+  TRY(dmalloc(&c->d_tile_pos, n_tiles + 1, c->stream));
+  TRY(dmalloc(&c->d_tile_list, n_tiles, c->stream));
   {
     const int64_t S = tile + 4;
     TRY(dmalloc(&c->d_part, n_tiles * (dim + 1) * (dim == 2 ? S * S : S * S * S), c->stream));
@@ -923,6 +945,8 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   TRY(launch_fill_f32(c->gp, dim * G, s));
   TRY(launch_fill_f32(c->gv, dim * G, s));
   TRY(launch_fill_f32(c->vbar, dim * G, s));
+  TRY(launch_fill_f32(c->pbar, dim * G, s));
+  TRY(launch_fill_f32(c->mbar, G, s));
   TRY(launch_fill_i32((int *)c->d_err, 1, s));
   TRY(hip_ok(hipStreamSynchronize(s)));
 #undef TRY

@@ -78,6 +78,7 @@ struct TileInfo {
   const int *scene;  // scene of each tile
   float *part;       // partial boxes [n_tiles][d+1][S^d]
   int B;             // cells per tile edge
+  const int *list;   // non-null: workgroup b handles tile list[b] (non-empty tiles)
 };
 
 struct P2GArgs {
@@ -190,8 +191,9 @@ int launch_adj_scatter_cell(int dim, const AdjScatterArgs &a,
                             const int *cell_cnt, int n_tiles, hipStream_t st);
 // Sorted per-cell variants (same tiles): each launch re-sorts a tile's
 // particles by their current cell in LDS, so drift does not matter.
-int launch_p2g_sorted(int dim, const P2GArgs &a, int n_tiles, hipStream_t st);
-int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_tiles,
+// n_blocks: number of tiles in a.tiles.list (or all tiles when it is null).
+int launch_p2g_sorted(int dim, const P2GArgs &a, int n_blocks, hipStream_t st);
+int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_blocks,
                               hipStream_t st);
 // Tile edges (cells) with compiled kernels for each dimension.
 bool tile_supported(int dim, int B);
@@ -212,6 +214,11 @@ int launch_sort_place(int dim, const SortArgs &a, const int *tile_start,
                       int *perm, hipStream_t st);
 int launch_chunk_count(const int *tile_cnt, int n_tiles, int *nch,
                        hipStream_t st);
+// flag[i] = tile_cnt[i] > 0; list[pos[i]] = i for flagged tiles.
+int launch_nonempty_flag(const int *tile_cnt, int n_tiles, int *flag,
+                         hipStream_t st);
+int launch_compact(const int *flag, const int *pos, int n_tiles, int *list,
+                   hipStream_t st);
 int launch_build_chunks(const int *tile_cnt, const int *tile_start,
                         const int *chunk_start, const int *tile_scene,
                         int n_tiles, Chunk *chunks, hipStream_t st);

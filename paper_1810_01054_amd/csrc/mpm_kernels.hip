@@ -915,7 +915,7 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
 template <int D>
 __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
   __shared__ SortedCellSmem<D, D + 1> sm;
-  const int tile = blockIdx.x;
+  const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   sorted_cell_scatter<D, D + 1, true>(
       A, tile, sm, A.gm, A.gp,
@@ -929,7 +929,7 @@ __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
   __shared__ SortedCellSmem<D, D> sm;
-  const int tile = blockIdx.x;
+  const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   sorted_cell_scatter<D, D, false>(
       A, tile, sm, nullptr, A.vbar,
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(256) void k_adj_scatter_cell(AdjScatterArgs A,
 // Sum over the tile boxes covering scene-local node `li` (coordinates g) of
 // channels [c_lo, c_lo + NC) into acc.
 template <int D, int B, int NC>
-__device__ __forceinline__ void add_tile_boxes(const DevScene &sc, int li,
+__device__ __forceinline__ bool add_tile_boxes(const DevScene &sc, int li,
                                                const int *tile_cnt,
                                                const float *part, int nch,
                                                int c_lo, float *acc) {
@@ -1003,11 +1003,13 @@ __device__ __forceinline__ void add_tile_boxes(const DevScene &sc, int li,
     thi[a] = min((g[a] + 1) / B, sc.nt - 1);
     tlo[a] = g[a] >= 3 ? (g[a] - 3) / B : 0;
   }
+  bool covered = false;
   if constexpr (D == 2) {
     for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
       for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
         const int tile = sc.tile_off + t0 * sc.nt + t1;
         if (tile_cnt[tile] == 0) continue;
+        covered = true;
         const int l = (g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1));
         const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
 #pragma unroll
@@ -1019,6 +1021,7 @@ __device__ __forceinline__ void add_tile_boxes(const DevScene &sc, int li,
         for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
           const int tile = sc.tile_off + (t0 * sc.nt + t1) * sc.nt + t2;
           if (tile_cnt[tile] == 0) continue;
+          covered = true;
           const int l = ((g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1))) * S +
                         (g[2] - (t2 * B - 1));
           const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
@@ -1026,19 +1029,21 @@ __device__ __forceinline__ void add_tile_boxes(const DevScene &sc, int li,
           for (int c = 0; c < NC; ++c) acc[c] += bx[c * SV];
         }
   }
+  return covered;
 }
 
+// Returns whether any non-empty tile's box covers the node.
 template <int D, int NC>
-__device__ __forceinline__ void add_tile_boxes_any(int B, const DevScene &sc,
+__device__ __forceinline__ bool add_tile_boxes_any(int B, const DevScene &sc,
                                                    int li, const int *tile_cnt,
                                                    const float *part, int nch,
                                                    int c_lo, float *acc) {
   if constexpr (D == 2) {
-    if (B == 8) add_tile_boxes<2, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
-    else add_tile_boxes<2, 16, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    if (B == 8) return add_tile_boxes<2, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    return add_tile_boxes<2, 16, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
   } else {
-    if (B == 4) add_tile_boxes<3, 4, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
-    else add_tile_boxes<3, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    if (B == 4) return add_tile_boxes<3, 4, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
+    return add_tile_boxes<3, 8, NC>(sc, li, tile_cnt, part, nch, c_lo, acc);
   }
 }
 
@@ -1085,7 +1090,13 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
 #pragma unroll
   for (int a = 0; a < D; ++a) mp[1 + a] = A.gp[a * A.G + gi];
   const bool direct = mp[0] != 0.0f;
-  if (A.part) add_tile_boxes_any<D, D + 1>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, mp);
+  if (A.part) {
+    const bool covered =
+        add_tile_boxes_any<D, D + 1>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, mp);
+    // a node that no particle reached keeps m = p = 0 and is never read with
+    // a non-zero weight: skip it (its buffers hold finite earlier values)
+    if (!covered && !direct) return;
+  }
   float v[D];
   node_velocity<D>(sc, li, mp[0], mp + 1, v);
 #pragma unroll
@@ -1388,7 +1399,11 @@ __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
     vb[a] = A.vbar[a * A.G + gi];
     nz = nz || vb[a] != 0.0f;
   }
-  if (A.part) add_tile_boxes_any<D, D>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, vb);
+  if (A.part) {
+    const bool covered =
+        add_tile_boxes_any<D, D>(A.B, sc, li, A.tile_cnt, A.part, D + 1, 0, vb);
+    if (!covered && !nz && !(m > 0.0f)) return;  // untouched node (see k_grid)
+  }
   float mb = 0.0f;
   if (m > 0.0f) {
     const float im = 1.0f / m;
@@ -1773,6 +1788,18 @@ __global__ __launch_bounds__(256) void k_chunk_count(const int *tile_cnt,
   if (i < n) nch[i] = (tile_cnt[i] + CH - 1) / CH;
 }
 
+__global__ __launch_bounds__(256) void k_nonempty_flag(const int *tile_cnt,
+                                                       int n, int *flag) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) flag[i] = tile_cnt[i] > 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_compact(const int *flag, const int *pos,
+                                                 int n, int *list) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && flag[i]) list[pos[i]] = i;
+}
+
 __global__ __launch_bounds__(256) void k_build_chunks(
     const int *tile_cnt, const int *tile_start, const int *chunk_start,
     const int *tile_scene, int n, Chunk *chunks) {
@@ -2042,6 +2069,15 @@ int launch_sort_place(int dim, const SortArgs &a, const int *tile_start,
 
 int launch_chunk_count(const int *tile_cnt, int n, int *nch, hipStream_t st) {
   MPM_LAUNCH(k_chunk_count, blocks_for(n), 256, st, tile_cnt, n, nch);
+}
+
+int launch_nonempty_flag(const int *tile_cnt, int n, int *flag, hipStream_t st) {
+  MPM_LAUNCH(k_nonempty_flag, blocks_for(n), 256, st, tile_cnt, n, flag);
+}
+
+int launch_compact(const int *flag, const int *pos, int n, int *list,
+                   hipStream_t st) {
+  MPM_LAUNCH(k_compact, blocks_for(n), 256, st, flag, pos, n, list);
 }
 
 int launch_build_chunks(const int *tile_cnt, const int *tile_start,
