@@ -46,6 +46,37 @@ def kernel_bytes_per_node(kernel: str, d: int) -> int:
             "adj_grid": 4 + 4 * d + 4 * d + 4 * d + 4 + 4 * d}[kernel]  # m, p, vbar in; pbar, mbar, v out
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "c3_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_01054_amd", "csrc", f)
+                  for f in ("mpm_kernels.hip", "mpm_internal.h")]
+
+
+def kernels_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str):
+    """Measured HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE
+    counters, scaled by the same counters' reading on a plain copy of known
+    size) from the committed counter summary; None when there is none or the
+    kernel sources changed since the counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel sources sha256: `([0-9a-f]{64})`", text)
+    if not m or m.group(1) != kernels_sha256():
+        return None
+    m = re.search(r"^\| k_%s\S* \|(?:[^|]*\|){3} *([0-9.]+) *\|" % re.escape(kernel), text, re.M)
+    return float(m.group(1)) if m else None
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -75,6 +106,35 @@ def cpu_baseline(sc, T_sample: int):
             "sample": f"{sc.name}: {sc.n_particles} particles, first {T_sample} "
                       f"substeps forward + reverse (memo), FP64, one thread, "
                       f"{dt:.1f} s"}
+
+
+def run_copy(args):
+    """Calibration workload for the HBM byte counters: an elementwise copy
+    (x 1.0) of --copy-mib MiB, device to device; reads and writes exactly
+    that many bytes per launch."""
+    import torch
+    n = args.copy_mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(max(args.warmup, 1)):
+        torch.mul(src, 1.0, out=dst)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(args.steps):
+        torch.mul(src, 1.0, out=dst)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / args.steps
+    nbytes = 2 * n * 4
+    print(json.dumps({"metric": "device copy bandwidth (read + write)",
+                      "value": round(nbytes / sec / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"elementwise copy of {args.copy_mib} MiB",
+                                 "bytes_read": n * 4, "bytes_written": n * 4}}), flush=True)
 
 
 def run_batched(args):
@@ -217,9 +277,11 @@ def main():
     ap.add_argument("--scatter", type=int, default=0,
                     help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
                          "2 per-cell in bin order, 3 per-cell after an LDS sort")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "copy"],
                     help="c3: 3D quadruped (headline); c4: 64 batched 2D scenes; "
-                         "c5: serving a Poisson request mix")
+                         "c5: serving a Poisson request mix; copy: plain device copy "
+                         "(calibrates the HBM byte counters)")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--requests", type=int, default=60, help="c5: requests per load point")
     ap.add_argument("--slots", type=int, default=8, help="c5: concurrent requests")
     ap.add_argument("--no-profile", action="store_true",
@@ -248,6 +310,8 @@ def main():
         return run_batched(args)
     if args.workload == "c5":
         return run_serving(args)
+    if args.workload == "copy":
+        return run_copy(args)
 
     sc = S.config_3()
     T, k = args.T, args.ckpt
@@ -308,9 +372,11 @@ def main():
         else:
             bpu, units = kernel_bytes_per_particle(dominant, d), N
         achieved = bpu * units / avg_s / 1e9
+        traffic = recorded_traffic(dominant)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "kernel": dominant,
+                "traffic": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+                "traffic_bytes_per_launch": traffic, "kernel": dominant,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": n_launch,
                 "bytes_per_unit": bpu, "units_per_launch": units}
 

@@ -1157,9 +1157,9 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
     __syncthreads();
   }
   if (!active) return;
-  float F[D * D];
-  load_mat<D>(A.s.F, A.ld, p, F);
   if (!ok) {
+    float F[D * D];
+    load_mat<D>(A.s.F, A.ld, p, F);
     // keep the output defined (the call reports the error)
     float z[D * D] = {};
     store_vec<D>(A.out.x, A.ld, p, xp);
@@ -1200,7 +1200,9 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
         }
       }
   } else {
-#pragma unroll
+    // the outer stencil row stays a loop: nine LDS records in flight instead
+    // of 27 keeps the kernel at five waves per SIMD
+#pragma unroll 1
     for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll
       for (int o1 = 0; o1 < 3; ++o1) {
@@ -1230,6 +1232,9 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
         }
       }
   }
+  // F is loaded after the stencil loop so it is not live across it
+  float F[D * D];
+  load_mat<D>(A.s.F, A.ld, p, F);
   // C' = (4/dx^2) sum N v_i (x_i - x_p)^T,  (x_i - x_p) = (o - f) dx
   const float cs = sc.Dinv * sc.dx;
   float Cn[D * D], Fn[D * D], xn[D];
@@ -1459,10 +1464,14 @@ __device__ __forceinline__ AdjNode adj_node_global(const AdjGatherArgs &A,
   return r;
 }
 
+// Launched for three waves per SIMD (at most 168 VGPRs): with F and dL/dF
+// parked in LDS across the stencil loop the 3D kernel fits without spills.
 template <int D>
-__global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
+__global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   __shared__ AdjNode s_n[LDS_NODES];
   __shared__ double s_act[LDS_ACT];
+  // F^n and dL/dF^{n+1} of each thread, kept for the post-loop algebra
+  __shared__ float s_keep[D == 3 ? 2 * D * D * CH : 1];
   const Chunk ch = A.chunks[chunk_id()];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
@@ -1493,9 +1502,9 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
     const float s_act = j_act >= 0 ? A.act[sc.act_off + j_act] : 0.0f;
     // --- quantities live across the stencil loop -------------------------
     float w[D][3], dw[D][3];
-    float cC[D], Cdx[D][D];  // (4/dx^2)-free C-tilde (x_i - x_p) = cC + Cdx o
+    // vt + (4/dx^2) Ct (x_i - x_p) = cV + CdxD o  (v-term and C-term of (J))
+    float cV[D], CdxD[D][D];
     float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
-    float vt[D];
     {
       float v[D], C[D * D], F[D * D];
       load_vec<D>(A.s.v, A.ld, p, v);
@@ -1510,22 +1519,28 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
       load_vec<D>(A.g1.v, A.ld, p, gv1);
       load_mat<D>(A.g1.C, A.ld, p, gC1);
       load_mat<D>(A.g1.F, A.ld, p, gF1);
+      if constexpr (D == 3) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) vt[a] = gv1[a] + sc.dt * gx1[a];  // (A)
+        for (int q = 0; q < D * D; ++q) {
+          s_keep[q * CH + t] = F[q];
+          s_keep[(D * D + q) * CH + t] = gF1[q];
+        }
+      }
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        float s1 = 0.0f, s2 = sc.mp * v[a];
+        float s1 = gv1[a] + sc.dt * gx1[a];  // (A) vt
+        float s2 = sc.mp * v[a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
           float ct = 0.0f;  // (B) Ct = gC1 + dt gF1 F^T
 #pragma unroll
           for (int g = 0; g < D; ++g) ct += gF1[a * D + g] * F[b * D + g];
-          Cdx[a][b] = (gC1[a * D + b] + sc.dt * ct) * sc.dx;
+          CdxD[a][b] = (gC1[a * D + b] + sc.dt * ct) * (sc.dx * sc.Dinv);
           Gdx[a][b] = G[a * D + b] * sc.dx;
-          s1 -= Cdx[a][b] * f[b];
+          s1 -= CdxD[a][b] * f[b];
           s2 -= Gdx[a][b] * f[b];
         }
-        cC[a] = s1;
+        cV[a] = s1;
         cq[a] = s2;
       }
     }
@@ -1534,6 +1549,7 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
       bspline_w(f[a], w[a]);
       bspline_dw(f[a], sc.inv_dx, dw[a]);
     }
+    // Go = sum N p_i o^T (dL/dG = (Go - Spb f^T) dx after the loop)
     float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {};
     load_vec<D>(A.g1.x, A.ld, p, xb);  // (J) direct term dL/dx^{n+1}
     const int lbase = box.lds ? box_index<D>(box, base) : 0;
@@ -1545,19 +1561,19 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
       float s_all = sc.mp * nd.a.w;  // (J) m-term
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        float Cd = cC[a], q = cq[a];
+        float cv = cV[a], q = cq[a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-          Cd += Cdx[a][b] * o[b];
+          cv += CdxD[a][b] * o[b];
           q += Gdx[a][b] * o[b];
         }
-        // (J) v-term, C-term (N part), p-term (N part)
-        s_all += vt[a] * vi[a] + sc.Dinv * vi[a] * Cd + pb[a] * q;
+        // (J) v-term and C-term (N parts), p-term (N part)
+        s_all += vi[a] * cv + pb[a] * q;
         const float Npb = N * pb[a];
         Spb[a] += Npb;       // (F), and the delta part of the (J) p-term
         Sv[a] += N * vi[a];  // delta part of the (J) C-term
 #pragma unroll
-        for (int b = 0; b < D; ++b) Gb[a * D + b] += Npb * (o[b] - f[b]);
+        for (int b = 0; b < D; ++b) Gb[a * D + b] += Npb * o[b];
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
@@ -1576,8 +1592,8 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
           node(nd, N, gN, o);
         }
     } else {
-      // rows of the stencil are not unrolled: keeps the kernel at two waves
-      // per SIMD (one row of LDS records in flight instead of all 27)
+      // rows of the stencil are not unrolled: one row of LDS records in
+      // flight instead of all 27 keeps the register count near the bound
 #pragma unroll 1
       for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll 1
@@ -1604,16 +1620,29 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
       float s = 0.0f;
 #pragma unroll
       for (int a = 0; a < D; ++a)
-        s += sc.Dinv * Cdx[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
+        s += CdxD[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
       xb[c] -= s * sc.inv_dx;
     }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) Gb[a * D + b] -= Spb[a] * f[b];
     // --- after the loop: reload F and dL/dF^{n+1}, recompute the stress ----
     // (the compiler barrier keeps the pre-loop copies from staying live
-    // across the stencil loop: reloading is cheaper than the registers)
+    // across the stencil loop; in 3D they come back from the thread's LDS
+    // slots instead of a second HBM read)
     asm volatile("" ::: "memory");
     float F[D * D], gF1[D * D], C1[D * D];
-    load_mat<D>(A.s.F, A.ld, p, F);
-    load_mat<D>(A.g1.F, A.ld, p, gF1);
+    if constexpr (D == 3) {
+#pragma unroll
+      for (int q = 0; q < D * D; ++q) {
+        F[q] = s_keep[q * CH + t];
+        gF1[q] = s_keep[(D * D + q) * CH + t];
+      }
+    } else {
+      load_mat<D>(A.s.F, A.ld, p, F);
+      load_mat<D>(A.g1.F, A.ld, p, gF1);
+    }
     load_mat<D>(A.C1, A.ld, p, C1);
     Stress<D> S;
     unsigned eb2 = 0;
@@ -1625,6 +1654,14 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
     for (int k = 0; k < D * D; ++k) {
       Gb[k] *= sc.dx;         // dL/dG = sum N p_i (x_i - x_p)^T
       Cb[k] = sc.mp * Gb[k];  // (I)
+    }
+    // x, v and C adjoints are final: store them now (frees their registers)
+    if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D)))
+      eb |= EB_NONFINITE;
+    if (ok) {
+      store_vec<D>(A.g0.x, A.ld, p, xb);
+      store_vec<D>(A.g0.v, A.ld, p, vb);
+      store_mat<D>(A.g0.C, A.ld, p, Cb);
     }
     // (G) dL/dP_t = kG dL/dG F
 #pragma unroll
@@ -1690,15 +1727,8 @@ __global__ __launch_bounds__(CH) void k_adj_gather(AdjGatherArgs A) {
         sb_act += sc.axis[a] * s;
       }
     }
-    if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D) &&
-          finite_all(Fb, D * D)))
-      eb |= EB_NONFINITE;
-    if (ok) {
-      store_vec<D>(A.g0.x, A.ld, p, xb);
-      store_vec<D>(A.g0.v, A.ld, p, vb);
-      store_mat<D>(A.g0.C, A.ld, p, Cb);
-      store_mat<D>(A.g0.F, A.ld, p, Fb);
-    }
+    if (!finite_all(Fb, D * D)) eb |= EB_NONFINITE;
+    if (ok) store_mat<D>(A.g0.F, A.ld, p, Fb);
   }
   if (active && !ok) {
     float z[D * D] = {};
