@@ -724,18 +724,25 @@ __device__ __forceinline__ void cell_scatter_wave(const Args &A,
 }
 
 // Sorted per-cell scatter (drift-proof).  One workgroup (4 waves) per tile.
-// The tile's particles are processed in batches of 256 (one per thread):
-//  1. each thread computes its particle's affine stencil record (f, c0, L)
-//     and its current cell in the tile box's (B+2)^d cell grid (one cell of
-//     drift per side), and takes a rank in that cell (integer LDS atomic);
+// The tile's particles are processed in batches of 256 PER (PER per thread):
+//  1. each thread computes its particles' affine stencil records (f, c0, L)
+//     and their current cells in the tile box's (B+2)^d cell grid (one cell
+//     of drift per side), and takes a rank in each cell (integer LDS atomic);
 //  2. an exclusive scan over the cells gives each cell a range; each thread
-//     stores its record at its cell's range + rank;
-//  3. thread c (< (B+2)^d) walks cell c's records and accumulates the
-//     3^d x NCH contributions in registers (one stencil base per cell).
-// After the last batch each wave adds its lanes' accumulators into its own
-// LDS box (plain read-add-write: for a fixed offset a wave's lanes touch
-// distinct nodes), the four boxes are summed and the tile box is stored.
-// Particles outside the slack ring add to the grid with global atomics.
+//     stores its records at their cell's range + rank;
+//  3. lane l of every wave takes one cell (the B^d cells of the tile itself
+//     first, then the occupied cells of the drift ring), and wave w the
+//     stencil offsets q = w, w+4, w+8, ... of all the cell's records.  A lane
+//     sums its share in registers (one stencil base per cell), then the
+//     waves, one after the other, add their sums into the tile's LDS box with
+//     plain read-add-write (for a fixed offset the lanes of a wave touch
+//     distinct nodes, and LDS executes a wave's accesses in issue order).
+//     LDS float atomics run an order of magnitude slower here; splitting the
+//     offsets over the waves keeps the accumulators at a quarter of the
+//     stencil and the read-add-write chains short.  Used in 3D.
+// At the end the box is stored.  Particles outside the slack ring add to the
+// grid with global atomics.  V4 keeps a box node's channels together (one
+// 16-byte LDS access per node and offset) instead of one plane per channel.
 template <int D>
 struct SortedCell {
   static constexpr int B = D == 2 ? 8 : 4;
@@ -743,16 +750,23 @@ struct SortedCell {
   static constexpr int SV = D == 2 ? S * S : S * S * S;
   static constexpr int BC = B + 2;  // box cells per axis
   static constexpr int NBC = D == 2 ? BC * BC : BC * BC * BC;
+  static constexpr int NIN = D == 2 ? B * B : B * B * B;  // the tile's own cells
   static constexpr int REC = D + D + D * D;  // f, c0, L
+  static constexpr int NO = D == 2 ? 9 : 27;  // stencil offsets
+  static constexpr int WS = 4;                 // offset stride of a wave
+  static constexpr int NQ = (NO + WS - 1) / WS;  // offsets per wave (at most)
 };
 
-template <int D, int NCH>
+template <int D, int NCH, int PER, bool V4>
 struct SortedCellSmem {
-  float box[4][NCH * SortedCell<D>::SV];
-  float rec[512 * SortedCell<D>::REC];
+  static constexpr int SV = SortedCell<D>::SV;
+  float box[V4 ? 4 * SV : NCH * SV];
+  float rec[PER * 256 * SortedCell<D>::REC];
   int cnt[256];
   int off[256];
+  short order[256];  // the tile's own cells, then the occupied ring cells
   int wsum[4];
+  int nring;
 };
 
 // Exclusive scan of cnt[0..256) into off (256 threads).
@@ -773,9 +787,270 @@ __device__ __forceinline__ void block_scan_256(const int *cnt, int *off,
   off[t] = pre + x - v;
 }
 
+// Stencil offset q = (o0 * 3 + o1) * 3 + o2 (2D: o0 * 3 + o1).
+template <int D, int Q>
+struct StencilOffset {
+  static constexpr int o0 = D == 2 ? Q / 3 : Q / 9;
+  static constexpr int o1 = D == 2 ? Q % 3 : (Q / 3) % 3;
+  static constexpr int o2 = D == 2 ? 0 : Q % 3;
+};
+
+// One record's contributions at the offsets W, W+WS, ... added into acc.
+template <int D, int NCH, bool HAS_MASS, int W, int J = 0>
+__device__ __forceinline__ void offsets_add(const float (&w)[D][3], float mp,
+                                            const float *c0,
+                                            const float (&L)[D][D],
+                                            float *acc) {
+  constexpr int Q = W + SortedCell<D>::WS * J;
+  if constexpr (Q < SortedCell<D>::NO) {
+    using O = StencilOffset<D, Q>;
+    float N = w[0][O::o0] * w[1][O::o1];
+    if constexpr (D == 3) N *= w[2][O::o2];
+    int ch = 0;
+    if constexpr (HAS_MASS) acc[J * NCH + ch++] += N * mp;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float v = c0[a] + L[a][0] * (float)O::o0 + L[a][1] * (float)O::o1;
+      if constexpr (D == 3) v += L[a][2] * (float)O::o2;
+      acc[J * NCH + ch + a] += N * v;
+    }
+    offsets_add<D, NCH, HAS_MASS, W, J + 1>(w, mp, c0, L, acc);
+  }
+}
+
+// The n records of the cell at r, summed into acc at offsets W, W+4, ...
+template <int D, int NCH, bool HAS_MASS, int W>
+__device__ __forceinline__ void cell_offsets_sum(const float *r, int n,
+                                                 float mp, float *acc) {
+  constexpr int REC = SortedCell<D>::REC;
+  for (int k = 0; k < n; ++k) {
+    const float *rk = r + k * REC;
+    float w[D][3], c0[D], L[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      bspline_w(rk[a], w[a]);
+      c0[a] = rk[D + a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) L[a][b] = rk[2 * D + a * D + b];
+    }
+    offsets_add<D, NCH, HAS_MASS, W>(w, mp, c0, L, acc);
+  }
+}
+
+// Read-add-write of acc (offsets W, W+WS, ...) into the box around lcell.
+template <int D, int NCH, bool V4, int W, int J = 0>
+__device__ __forceinline__ void offsets_flush(float *box, int lcell,
+                                              const float *acc) {
+  constexpr int Q = W + SortedCell<D>::WS * J;
+  if constexpr (Q < SortedCell<D>::NO) {
+    using O = StencilOffset<D, Q>;
+    constexpr int S = SortedCell<D>::S, SV = SortedCell<D>::SV;
+    const int li = D == 2 ? lcell + O::o0 * S + O::o1
+                          : lcell + (O::o0 * S + O::o1) * S + O::o2;
+    if constexpr (V4) {
+      float4 *node = reinterpret_cast<float4 *>(box) + li;
+      float4 cur = *node;
+      cur.x += acc[J * NCH + 0];
+      cur.y += acc[J * NCH + 1];
+      if constexpr (NCH > 2) cur.z += acc[J * NCH + 2];
+      if constexpr (NCH > 3) cur.w += acc[J * NCH + 3];
+      *node = cur;
+    } else {
+      float cur[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) cur[ch] = box[ch * SV + li];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) box[ch * SV + li] = cur[ch] + acc[J * NCH + ch];
+    }
+    MPM_LDS_ORDER();
+    offsets_flush<D, NCH, V4, W, J + 1>(box, lcell, acc);
+  }
+}
+
+template <int D, int NCH, bool HAS_MASS, int PER, bool V4, typename Args,
+          typename Part>
+__device__ __forceinline__ void sorted_cell_scatter(
+    const Args &A, int tile, SortedCellSmem<D, NCH, PER, V4> &sm, float *gm,
+    float *gp, Part &&part) {
+  using SC = SortedCell<D>;
+  constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
+                NIN = SC::NIN, REC = SC::REC, B = SC::B, NQ = SC::NQ;
+  constexpr int BOXF = V4 ? 4 * SV : NCH * SV;  // floats in the box
+  static_assert(!V4 || NCH <= 4, "V4 holds at most four channels");
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  const int cnt = A.tiles.cnt[tile];
+  const int start = A.tiles.start[tile];
+  for (int i = t; i < BOXF; i += 256) sm.box[i] = 0.0f;
+  sm.cnt[t] = 0;
+  // is box cell t one of the tile's own cells (1..B on every axis)?
+  bool own = t < NBC;
+  {
+    int l = t;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      const int c = l % BC;
+      own = own && c >= 1 && c <= B;
+      l /= BC;
+    }
+  }
+  {
+    // the own cells take the first NIN slots of the order, in cell order
+    const unsigned long long bal = __ballot(own);
+    if (lane == 0) sm.wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = __popcll(bal & ((1ull << lane) - 1));
+    for (int w = 0; w < wave; ++w) before += sm.wsum[w];
+    if (own) sm.order[before] = (short)t;
+  }
+  unsigned eb = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < cnt; b0 += PER * 256) {
+    // 1. records, cells and ranks of up to PER particles per thread
+    int lc[PER], rank[PER];
+    float rec[PER][REC];
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      lc[h] = -1;
+      rank[h] = 0;
+      const int j = b0 + h * 256 + t;
+      const int p = start + j;
+      float xp[D], f[D], w[D][3], c0[D], L[D][D];
+      int base[D];
+      bool ok = false;
+      if (j < cnt) {
+        load_vec<D>(A.s.x, A.ld, p, xp);
+        ok = stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb);
+      }
+      if (!ok) continue;
+      int l[D];
+      bool inbox = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        l[a] = base[a] - org[a];
+        inbox = inbox && l[a] >= 0 && l[a] < BC;
+      }
+      if (inbox) {
+        lc[h] = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          rec[h][a] = f[a];
+          rec[h][D + a] = c0[a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
+        }
+        rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
+      } else {
+        const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+                                     [&](int o0, int o1, int o2, const float *val) {
+          add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
+                                          stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+        });
+      }
+    }
+    __syncthreads();
+    // 2. cell ranges; records to their sorted slots; the occupied ring
+    //    cells (particles that drifted out of the tile) after the own cells
+    block_scan_256(sm.cnt, sm.off, sm.wsum);
+    __syncthreads();
+    {
+      const bool ring = t < NBC && !own && sm.cnt[t] > 0;
+      const unsigned long long bal = __ballot(ring);
+      if (lane == 0) sm.wsum[wave] = __popcll(bal);
+      __syncthreads();
+      int before = __popcll(bal & ((1ull << lane) - 1));
+      for (int w = 0; w < wave; ++w) before += sm.wsum[w];
+      if (ring) sm.order[NIN + before] = (short)t;
+      if (t == 0) sm.nring = sm.wsum[0] + sm.wsum[1] + sm.wsum[2] + sm.wsum[3];
+    }
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      if (lc[h] < 0) continue;
+      float *dst = sm.rec + (sm.off[lc[h]] + rank[h]) * REC;
+#pragma unroll
+      for (int k = 0; k < REC; ++k) dst[k] = rec[h][k];
+    }
+    __syncthreads();
+    // 3. per-cell sums of this wave's offsets, then the waves' read-add-write
+    //    into the box, one wave at a time
+    const int nslot = NIN + sm.nring;
+    for (int ps = 0; ps * 64 < nslot; ++ps) {
+      const int slot = ps * 64 + lane;
+      const int c = slot < nslot ? sm.order[slot] : 0;
+      const int n = slot < nslot ? sm.cnt[c] : 0;
+      const float *r = sm.rec + sm.off[c] * REC;
+      float acc[NQ * NCH];
+#pragma unroll
+      for (int k = 0; k < NQ * NCH; ++k) acc[k] = 0.0f;
+      switch (wave) {
+        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0>(r, n, sc.mp, acc); break;
+        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1>(r, n, sc.mp, acc); break;
+        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2>(r, n, sc.mp, acc); break;
+        default: cell_offsets_sum<D, NCH, HAS_MASS, 3>(r, n, sc.mp, acc); break;
+      }
+      int cc[D];
+      {
+        int l = c;
+#pragma unroll
+        for (int a = D - 1; a >= 0; --a) {
+          cc[a] = l % BC;
+          l /= BC;
+        }
+      }
+      const int lcell = D == 2 ? cc[0] * S + cc[1] : (cc[0] * S + cc[1]) * S + cc[2];
+      for (int fw = 0; fw < 4; ++fw) {
+        if (wave == fw && n > 0) {
+          MPM_LDS_ORDER();
+          switch (fw) {
+            case 0: offsets_flush<D, NCH, V4, 0>(sm.box, lcell, acc); break;
+            case 1: offsets_flush<D, NCH, V4, 1>(sm.box, lcell, acc); break;
+            case 2: offsets_flush<D, NCH, V4, 2>(sm.box, lcell, acc); break;
+            default: offsets_flush<D, NCH, V4, 3>(sm.box, lcell, acc); break;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    sm.cnt[t] = 0;
+    __syncthreads();
+  }
+  if (eb) atomicOr(A.err, eb);
+  // 4. store the tile box (one plane per channel)
+  float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
+  if constexpr (V4) {
+    for (int i = t; i < SV; i += 256) {
+      const float4 a = reinterpret_cast<const float4 *>(sm.box)[i];
+      dst[i] = a.x;
+      dst[SV + i] = a.y;
+      if constexpr (NCH > 2) dst[2 * SV + i] = a.z;
+      if constexpr (NCH > 3) dst[3 * SV + i] = a.w;
+    }
+  } else {
+    for (int i = t; i < NCH * SV; i += 256) dst[i] = sm.box[i];
+  }
+}
+
+// 2D variant of the sorted scatter (tiles of 8 x 8 cells, about four
+// particles per cell): records are sorted as above, then thread c takes box
+// cell c and sums all its records at all nine offsets (the 100 box cells
+// keep two waves busy), and each wave adds its lanes' sums into its own LDS
+// box (read-add-write, the four chains run in parallel); the four boxes are
+// summed at the end.  On the 64-scene 2D batch this beats the offset split.
+template <int D, int NCH>
+struct WaveBoxSmem {
+  float box[4][NCH * SortedCell<D>::SV];
+  float rec[512 * SortedCell<D>::REC];
+  int cnt[256];
+  int off[256];
+  int wsum[4];
+};
+
 template <int D, int NCH, bool HAS_MASS, typename Args, typename Part>
-__device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
-                                                    SortedCellSmem<D, NCH> &sm,
+__device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
+                                                       WaveBoxSmem<D, NCH> &sm,
                                                     float *gm, float *gp,
                                                     Part &&part) {
   using SC = SortedCell<D>;
@@ -912,33 +1187,46 @@ __device__ __forceinline__ void sorted_cell_scatter(const Args &A, int tile,
     dst[i] = (sm.box[0][i] + sm.box[1][i]) + (sm.box[2][i] + sm.box[3][i]);
 }
 
+
+// 3D: both scatters take batches of 512 (a full tile in one pass: one sort
+// and one set of read-add-write chains per tile); P2G keeps its four
+// channels node-major, the adjoint scatter's three channels are planes.
+// 2D: the per-wave-box variant above.
 template <int D>
 __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
-  __shared__ SortedCellSmem<D, D + 1> sm;
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
-  sorted_cell_scatter<D, D + 1, true>(
-      A, tile, sm, A.gm, A.gp,
-      [&](int p, const float *xp, const float *f, float (&w)[D][3], float *c0,
-          float (&L)[D][D], unsigned &eb) {
-        const DevScene sc = A.scenes[A.tiles.scene[tile]];
-        return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
-      });
+  auto part = [&](int p, const float *xp, const float *f, float (&w)[D][3],
+                  float *c0, float (&L)[D][D], unsigned &eb) {
+    const DevScene sc = A.scenes[A.tiles.scene[tile]];
+    return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+  };
+  if constexpr (D == 2) {
+    __shared__ WaveBoxSmem<D, D + 1> sm;
+    sorted_cell_scatter_wb<D, D + 1, true>(A, tile, sm, A.gm, A.gp, part);
+  } else {
+    __shared__ SortedCellSmem<D, D + 1, 2, true> sm;
+    sorted_cell_scatter<D, D + 1, true, 2, true>(A, tile, sm, A.gm, A.gp, part);
+  }
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
-  __shared__ SortedCellSmem<D, D> sm;
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
-  sorted_cell_scatter<D, D, false>(
-      A, tile, sm, nullptr, A.vbar,
-      [&](int p, const float *, const float *f, float (&w)[D][3], float *c0,
-          float (&L)[D][D], unsigned &) {
-        const DevScene sc = A.scenes[A.tiles.scene[tile]];
-        adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
-        return true;
-      });
+  auto part = [&](int p, const float *, const float *f, float (&w)[D][3],
+                  float *c0, float (&L)[D][D], unsigned &) {
+    const DevScene sc = A.scenes[A.tiles.scene[tile]];
+    adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+    return true;
+  };
+  if constexpr (D == 2) {
+    __shared__ WaveBoxSmem<D, D> sm;
+    sorted_cell_scatter_wb<D, D, false>(A, tile, sm, nullptr, A.vbar, part);
+  } else {
+    __shared__ SortedCellSmem<D, D, 2, false> sm;
+    sorted_cell_scatter<D, D, false, 2, false>(A, tile, sm, nullptr, A.vbar, part);
+  }
 }
 
 template <int D>
