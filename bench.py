@@ -37,6 +37,7 @@ def kernel_bytes_per_particle(kernel: str, d: int) -> int:
         "g2p": (v + m) + state,                    # x, F in; state out
         "adj_scatter": (v + m) + state,            # x, F, adjoint in
         "adj_gather": state + m + state + 4 + state,  # S^n, C^{n+1}, adj in, id; adj out
+        "g2p_p2g": (v + m) + 4 + state,            # x, F, id in; state out
     }[kernel]
 
 
@@ -242,12 +243,17 @@ def run_serving(args):
     burst = [S.Request(0.0, r.scene, r.T) for r in base]
     cap_res = Server(max_slots=1, ckpt_k=args.ckpt).run(burst, fifo=True)
     cap = summarize(cap_res)["requests_per_s"]
+    print(f"c5: plain-loop capacity {cap:.2f} requests/s", file=sys.stderr, flush=True)
     points = []
     for frac in (0.5, 0.8, 0.95, 1.5):
         rate = frac * cap
         reqs = [S.Request(r.arrival / rate, r.scene, r.T) for r in base]
         mix = summarize(Server(max_slots=args.slots, ckpt_k=args.ckpt).run(reqs))
+        print(f"c5: load {frac} continuous p99 {mix['latency_s']['p99']}", file=sys.stderr,
+              flush=True)
         fifo = summarize(Server(max_slots=1, ckpt_k=args.ckpt).run(reqs, fifo=True))
+        print(f"c5: load {frac} fifo p99 {fifo['latency_s']['p99']}", file=sys.stderr,
+              flush=True)
         points.append({"load": frac, "rate_per_s": round(rate, 3), "continuous": mix,
                        "fifo": fifo})
     top = points[2]["continuous"]
@@ -267,8 +273,8 @@ def run_serving(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--T", type=int, default=512, help="substeps per rollout")
     ap.add_argument("--ckpt", type=int, default=32,
                     help="checkpoint interval (0 = store every state)")
@@ -336,7 +342,8 @@ def main():
     warm_prof = None
     for w in range(max(args.warmup, 1)):
         if w == 0 and not args.no_profile:
-            sim.profile(["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather"])
+            sim.profile(["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather",
+                         "g2p_p2g"])
         one_step()
         if w == 0 and not args.no_profile:
             prof = sim.profile_read()

@@ -203,7 +203,8 @@ int mpm_sync_errors(mpm_ctx *ctx);
 #define MPM_K_ADJ_SCATTER 3
 #define MPM_K_ADJ_GRID 4
 #define MPM_K_ADJ_GATHER 5
-#define MPM_NUM_KERNELS 6
+#define MPM_K_G2P_P2G 6 /* G2P of substep n fused with P2G of n+1 (3D rollouts) */
+#define MPM_NUM_KERNELS 7
 int mpm_profile(mpm_ctx *ctx, uint32_t mask);
 int mpm_profile_read(mpm_ctx *ctx, int64_t *count, double *ms);
 

@@ -49,7 +49,7 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_act_bank_backward", "mpm_sync_errors", "mpm_strerror",
            "mpm_profile", "mpm_profile_read"]
 
-KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather"]
+KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
 
 _lib = None
 

@@ -308,6 +308,27 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   return launch_g2p(c->dim, a, c->stream);
 }
 
+// G2P of substep n (state s, grid velocity gv) fused with the binned P2G of
+// substep n+1 (actuation act1) into the tile boxes; writes state n+1.
+int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
+                const int *act_id, const float *act1) {
+  G2P2GArgs a;
+  a.scenes = c->d_scenes;
+  a.s = s;
+  a.out = out;
+  a.ld = (int)c->N;
+  a.gv = gv;
+  a.act_id = act_id;
+  a.act = act1;
+  a.gm = c->gm;
+  a.gp = c->gp;
+  a.G = c->G;
+  a.err = c->d_err;
+  a.tiles = tile_info(c);
+  ProfScope ps(c, MPM_K_G2P_P2G);
+  return launch_g2p_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
+}
+
 // ---- the three kernels of one reverse substep ------------------------------
 // gm/gp: forward grid of step n (m, p).  C1: C of state n+1.
 
@@ -588,18 +609,27 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   const Chunk *chunks = cur_chunks(c, &nch);
   const int *ids = cur_act_id(c);
   const bool tiles = c->tape.sorted;
+  // 3D binned rollouts with the sorted scatter fuse each G2P with the next
+  // substep's P2G (state n+1 goes from registers to the scatter)
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3;
+  auto act_of = [&](int n) {
+    return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
+  };
   for (int n = 0; n < L.T; ++n) {
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
-    const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
-    RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+    if (!fuse || n == 0)
+      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp));
     if (c->tape.grids_all) {
       float *g = slot_grid(c, n);  // keep this substep's grid on the tape
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
     } else {
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
-    RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
+    if (fuse && n + 1 < L.T)
+      RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1)));
+    else
+      RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
   }
   return MPM_OK;
 }

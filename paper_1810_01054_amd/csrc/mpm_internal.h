@@ -121,6 +121,23 @@ struct G2PArgs {
   unsigned *err;
 };
 
+// G2P of substep n fused with the binned P2G of substep n+1 (3D rollouts):
+// reads x, F of state n and the grid velocity of substep n, writes state
+// n+1, scatters state n+1 into the tile boxes (and the overflow grid gm, gp).
+struct G2P2GArgs {
+  const DevScene *scenes;
+  CState s;           // state n (x, F read)
+  State out;          // state n+1 (x, v, C, F written); must not alias s
+  int ld;
+  const float *gv;    // grid velocity of substep n
+  const int *act_id;  // scene-local actuator of each particle (-1 passive)
+  const float *act;   // [n_act_tot] of substep n+1
+  float *gm, *gp;     // overflow grid of substep n+1
+  int64_t G;
+  unsigned *err;
+  TileInfo tiles;
+};
+
 struct AdjScatterArgs {
   const DevScene *scenes;
   const Chunk *chunks;
@@ -199,6 +216,7 @@ int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_blocks,
 bool tile_supported(int dim, int B);
 int launch_grid(int dim, const GridArgs &a, hipStream_t st);
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st);
+int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_blocks, hipStream_t st);
 int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st);
 int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st);
 int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st);

@@ -369,20 +369,15 @@ __device__ __forceinline__ void scatter_stencil(const float (&w)[D][3],
 // affine form of m_p v_p + G_p (x_i - x_p) = c0 + sum_b Gdx[.][b] o_b.
 // Returns false (with eb set) for an invalid particle.
 template <int D>
-__device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
-                                             const DevScene &sc, int p,
-                                             const float *xp, const float *f,
-                                             float (&w)[D][3], float *c0,
-                                             float (&Gdx)[D][D],
-                                             unsigned &eb) {
-  float F[D * D], C[D * D], v[D], G[D * D];
-  load_mat<D>(A.s.F, A.ld, p, F);
-  load_mat<D>(A.s.C, A.ld, p, C);
-  load_vec<D>(A.s.v, A.ld, p, v);
-  const int j = A.act_id[p];
-  const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
+__device__ __forceinline__ bool p2g_record(const DevScene &sc, const float *F,
+                                           const float *C, const float *v,
+                                           float s_act, bool has_act,
+                                           const float *f, float (&w)[D][3],
+                                           float *c0, float (&Gdx)[D][D],
+                                           unsigned &eb) {
+  float G[D * D];
   Stress<D> S;
-  if (!stress<D>(sc, F, s_act, j >= 0, S, eb)) return false;
+  if (!stress<D>(sc, F, s_act, has_act, S, eb)) return false;
   affine_G<D>(sc, S.Pt, F, C, G);
 #pragma unroll
   for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
@@ -397,6 +392,22 @@ __device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
     c0[a] = s;
   }
   return true;
+}
+
+template <int D>
+__device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
+                                             const DevScene &sc, int p,
+                                             const float *xp, const float *f,
+                                             float (&w)[D][3], float *c0,
+                                             float (&Gdx)[D][D],
+                                             unsigned &eb) {
+  float F[D * D], C[D * D], v[D];
+  load_mat<D>(A.s.F, A.ld, p, F);
+  load_mat<D>(A.s.C, A.ld, p, C);
+  load_vec<D>(A.s.v, A.ld, p, v);
+  const int j = A.act_id[p];
+  const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
+  return p2g_record<D>(sc, F, C, v, s_act, j >= 0, f, w, c0, Gdx, eb);
 }
 
 // Per-particle adjoint-scatter quantities (supplement (A)-(C)):
@@ -725,7 +736,8 @@ __device__ __forceinline__ void cell_scatter_wave(const Args &A,
 
 // Sorted per-cell scatter (drift-proof).  One workgroup (4 waves) per tile.
 // The tile's particles are processed in batches of 256 PER (PER per thread):
-//  1. each thread computes its particles' affine stencil records (f, c0, L)
+//  1. each thread has PART(p, base, f, w, c0, L, eb) produce its particles'
+//     stencil bases and affine stencil records (f, c0, L)
 //     and their current cells in the tile box's (B+2)^d cell grid (one cell
 //     of drift per side), and takes a rank in each cell (integer LDS atomic);
 //  2. an exclusive scan over the cells gives each cell a range; each thread
@@ -917,14 +929,9 @@ __device__ __forceinline__ void sorted_cell_scatter(
       rank[h] = 0;
       const int j = b0 + h * 256 + t;
       const int p = start + j;
-      float xp[D], f[D], w[D][3], c0[D], L[D][D];
+      float f[D], w[D][3], c0[D], L[D][D];
       int base[D];
-      bool ok = false;
-      if (j < cnt) {
-        load_vec<D>(A.s.x, A.ld, p, xp);
-        ok = stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb);
-      }
-      if (!ok) continue;
+      if (!(j < cnt && part(p, base, f, w, c0, L, eb))) continue;
       int l[D];
       bool inbox = true;
 #pragma unroll
@@ -1196,17 +1203,26 @@ template <int D>
 __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
-  auto part = [&](int p, const float *xp, const float *f, float (&w)[D][3],
-                  float *c0, float (&L)[D][D], unsigned &eb) {
-    const DevScene sc = A.scenes[A.tiles.scene[tile]];
-    return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
-  };
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
   if constexpr (D == 2) {
     __shared__ WaveBoxSmem<D, D + 1> sm;
-    sorted_cell_scatter_wb<D, D + 1, true>(A, tile, sm, A.gm, A.gp, part);
+    sorted_cell_scatter_wb<D, D + 1, true>(
+        A, tile, sm, A.gm, A.gp,
+        [&](int p, const float *xp, const float *f, float (&w)[D][3],
+            float *c0, float (&L)[D][D], unsigned &eb) {
+          return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+        });
   } else {
     __shared__ SortedCellSmem<D, D + 1, 2, true> sm;
-    sorted_cell_scatter<D, D + 1, true, 2, true>(A, tile, sm, A.gm, A.gp, part);
+    sorted_cell_scatter<D, D + 1, true, 2, true>(
+        A, tile, sm, A.gm, A.gp,
+        [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+            float (&L)[D][D], unsigned &eb) {
+          float xp[D];
+          load_vec<D>(A.s.x, A.ld, p, xp);
+          return stencil_base<D>(xp, sc, base, f, eb) &&
+                 p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+        });
   }
 }
 
@@ -1214,19 +1230,147 @@ template <int D>
 __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
-  auto part = [&](int p, const float *, const float *f, float (&w)[D][3],
-                  float *c0, float (&L)[D][D], unsigned &) {
-    const DevScene sc = A.scenes[A.tiles.scene[tile]];
-    adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
-    return true;
-  };
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
   if constexpr (D == 2) {
     __shared__ WaveBoxSmem<D, D> sm;
-    sorted_cell_scatter_wb<D, D, false>(A, tile, sm, nullptr, A.vbar, part);
+    sorted_cell_scatter_wb<D, D, false>(
+        A, tile, sm, nullptr, A.vbar,
+        [&](int p, const float *, const float *f, float (&w)[D][3], float *c0,
+            float (&L)[D][D], unsigned &) {
+          adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+          return true;
+        });
   } else {
     __shared__ SortedCellSmem<D, D, 2, false> sm;
-    sorted_cell_scatter<D, D, false, 2, false>(A, tile, sm, nullptr, A.vbar, part);
+    sorted_cell_scatter<D, D, false, 2, false>(
+        A, tile, sm, nullptr, A.vbar,
+        [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+            float (&L)[D][D], unsigned &eb) {
+          float xp[D];
+          load_vec<D>(A.s.x, A.ld, p, xp);
+          if (!stencil_base<D>(xp, sc, base, f, eb)) return false;
+          adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+          return true;
+        });
   }
+}
+
+// G2P of substep n and the sorted P2G of substep n+1 in one pass over a
+// tile (3D): the tile's box of grid velocities is staged in LDS, each thread
+// gathers its particles (section III, G2P), writes state n+1, and hands the
+// new state straight to the scatter's record step (section III, P2G), so
+// state n+1 is not read back from HBM.  Particles whose stencil left the box
+// gather from HBM.
+template <int D>
+__global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
+  static_assert(D == 3, "the fused pass is built for 3D tiles");
+  using SC = SortedCell<D>;
+  constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, B = SC::B;
+  __shared__ SortedCellSmem<D, D + 1, 2, true> sm;
+  __shared__ float s_v[D * SV];
+  const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
+  if (A.tiles.cnt[tile] == 0) return;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  for (int i = threadIdx.x; i < SV; i += 256) {
+    const int g[3] = {org[0] + i / (S * S), org[1] + (i / S) % S, org[2] + i % S};
+    const bool in = g[0] >= 0 && g[0] < sc.n && g[1] >= 0 && g[1] < sc.n &&
+                    g[2] >= 0 && g[2] < sc.n;
+    const int64_t gi = sc.g_off + ((int64_t)g[0] * sc.n + g[1]) * sc.n + g[2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) s_v[a * SV + i] = in ? A.gv[a * A.G + gi] : 0.0f;
+  }
+  // (the scatter synchronises before its record step reads s_v)
+  sorted_cell_scatter<D, D + 1, true, 2, true>(
+      A, tile, sm, A.gm, A.gp,
+      [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+          float (&L)[D][D], unsigned &eb) {
+        float x[D], f0[D], F[D * D];
+        int b0[D];
+        load_vec<D>(A.s.x, A.ld, p, x);
+        if (!stencil_base<D>(x, sc, b0, f0, eb)) {
+          // keep state n+1 defined (the rollout reports the error)
+          float z[D * D] = {};
+          load_mat<D>(A.s.F, A.ld, p, F);
+          store_vec<D>(A.out.x, A.ld, p, x);
+          store_vec<D>(A.out.v, A.ld, p, z);
+          store_mat<D>(A.out.C, A.ld, p, z);
+          store_mat<D>(A.out.F, A.ld, p, F);
+          return false;
+        }
+        int lb[D];
+        bool inb = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          lb[a] = b0[a] - org[a];
+          inb = inb && lb[a] >= 0 && lb[a] < BC;
+        }
+        const int lbase = (lb[0] * S + lb[1]) * S + lb[2];
+        const int64_t gbase = sc.g_off + node_index<D>(b0, sc.n);
+        float w0[D][3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) bspline_w(f0[a], w0[a]);
+        float vn[D] = {}, Bm[D * D] = {};  // sum N v_i, sum N v_i (o - f)^T
+#pragma unroll 1
+        for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+          for (int o1 = 0; o1 < 3; ++o1) {
+            const float w01 = w0[0][o0] * w0[1][o1];
+#pragma unroll
+            for (int o2 = 0; o2 < 3; ++o2) {
+              const float N = w01 * w0[2][o2];
+              const float d[3] = {(float)o0 - f0[0], (float)o1 - f0[1], (float)o2 - f0[2]};
+              float vi[3];
+              if (inb) {
+                const int li = lbase + (o0 * S + o1) * S + o2;
+#pragma unroll
+                for (int a = 0; a < D; ++a) vi[a] = s_v[a * SV + li];
+              } else {
+                const int64_t gi = gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2;
+#pragma unroll
+                for (int a = 0; a < D; ++a) vi[a] = A.gv[a * A.G + gi];
+              }
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                const float Nv = N * vi[a];
+                vn[a] += Nv;
+#pragma unroll
+                for (int b = 0; b < D; ++b) Bm[a * D + b] += Nv * d[b];
+              }
+            }
+          }
+        load_mat<D>(A.s.F, A.ld, p, F);
+        // C' = (4/dx^2) sum N v_i (x_i - x_p)^T; F' = (I + dt C') F;
+        // x' = x + dt v'
+        const float cs = sc.Dinv * sc.dx;
+        float Cn[D * D], Fn[D * D], xn[D];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) Cn[k] = cs * Bm[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) {
+            float acc = F[a * D + b];
+#pragma unroll
+            for (int g = 0; g < D; ++g) acc += sc.dt * Cn[a * D + g] * F[g * D + b];
+            Fn[a * D + b] = acc;
+          }
+#pragma unroll
+        for (int a = 0; a < D; ++a) xn[a] = x[a] + sc.dt * vn[a];
+        if (!(finite_all(xn, D) && finite_all(vn, D) && finite_all(Cn, D * D) &&
+              finite_all(Fn, D * D)))
+          eb |= EB_NONFINITE;
+        store_vec<D>(A.out.x, A.ld, p, xn);
+        store_vec<D>(A.out.v, A.ld, p, vn);
+        store_mat<D>(A.out.C, A.ld, p, Cn);
+        store_mat<D>(A.out.F, A.ld, p, Fn);
+        // the record of state n+1 for the scatter
+        if (!stencil_base<D>(xn, sc, base, f, eb)) return false;
+        const int j = A.act_id[p];
+        const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
+        return p2g_record<D>(sc, Fn, Cn, vn, s_act, j >= 0, f, w, c0, L, eb);
+      });
 }
 
 template <int D>
@@ -2331,6 +2475,11 @@ int launch_adj_scatter_cell(int dim, const AdjScatterArgs &a,
 int launch_grid(int dim, const GridArgs &a, hipStream_t st) {
   if (dim == 2) MPM_LAUNCH(k_grid<2>, a.n_blocks, 256, st, a);
   MPM_LAUNCH(k_grid<3>, a.n_blocks, 256, st, a);
+}
+
+int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_tiles, hipStream_t st) {
+  if (dim != 3) return -1;  // the caller only fuses 3D passes
+  MPM_LAUNCH(k_g2p_p2g_sorted<3>, n_tiles, 256, st, a);
 }
 
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st) {

@@ -194,23 +194,26 @@ def test_rollout_then_step_then_backward(recompute_grids):
     assert rel_err(to_np(g0b)[0], to_np(g0)[0]) < 1e-6
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_graph_replays_match_eager(dim):
     """Rollouts replayed from captured hipGraphs, several times, with eager
     work and synchronisations between replays, each checked against the
     eager context and the oracle."""
-    sc = S.config_1b()
+    sc = S.config_1b() if dim == 2 else S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=36)
     T, k = 30, 8
     acts32 = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
     N = sc.n_particles
-    gT = [np.random.default_rng(8).normal(size=(2, N)).astype(np.float32) / N,
-          np.zeros((2, N), np.float32), np.zeros((4, N), np.float32), np.zeros((4, N), np.float32)]
+    d = sc.dim
+    gT = [np.random.default_rng(8).normal(size=(d, N)).astype(np.float32) / N,
+          np.zeros((d, N), np.float32), np.zeros((d * d, N), np.float32),
+          np.zeros((d * d, N), np.float32)]
     refT, ref0, _ = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
                                    acts32.astype(np.float64), f64(gT))
     eager = sim_for(sc, graphs=False)
     graph = sim_for(sc, graphs=True)
     act = torch.tensor(acts32, device="cuda")
     for rep in range(4):
-        say("graph replay", rep)
+        say("graph replay", dim, rep)
         e = eager.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
         g = graph.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
         graph.step_forward(to_gpu(sc.state), torch.ones(sc.n_act, device="cuda"))
@@ -239,6 +242,78 @@ def test_rollout_fast_drift_uses_overflow_path(scatter):
     sc.v[0, :] = 6.0
     sc.v[1, :] = 2.0
     _rollout_case(sc, 100, ks=[0, 25], scatter=scatter)
+
+
+def test_rollout_c2_100_steps_and_k_invariance():
+    """C2 (2D 256^2, 98,304 particles, 48 actuators x 4-sinusoid banks):
+    100 substeps fwd + bwd against the oracle; then the full 1,000-substep
+    rollout with k = 64 against the same rollout with every state stored.
+    The two schedules differ only in FP32 rounding of the recomputed states
+    (the recompute rebuilds grid velocities from the stored m, p inside the
+    gather); the final states agree to 1e-6 and the adjoints, after 1,000
+    reverse substeps, to 1e-4 (an order below the gradient tolerance)."""
+    sc = S.config_2()
+    _rollout_case(sc, 100, ks=[64])
+    T = 1000
+    say("c2 full", sc.n_particles, T)
+    act = gpu_act_bank(sc, T)
+    N = sc.n_particles
+    gT = [np.zeros((2, N), np.float32), np.zeros((2, N), np.float32),
+          np.zeros((4, N), np.float32), np.zeros((4, N), np.float32)]
+    gT[0][0] = 1.0 / N                     # centroid x-displacement
+    sim = sim_for(sc)
+    outs = []
+    for k in (64, 0):
+        sT, g0, gact = sim.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
+        sim.sync_errors()
+        outs.append((to_np(sT), to_np(g0), gact.cpu().numpy()))
+    (sa, ga, aa), (sb, gb, ab) = outs
+    assert all(np.isfinite(x).all() for x in sa + ga) and np.isfinite(aa).all()
+    for c in range(4):
+        assert rel_err(sa[c], sb[c]) < 1e-6, ("state", c)
+        assert rel_err(ga[c], gb[c]) < 1e-4, ("adjoint", c, rel_err(ga[c], gb[c]))
+    assert rel_err(aa, ab) < 1e-4, rel_err(aa, ab)
+
+
+def test_rollout_3d_fast_drift():
+    # 3D rollouts fuse each G2P with the next P2G: a block moving ~3 cells
+    # over the rollout leaves its tile's staged velocity box (gather from
+    # HBM) and its box slack (global atomics) on both passes
+    sc = S.box_3d(32, (8, 8, 8), (14, 13, 15), seed=33)
+    sc.v[0, :] = 9.0
+    sc.v[2, :] = -6.0
+    _rollout_case(sc, 100, ks=[0, 25])
+
+
+def test_batched_3d_scenes_rollout():
+    # two 3D scenes of different grids in one context (tiles of both scenes
+    # in every launch, fused forward included), each against the oracle
+    a = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=34)
+    b = S.box_3d(32, (9, 4, 8), (15, 11, 14), seed=35)
+    scs = [a, b]
+    T = 30
+    say("batched_3d", [s.n_particles for s in scs])
+    acts = [oracle.act_bank_fwd(T, s.dt, s.freq, s.amp, s.phase).astype(np.float32) for s in scs]
+    act = torch.tensor(np.concatenate(acts, axis=1), device="cuda")
+    Ntot = sum(s.n_particles for s in scs)
+    rng = np.random.default_rng(6)
+    gT = [rng.normal(size=(3, Ntot)).astype(np.float32) / Ntot, np.zeros((3, Ntot), np.float32),
+          np.zeros((9, Ntot), np.float32), np.zeros((9, Ntot), np.float32)]
+    sim = sim_for(scs)
+    sT, g0, gact = sim.rollout(to_gpu(concat_state(scs)), act, T, ckpt_k=8, gT=to_gpu(gT))
+    sim.sync_errors()
+    sT, g0, gact = to_np(sT), to_np(g0), gact.cpu().numpy()
+    offs = np.cumsum([0] + [s.n_particles for s in scs])
+    aoffs = np.cumsum([0] + [s.n_act for s in scs])
+    for i, s in enumerate(scs):
+        sl = slice(offs[i], offs[i + 1])
+        refT, ref0, ref_act = oracle.rollout(oscene(s), f64(s.state), T, s.act_id,
+                                             acts[i].astype(np.float64),
+                                             tuple(np.asarray(x[:, sl], np.float64) for x in gT))
+        assert rel_err(sT[0][:, sl], refT[0]) < POS_TOL
+        for c in range(4):
+            assert rel_err(g0[c][:, sl], ref0[c]) < GRAD_TOL, (i, c)
+        assert rel_err(gact[:, aoffs[i]:aoffs[i + 1]], ref_act) < GRAD_TOL
 
 
 def test_batched_scenes_match_per_scene_oracle():
