@@ -36,7 +36,7 @@ def kernel_bytes_per_particle(kernel: str, d: int) -> int:
         "p2g": state + 4,                          # state + act id
         "g2p": (v + m) + state,                    # x, F in; state out
         "adj_scatter": (v + m) + state,            # x, F, adjoint in
-        "adj_gather": state + m + state + 4 + state,  # S^n, C^{n+1}, adj in, id; adj out
+        "adj_gather": state + state + 4 + state,   # S^n, adj in, id; adj out
         "g2p_p2g": (v + m) + 4 + state,            # x, F, id in; state out
     }[kernel]
 
@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--T", type=int, default=512, help="substeps per rollout")
     ap.add_argument("--ckpt", type=int, default=32,
                     help="checkpoint interval (0 = store every state)")
-    ap.add_argument("--cpu-sample", type=int, default=2,
+    ap.add_argument("--cpu-sample", type=int, default=10,
                     help="substeps of the oracle sample (0 = skip)")
     ap.add_argument("--scatter", type=int, default=0,
                     help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
@@ -340,6 +340,7 @@ def main():
     # warm-up; the first warm-up step also finds the dominant kernel
     dominant = "adj_gather"
     warm_prof = None
+    kernel_roof = None
     for w in range(max(args.warmup, 1)):
         if w == 0 and not args.no_profile:
             sim.profile(["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather",
@@ -351,6 +352,23 @@ def main():
             dominant = max(prof, key=lambda kk: prof[kk][1])
             warm_prof = {kk: round(ms * 1e3 / max(n, 1), 2)
                          for kk, (n, ms) in prof.items() if n}
+            # every kernel against the HBM roofline (algorithmic bytes)
+            kernel_roof = {}
+            for kk, (n, ms) in prof.items():
+                if not n:
+                    continue
+                if kk in ("grid", "adj_grid"):
+                    b = kernel_bytes_per_node(kk, d) * sim.G
+                else:
+                    b = kernel_bytes_per_particle(kk, d) * N
+                gbs = b / (ms / n / 1e3) / 1e9
+                kernel_roof[kk] = {"avg_us": round(ms * 1e3 / n, 2), "launches": n,
+                                   "algorithmic_GBps": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                   "share_of_time": None, "_ms": ms}
+            tot = sum(v["_ms"] for v in kernel_roof.values())
+            for v in kernel_roof.values():
+                v["share_of_time"] = round(v.pop("_ms") / tot, 4)
     sim.sync_errors()
     torch.cuda.synchronize()
 
@@ -413,6 +431,7 @@ def main():
                                "p99": round(percentile(lat, 0.99), 3)},
         "roofline": roof,
         "kernel_avg_us": warm_prof,
+        "kernel_roofline": kernel_roof,
         "cpu_baseline": None,
     }
     if args.cpu_sample > 0:

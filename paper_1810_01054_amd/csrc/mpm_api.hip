@@ -330,11 +330,10 @@ int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
 }
 
 // ---- the three kernels of one reverse substep ------------------------------
-// gm/gp: forward grid of step n (m, p).  C1: C of state n+1.
+// gm/gp: forward grid of step n (m, p).
 
 int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
-             CState s,
-             const float *C1, const int *act_id, const float *act,
+             CState s, const int *act_id, const float *act,
              const float *gm, const float *gp, CState g1, State g0,
              double *gact) {
   AdjScatterArgs r1;
@@ -385,7 +384,6 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r3.chunks = chunks;
   r3.n_chunks = n_chunks;
   r3.s = s;
-  r3.C1 = C1;
   r3.g1 = g1;
   r3.g0 = g0;
   r3.ld = (int)c->N;
@@ -654,7 +652,7 @@ int rollout_backward_core(mpm_ctx *c) {
   const int seglen = t.memo ? 1 : t.k;
   for (int j = nseg - 1; j >= 0; --j) {
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
-    // state n and the C of state n+1 for n in [n0, n1)
+    // state n for n in [n0, n1)
     auto S = [&](int n) -> float * {
       if (t.memo) return slot_state(c, n);
       if (n == n0) return slot_state(c, j);
@@ -686,10 +684,9 @@ int rollout_backward_core(mpm_ctx *c) {
     }
     for (int n = n1 - 1; n >= n0; --n) {
       const State s = state_at(c, S(n));
-      const State s1 = state_at(c, S(n + 1));
       const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
       const float *g = Gr(n);
-      RC(bwd_step(c, tiles, chunks, nch, cs(s), s1.C, ids, act, g, g + c->G, cs(A1),
+      RC(bwd_step(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G, cs(A1),
                   A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
       std::swap(A0, A1);
     }
@@ -1037,21 +1034,20 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
   if (!state_ok(c, s_n) || !state_ok(c, g_np1) || !state_ok(c, g_n) ||
       (c->n_act && !act_n))
     return MPM_ERR_ARG;
-  // forward grid of step n and C of state n+1
+  // forward grid of step n (the adjoint gather rebuilds C of state n+1
+  // from it)
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   RC(fwd_p2g(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n),
              c->d_act_id, act_n, c->gm, c->gp));
   RC(fwd_grid(c, false, c->gm, c->gp, c->gv, 0));
-  const State s1 = state_at(c, c->scratch);
-  RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1, c->gv));
   double *gact = nullptr;
   if (g_act_n && c->n_act > 0) {
     RC(ensure_gact(c, c->n_act));
     RC(launch_fill_f64(c->gact, c->n_act, c->stream));
     gact = c->gact;
   }
-  RC(bwd_step(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n), s1.C,
+  RC(bwd_step(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n),
               c->d_act_id, act_n, c->gm, c->gp, cs(*g_np1), st(*g_n), gact));
   if (gact) RC(launch_gact_store(gact, g_act_n, c->n_act, 1, c->stream));
   return MPM_OK;

@@ -169,7 +169,6 @@ struct AdjGatherArgs {
   const Chunk *chunks;
   int n_chunks;
   CState s;          // state n
-  const float *C1;   // C of state n+1 ([d*d][ld])
   CState g1;         // adjoint of state n+1
   State g0;          // adjoint of state n (may alias g1)
   int ld;

@@ -1981,8 +1981,10 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
       bspline_w(f[a], w[a]);
       bspline_dw(f[a], sc.inv_dx, dw[a]);
     }
-    // Go = sum N p_i o^T (dL/dG = (Go - Spb f^T) dx after the loop)
-    float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {};
+    // Go = sum N p_i o^T (dL/dG = (Go - Spb f^T) dx after the loop);
+    // Co = sum N v_i o^T gives C^{n+1} = (4/dx^2) dx (Co - Sv f^T), the G2P
+    // of this substep, from the same staged velocities
+    float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {}, Co[D * D] = {};
     load_vec<D>(A.g1.x, A.ld, p, xb);  // (J) direct term dL/dx^{n+1}
     const int lbase = box.lds ? box_index<D>(box, base) : 0;
     const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
@@ -2001,11 +2003,14 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
         }
         // (J) v-term and C-term (N parts), p-term (N part)
         s_all += vi[a] * cv + pb[a] * q;
-        const float Npb = N * pb[a];
-        Spb[a] += Npb;       // (F), and the delta part of the (J) p-term
-        Sv[a] += N * vi[a];  // delta part of the (J) C-term
+        const float Npb = N * pb[a], Nv = N * vi[a];
+        Spb[a] += Npb;  // (F), and the delta part of the (J) p-term
+        Sv[a] += Nv;    // delta part of the (J) C-term
 #pragma unroll
-        for (int b = 0; b < D; ++b) Gb[a * D + b] += Npb * o[b];
+        for (int b = 0; b < D; ++b) {
+          Gb[a * D + b] += Npb * o[b];
+          Co[a * D + b] += Nv * o[b];
+        }
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
@@ -2055,16 +2060,20 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
         s += CdxD[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
       xb[c] -= s * sc.inv_dx;
     }
+    float C1[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int b = 0; b < D; ++b) Gb[a * D + b] -= Spb[a] * f[b];
+      for (int b = 0; b < D; ++b) {
+        Gb[a * D + b] -= Spb[a] * f[b];
+        C1[a * D + b] = (sc.Dinv * sc.dx) * (Co[a * D + b] - Sv[a] * f[b]);
+      }
     // --- after the loop: reload F and dL/dF^{n+1}, recompute the stress ----
     // (the compiler barrier keeps the pre-loop copies from staying live
     // across the stencil loop; in 3D they come back from the thread's LDS
     // slots instead of a second HBM read)
     asm volatile("" ::: "memory");
-    float F[D * D], gF1[D * D], C1[D * D];
+    float F[D * D], gF1[D * D];
     if constexpr (D == 3) {
 #pragma unroll
       for (int q = 0; q < D * D; ++q) {
@@ -2075,7 +2084,6 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
       load_mat<D>(A.s.F, A.ld, p, F);
       load_mat<D>(A.g1.F, A.ld, p, gF1);
     }
-    load_mat<D>(A.C1, A.ld, p, C1);
     Stress<D> S;
     unsigned eb2 = 0;
     stress<D>(sc, F, s_act, j_act >= 0, S, eb2);
