@@ -450,6 +450,22 @@ int bin_particles(mpm_ctx *c, const float *x) {
   RC(read_err(c));  // synchronises
   c->n_chunks_sorted = nch;
   c->n_tiles_ne = nne;
+  // launch the fullest tiles first: one workgroup per tile takes time
+  // roughly in proportion to its particles, and the small tiles then fill
+  // the last round of workgroup slots instead of trailing it
+  if (nne > 1) {
+    std::vector<int> cnt(c->n_tiles), list(nne);
+    RC(hip_ok(hipMemcpyAsync(cnt.data(), c->d_tile_cnt, sizeof(int) * c->n_tiles,
+                             hipMemcpyDeviceToHost, s)));
+    RC(hip_ok(hipMemcpyAsync(list.data(), c->d_tile_list, sizeof(int) * nne,
+                             hipMemcpyDeviceToHost, s)));
+    RC(hip_ok(hipStreamSynchronize(s)));
+    std::stable_sort(list.begin(), list.end(),
+                     [&](int a, int b) { return cnt[a] > cnt[b]; });
+    RC(hip_ok(hipMemcpyAsync(c->d_tile_list, list.data(), sizeof(int) * nne,
+                             hipMemcpyHostToDevice, s)));
+    RC(hip_ok(hipStreamSynchronize(s)));  // `list` is host memory
+  }
   return MPM_OK;
 }
 
