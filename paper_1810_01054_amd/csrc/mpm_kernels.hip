@@ -315,7 +315,17 @@ __device__ __forceinline__ void affine_G(const DevScene &sc, const float *Pt,
     }
 }
 
-__device__ __forceinline__ int chunk_id() { return blockIdx.x; }
+// Workgroups go to the eight XCDs round-robin by block index, and each XCD
+// has its own L2.  Chunks are in tile order and node blocks in node order,
+// so neighbouring work items share grid nodes or tile boxes: give each XCD a
+// contiguous run of them (a bijection of the block indices) so that the
+// shared data passes through one L2.
+__device__ __forceinline__ int xcd_block_id() {
+  constexpr int NX = 8;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb / NX, r = nb % NX, x = b % NX, k = b / NX;
+  return x * q + min(x, r) + k;
+}
 
 // ---------------------------------------------------------------------------
 // step 1: P2G scatter
@@ -477,7 +487,7 @@ __device__ __forceinline__ int64_t stencil_gindex(int64_t gbase, int n, int o0,
 template <int D>
 __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
   __shared__ float s_grid[(D + 1) * LDS_NODES];
-  const Chunk ch = A.chunks[chunk_id()];
+  const Chunk ch = A.chunks[xcd_block_id()];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
   const bool active = t < ch.count;
@@ -1512,7 +1522,7 @@ __device__ __forceinline__ void node_velocity(const DevScene &sc, int li,
 
 template <int D>
 __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
-  const GridBlock gb = A.blocks[blockIdx.x];
+  const GridBlock gb = A.blocks[xcd_block_id()];
   if ((int)threadIdx.x >= gb.count) return;
   const DevScene sc = A.scenes[gb.scene];
   const int li = gb.start + threadIdx.x;
@@ -1552,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
 template <int D>
 __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
   __shared__ float s_v[D * LDS_NODES];
-  const Chunk ch = A.chunks[chunk_id()];
+  const Chunk ch = A.chunks[xcd_block_id()];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
   const bool active = t < ch.count;
@@ -1702,7 +1712,7 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
 template <int D>
 __global__ __launch_bounds__(CH) void k_adj_scatter(AdjScatterArgs A) {
   __shared__ float s_grid[D * LDS_NODES];
-  const Chunk ch = A.chunks[chunk_id()];
+  const Chunk ch = A.chunks[xcd_block_id()];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
   const bool active = t < ch.count;
@@ -1822,7 +1832,7 @@ __global__ __launch_bounds__(256) void k_adj_scatter_tile(AdjScatterArgs A) {
 
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
-  const GridBlock gb = A.blocks[blockIdx.x];
+  const GridBlock gb = A.blocks[xcd_block_id()];
   if ((int)threadIdx.x >= gb.count) return;
   const DevScene sc = A.scenes[gb.scene];
   const int li = gb.start + threadIdx.x;
@@ -1904,7 +1914,7 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   __shared__ double s_act[LDS_ACT];
   // F^n and dL/dF^{n+1} of each thread, kept for the post-loop algebra
   __shared__ float s_keep[D == 3 ? 2 * D * D * CH : 1];
-  const Chunk ch = A.chunks[chunk_id()];
+  const Chunk ch = A.chunks[xcd_block_id()];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
   const bool active = t < ch.count;
