@@ -1923,8 +1923,20 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   float xp[D], f[D];
   int base[D];
   bool ok = false;
+  // the particle's streams are requested before the node staging and its
+  // barriers, so their latency overlaps the staging
+  float v[D], C[D * D], F[D * D], gx1[D], gv1[D], gC1[D * D], gF1[D * D];
+  int j_act = -1;
   if (active) {
     load_vec<D>(A.s.x, A.ld, p, xp);
+    load_vec<D>(A.s.v, A.ld, p, v);
+    load_mat<D>(A.s.C, A.ld, p, C);
+    load_mat<D>(A.s.F, A.ld, p, F);
+    load_vec<D>(A.g1.x, A.ld, p, gx1);
+    load_vec<D>(A.g1.v, A.ld, p, gv1);
+    load_mat<D>(A.g1.C, A.ld, p, gC1);
+    load_mat<D>(A.g1.F, A.ld, p, gF1);
+    j_act = A.act_id[p];
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
   const Box<D> box = chunk_box<D>(ok, base);
@@ -1938,9 +1950,8 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   __syncthreads();
 
   float sb_act = 0.0f;
-  int j_act = -1;
+  if (!ok) j_act = -1;
   if (ok) {
-    j_act = A.act_id[p];
     const float s_act = j_act >= 0 ? A.act[sc.act_off + j_act] : 0.0f;
     // --- quantities live across the stencil loop -------------------------
     float w[D][3], dw[D][3];
@@ -1948,19 +1959,10 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     float cV[D], CdxD[D][D];
     float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
     {
-      float v[D], C[D * D], F[D * D];
-      load_vec<D>(A.s.v, A.ld, p, v);
-      load_mat<D>(A.s.C, A.ld, p, C);
-      load_mat<D>(A.s.F, A.ld, p, F);
       Stress<D> S;
       ok = stress<D>(sc, F, s_act, j_act >= 0, S, eb);
       float G[D * D];
       affine_G<D>(sc, S.Pt, F, C, G);
-      float gx1[D], gv1[D], gC1[D * D], gF1[D * D];
-      load_vec<D>(A.g1.x, A.ld, p, gx1);
-      load_vec<D>(A.g1.v, A.ld, p, gv1);
-      load_mat<D>(A.g1.C, A.ld, p, gC1);
-      load_mat<D>(A.g1.F, A.ld, p, gF1);
       if constexpr (D == 3) {
 #pragma unroll
         for (int q = 0; q < D * D; ++q) {
