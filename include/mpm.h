@@ -148,7 +148,9 @@ int mpm_step_backward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
  * the reverse pass are kept in a library-owned tape (the paper's "memo"):
  *   ckpt_k = 0  every state and grid is stored (no recompute);
  *   ckpt_k >= 1 every k-th state is stored and each segment of k substeps is
- *               recomputed from its checkpoint during the reverse pass.
+ *               recomputed from its checkpoint during the reverse pass (with
+ *               the grids kept, on a second library stream, one segment
+ *               ahead of the adjoint kernels).
  * If `gT` is non-NULL the reverse pass runs at once and writes the adjoint
  * of s0 to `g0` and dL/ds [T][n_act_tot] to `g_act` (DEVICE, overwritten,
  * nullable); otherwise the tape is kept for mpm_rollout_backward.  The tape

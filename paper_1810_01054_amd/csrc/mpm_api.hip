@@ -56,6 +56,10 @@ struct mpm_ctx {
     bool valid = false;
   } gfwd, gbwd;
   hipStream_t cap_stream = nullptr;
+  // second library stream for the reverse pass's recompute, which runs one
+  // segment ahead of the adjoint kernels (default priority)
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_recomp = nullptr, ev_adj = nullptr;
   hipStream_t stream = nullptr;
   int poisoned = 0;
 
@@ -291,7 +295,7 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
 
 int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
             State out, const float *gv, const float *gm = nullptr,
-            const float *gp = nullptr) {
+            const float *gp = nullptr, hipStream_t st = nullptr) {
   G2PArgs a;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
@@ -305,7 +309,7 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   a.G = c->G;
   a.err = c->d_err;
   ProfScope ps(c, MPM_K_G2P);
-  return launch_g2p(c->dim, a, c->stream);
+  return launch_g2p(c->dim, a, st ? st : c->stream);
 }
 
 // G2P of substep n (state s, grid velocity gv) fused with the binned P2G of
@@ -666,46 +670,80 @@ int rollout_backward_core(mpm_ctx *c) {
   if (nga > 0) RC(launch_fill_f64(c->gact, nga, c->stream));
   const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
   const int seglen = t.memo ? 1 : t.k;
+  const bool keep = !t.memo && t.grids_all;  // stored grids: G2P-only recompute
+  // state n of segment j (segment states alternate between two banks when
+  // the grids are kept, so one segment can be recomputed while the adjoint
+  // of the next one runs)
+  auto S = [&](int j, int n) -> float * {
+    const int n0 = j * seglen;
+    if (t.memo) return slot_state(c, n);
+    if (n == n0) return slot_state(c, j);
+    const int64_t bank = keep ? (j & 1) : 0;
+    return slot_state(c, L.ncp + bank * t.k + (n - n0));
+  };
+  auto Gr = [&](int n0, int n) -> float * {
+    return t.grids_all ? slot_grid(c, n) : slot_grid(c, n - n0);
+  };
+  // recompute segment j's states from its checkpoint with G2P alone,
+  // reading each substep's stored grid
+  auto recompute = [&](int j, hipStream_t st) -> int {
+    const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
+    for (int n = n0; n + 1 < n1; ++n) {
+      const float *g = Gr(n0, n);
+      RC(fwd_g2p(c, chunks, nch, cs(state_at(c, S(j, n))), state_at(c, S(j, n + 1)),
+                 nullptr, g, g + c->G, st));
+    }
+    return MPM_OK;
+  };
+  // overlap: the recompute of segment j-1 runs on a second stream while the
+  // adjoint kernels of segment j run on the context's stream (not under
+  // graph capture, nor while G2P launches are being timed)
+  const bool overlap = keep && nseg > 1 && !(c->use_graphs && !c->prof.mask) &&
+                       !((c->prof.mask >> MPM_K_G2P) & 1u);
+  if (overlap) {
+    if (!c->aux_stream)
+      RC(hip_ok(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking)));
+    for (hipEvent_t *e : {&c->ev_start, &c->ev_recomp, &c->ev_adj})
+      if (!*e) RC(hip_ok(hipEventCreateWithFlags(e, hipEventDisableTiming)));
+    RC(hip_ok(hipEventRecord(c->ev_start, c->stream)));
+    RC(hip_ok(hipStreamWaitEvent(c->aux_stream, c->ev_start, 0)));
+    RC(recompute(nseg - 1, c->aux_stream));
+    RC(hip_ok(hipEventRecord(c->ev_recomp, c->aux_stream)));
+  }
   for (int j = nseg - 1; j >= 0; --j) {
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
-    // state n for n in [n0, n1)
-    auto S = [&](int n) -> float * {
-      if (t.memo) return slot_state(c, n);
-      if (n == n0) return slot_state(c, j);
-      if (n == n1) return slot_state(c, j + 1);
-      return slot_state(c, L.ncp + (n - n0));
-    };
-    auto Gr = [&](int n) -> float * {
-      return t.grids_all ? slot_grid(c, n) : slot_grid(c, n - n0);
-    };
-    if (!t.memo && t.grids_all) {
-      // recompute the segment's states from its checkpoint with G2P alone,
-      // reading each substep's stored grid
-      for (int n = n0; n + 1 < n1; ++n) {
-        const float *g = Gr(n);
-        RC(fwd_g2p(c, chunks, nch, cs(state_at(c, S(n))), state_at(c, S(n + 1)),
-                   nullptr, g, g + c->G));
+    if (overlap) {
+      // segment j's states are ready; start segment j-1's recompute once the
+      // adjoint of segment j+1 (same bank) is done
+      RC(hip_ok(hipStreamWaitEvent(c->stream, c->ev_recomp, 0)));
+      if (j > 0) {
+        RC(hip_ok(hipStreamWaitEvent(c->aux_stream, c->ev_adj, 0)));
+        RC(recompute(j - 1, c->aux_stream));
+        RC(hip_ok(hipEventRecord(c->ev_recomp, c->aux_stream)));
       }
+    } else if (keep) {
+      RC(recompute(j, nullptr));
     } else if (!t.memo) {
       // recompute the segment from its checkpoint, keeping states and grids
       for (int n = n0; n < n1; ++n) {
-        const State s = state_at(c, S(n));
+        const State s = state_at(c, S(j, n));
         const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
-        float *g = Gr(n);
+        float *g = Gr(n0, n);
         RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
         RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
         if (n + 1 < n1)
-          RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(n + 1)), c->gv));
+          RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(j, n + 1)), c->gv));
       }
     }
     for (int n = n1 - 1; n >= n0; --n) {
-      const State s = state_at(c, S(n));
+      const State s = state_at(c, S(j, n));
       const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
-      const float *g = Gr(n);
+      const float *g = Gr(n0, n);
       RC(bwd_step(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G, cs(A1),
                   A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
       std::swap(A0, A1);
     }
+    if (overlap) RC(hip_ok(hipEventRecord(c->ev_adj, c->stream)));
   }
   return MPM_OK;
 }
@@ -788,6 +826,9 @@ void mpm_destroy(mpm_ctx *c) {
   if (c->gfwd.exec) (void)hipGraphExecDestroy(c->gfwd.exec);
   if (c->gbwd.exec) (void)hipGraphExecDestroy(c->gbwd.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+  for (hipEvent_t e : {c->ev_start, c->ev_recomp, c->ev_adj})
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -1083,7 +1124,10 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   const int k = memo ? 1 : std::min(ckpt_k, std::max(T, 1));
   const int ncp = memo ? T + 1 : (T + k - 1) / k + 1;
   const int grids_all = memo || c->keep_grids;
-  const int64_t nstates = memo ? T + 1 : ncp + k;
+  // checkpointed tapes with stored grids keep two banks of segment states:
+  // the reverse pass recomputes one segment while it runs the adjoint of
+  // the next
+  const int64_t nstates = memo ? T + 1 : ncp + (grids_all ? 2 * k : k);
   const int64_t ngrids = grids_all ? T : k;
   RC(ensure_tape(c, nstates, ngrids, (int64_t)T * c->n_act));
   t.T = T;
