@@ -783,7 +783,7 @@ template <int D, int NCH, int PER, bool V4>
 struct SortedCellSmem {
   static constexpr int SV = SortedCell<D>::SV;
   float box[V4 ? 4 * SV : NCH * SV];
-  float rec[PER * 256 * SortedCell<D>::REC];
+  float rec[SortedCell<D>::REC * PER * 256];  // field-major, swizzled slots
   int cnt[256];
   int off[256];
   short order[256];  // the tile's own cells, then the occupied ring cells
@@ -840,20 +840,36 @@ __device__ __forceinline__ void offsets_add(const float (&w)[D][3], float mp,
   }
 }
 
-// The n records of the cell at r, summed into acc at offsets W, W+4, ...
+// LDS bank swizzles of the offset-split scatter.  Records: a cell holds
+// about eight of them, so the lanes of a wave (one cell each) read slots
+// about 8 apart, which fall on few banks; flipping the low three slot bits
+// by bits 6-8 spreads them.  Box nodes (S = 8, 64 nodes per x-plane): the
+// 4x4x4 own cells of a wave touch a 4x4 patch in four planes; flipping node
+// bits per plane parity moves each plane's patch to other banks (V4: bits 2
+// and 3 of the 16-byte node index; planes: bits 2 and 5 of the float index).
+__device__ __forceinline__ int rec_slot(int s) { return s ^ ((s >> 6) & 7); }
+template <bool V4>
+__device__ __forceinline__ int box_slot(int li) {
+  const int n0 = li >> 6;
+  return V4 ? li ^ (((n0 & 1) << 2) | (((n0 >> 1) & 1) << 3))
+            : li ^ (((n0 & 1) << 2) | (((n0 >> 1) & 1) << 5));
+}
+
+// The n records of a cell (first slot o; NR slots per field), summed into
+// acc at offsets W, W+4, ...
 template <int D, int NCH, bool HAS_MASS, int W>
-__device__ __forceinline__ void cell_offsets_sum(const float *r, int n,
-                                                 float mp, float *acc) {
-  constexpr int REC = SortedCell<D>::REC;
+__device__ __forceinline__ void cell_offsets_sum(const float *rec, int NR,
+                                                 int o, int n, float mp,
+                                                 float *acc) {
   for (int k = 0; k < n; ++k) {
-    const float *rk = r + k * REC;
+    const int ps = rec_slot(o + k);
     float w[D][3], c0[D], L[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      bspline_w(rk[a], w[a]);
-      c0[a] = rk[D + a];
+      bspline_w(rec[a * NR + ps], w[a]);
+      c0[a] = rec[(D + a) * NR + ps];
 #pragma unroll
-      for (int b = 0; b < D; ++b) L[a][b] = rk[2 * D + a * D + b];
+      for (int b = 0; b < D; ++b) L[a][b] = rec[(2 * D + a * D + b) * NR + ps];
     }
     offsets_add<D, NCH, HAS_MASS, W>(w, mp, c0, L, acc);
   }
@@ -867,8 +883,8 @@ __device__ __forceinline__ void offsets_flush(float *box, int lcell,
   if constexpr (Q < SortedCell<D>::NO) {
     using O = StencilOffset<D, Q>;
     constexpr int S = SortedCell<D>::S, SV = SortedCell<D>::SV;
-    const int li = D == 2 ? lcell + O::o0 * S + O::o1
-                          : lcell + (O::o0 * S + O::o1) * S + O::o2;
+    const int li = box_slot<V4>(D == 2 ? lcell + O::o0 * S + O::o1
+                                       : lcell + (O::o0 * S + O::o1) * S + O::o2);
     if constexpr (V4) {
       float4 *node = reinterpret_cast<float4 *>(box) + li;
       float4 cur = *node;
@@ -898,6 +914,7 @@ __device__ __forceinline__ void sorted_cell_scatter(
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
                 NIN = SC::NIN, REC = SC::REC, B = SC::B, NQ = SC::NQ;
   constexpr int BOXF = V4 ? 4 * SV : NCH * SV;  // floats in the box
+  constexpr int NR = PER * 256;                 // record slots per field
   static_assert(!V4 || NCH <= 4, "V4 holds at most four channels");
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
@@ -986,9 +1003,9 @@ __device__ __forceinline__ void sorted_cell_scatter(
 #pragma unroll
     for (int h = 0; h < PER; ++h) {
       if (lc[h] < 0) continue;
-      float *dst = sm.rec + (sm.off[lc[h]] + rank[h]) * REC;
+      const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
 #pragma unroll
-      for (int k = 0; k < REC; ++k) dst[k] = rec[h][k];
+      for (int k = 0; k < REC; ++k) sm.rec[k * NR + ps] = rec[h][k];
     }
     __syncthreads();
     // 3. per-cell sums of this wave's offsets, then the waves' read-add-write
@@ -998,15 +1015,15 @@ __device__ __forceinline__ void sorted_cell_scatter(
       const int slot = ps * 64 + lane;
       const int c = slot < nslot ? sm.order[slot] : 0;
       const int n = slot < nslot ? sm.cnt[c] : 0;
-      const float *r = sm.rec + sm.off[c] * REC;
+      const int o = sm.off[c];
       float acc[NQ * NCH];
 #pragma unroll
       for (int k = 0; k < NQ * NCH; ++k) acc[k] = 0.0f;
       switch (wave) {
-        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0>(r, n, sc.mp, acc); break;
-        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1>(r, n, sc.mp, acc); break;
-        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2>(r, n, sc.mp, acc); break;
-        default: cell_offsets_sum<D, NCH, HAS_MASS, 3>(r, n, sc.mp, acc); break;
+        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2>(sm.rec, NR, o, n, sc.mp, acc); break;
+        default: cell_offsets_sum<D, NCH, HAS_MASS, 3>(sm.rec, NR, o, n, sc.mp, acc); break;
       }
       int cc[D];
       {
@@ -1039,14 +1056,15 @@ __device__ __forceinline__ void sorted_cell_scatter(
   float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
   if constexpr (V4) {
     for (int i = t; i < SV; i += 256) {
-      const float4 a = reinterpret_cast<const float4 *>(sm.box)[i];
+      const float4 a = reinterpret_cast<const float4 *>(sm.box)[box_slot<true>(i)];
       dst[i] = a.x;
       dst[SV + i] = a.y;
       if constexpr (NCH > 2) dst[2 * SV + i] = a.z;
       if constexpr (NCH > 3) dst[3 * SV + i] = a.w;
     }
   } else {
-    for (int i = t; i < NCH * SV; i += 256) dst[i] = sm.box[i];
+    for (int i = t; i < NCH * SV; i += 256)
+      dst[i] = sm.box[(i / SV) * SV + box_slot<false>(i % SV)];
   }
 }
 
