@@ -112,6 +112,8 @@ def _load(path: str):
     L.orc_step_bwd.argtypes = [sp, ip, dp] + [dp] * 13
     L.orc_rollout.argtypes = ([sp, ip, ctypes.c_int, dp] + [dp] * 8 +
                               [dp] * 4 + [dp] * 5)
+    L.orc_rollout_ctrl.argtypes = ([sp, ip, ip, ctypes.c_int, dp, dp, dp, ctypes.c_int] +
+                                   [dp] * 8 + [dp] + [dp] * 4 + [dp] * 4 + [dp] * 2)
     L.orc_act_bank_fwd.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] + [dp] * 4
     L.orc_act_bank_fwd.restype = None
     L.orc_act_bank_bwd.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] + [dp] * 6
@@ -285,6 +287,37 @@ def rollout(scene: Scene, state0, T: int, act_id=None, act=None, gradT=None):
                              *[_d(o) for o in g], *[_d(o) for o in g0],
                              _d(g_act)))
     return tuple(out), tuple(g0), g_act[:, :scene.n_act]
+
+
+def rollout_ctrl(scene: Scene, state0, T: int, comp_id, n_comp: int, W, b, target,
+                 act_id=None, gradT=None):
+    """T substeps driven by the closed-loop controller a^n = tanh(W z^n + b)
+    (section IV, Control; z^n = [target, mean x and mean v of each
+    component]).  Returns ``(stateT, acts[T][n_act])`` or, with ``gradT``,
+    ``(stateT, acts, grad0, gW, gb)``."""
+    x, v, C, F = (_f64(a) for a in state0)
+    out = [np.zeros_like(x), np.zeros_like(v), np.zeros_like(C), np.zeros_like(F)]
+    ids = _ids(scene, act_id)
+    comp = np.ascontiguousarray(np.asarray(comp_id, np.int32))
+    W, b, target = _f64(W), _f64(b), _f64(target)
+    nact = scene.n_act
+    acts = np.zeros((T, nact))
+    if gradT is None:
+        _check(lib().orc_rollout_ctrl(ctypes.byref(scene.c()), _i(ids), _i(comp), n_comp,
+                                      _d(W), _d(b), _d(target), T,
+                                      _d(x), _d(v), _d(C), _d(F), *[_d(o) for o in out],
+                                      _d(acts), None, None, None, None,
+                                      None, None, None, None, None, None))
+        return tuple(out), acts
+    g = [_f64(a) for a in gradT]
+    g0 = [np.zeros_like(x), np.zeros_like(v), np.zeros_like(C), np.zeros_like(F)]
+    gW, gb = np.zeros_like(W), np.zeros_like(b)
+    _check(lib().orc_rollout_ctrl(ctypes.byref(scene.c()), _i(ids), _i(comp), n_comp,
+                                  _d(W), _d(b), _d(target), T,
+                                  _d(x), _d(v), _d(C), _d(F), *[_d(o) for o in out],
+                                  _d(acts), *[_d(o) for o in g], *[_d(o) for o in g0],
+                                  _d(gW), _d(gb)))
+    return tuple(out), acts, tuple(g0), gW, gb
 
 
 def act_bank_fwd(T: int, dt: float, freq, amp, phase):

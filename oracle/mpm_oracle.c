@@ -740,6 +740,155 @@ int orc_rollout(const orc_scene *s, const int32_t *act_id, int T,
 }
 
 /* ------------------------------------------------------------------ */
+/* closed-loop controller a = tanh(W z + b) (section IV, Control)        */
+/* ------------------------------------------------------------------ */
+
+/* z = [target, per component: mean x, mean v] of one state. */
+static void ctrl_state_vector(const orc_scene *s, const int32_t *comp_id,
+                              int n_comp, const long *count,
+                              const double *target, const double *x,
+                              const double *v, double *z) {
+  int d = s->dim;
+  long N = s->n_particles;
+  int nz = d * (1 + 2 * n_comp);
+  for (int i = 0; i < nz; ++i) z[i] = 0.0;
+  for (int a = 0; a < d; ++a) z[a] = target[a];
+  for (long p = 0; p < N; ++p) {
+    int c = comp_id[p];
+    if (c < 0) continue;
+    for (int a = 0; a < d; ++a) {
+      z[d + 2 * d * c + a] += x[(size_t)a * N + p];
+      z[d + 2 * d * c + d + a] += v[(size_t)a * N + p];
+    }
+  }
+  for (int c = 0; c < n_comp; ++c)
+    for (int i = 0; i < 2 * d; ++i) z[d + 2 * d * c + i] /= (double)count[c];
+}
+
+int orc_rollout_ctrl(const orc_scene *s, const int32_t *act_id,
+                     const int32_t *comp_id, int n_comp, const double *W,
+                     const double *b, const double *target, int T,
+                     const double *x0, const double *v0, const double *C0,
+                     const double *F0, double *xT, double *vT, double *CT,
+                     double *FT, double *acts, const double *gxT,
+                     const double *gvT, const double *gCT, const double *gFT,
+                     double *gx0, double *gv0, double *gC0, double *gF0,
+                     double *gW, double *gb) {
+  if (!scene_ok(s) || T < 0 || n_comp < 1 || s->n_act < 1 || !comp_id)
+    return ORC_ERR_ARG;
+  int d = s->dim, nact = s->n_act, nz = d * (1 + 2 * n_comp);
+  long N = s->n_particles;
+  long *count = (long *)calloc((size_t)n_comp, sizeof(long));
+  if (!count) return ORC_ERR_OOM;
+  for (long p = 0; p < N; ++p) {
+    if (comp_id[p] >= n_comp) {
+      free(count);
+      return ORC_ERR_ARG;
+    }
+    if (comp_id[p] >= 0) count[comp_id[p]]++;
+  }
+  for (int c = 0; c < n_comp; ++c)
+    if (count[c] == 0) {
+      free(count);
+      return ORC_ERR_ARG;
+    }
+  size_t vs = (size_t)N * d, ms = (size_t)N * d * d;
+  size_t ss = 2 * vs + 2 * ms;
+  double *memo = (double *)malloc(sizeof(double) * ss * (size_t)(T + 1) + 8);
+  double *Z = (double *)malloc(sizeof(double) * (size_t)nz * (T + 1) + 8);
+  double *A = (double *)malloc(sizeof(double) * (size_t)nact * (T + 1) + 8);
+  if (!memo || !Z || !A) {
+    free(memo), free(Z), free(A), free(count);
+    return ORC_ERR_OOM;
+  }
+#define SX(n) (memo + (size_t)(n) * ss)
+#define SV(n) (SX(n) + vs)
+#define SC(n) (SX(n) + 2 * vs)
+#define SF(n) (SX(n) + 2 * vs + ms)
+  memcpy(SX(0), x0, sizeof(double) * vs);
+  memcpy(SV(0), v0, sizeof(double) * vs);
+  memcpy(SC(0), C0, sizeof(double) * ms);
+  memcpy(SF(0), F0, sizeof(double) * ms);
+  int rc = ORC_OK;
+  for (int n = 0; n < T && !rc; ++n) {
+    double *z = Z + (size_t)n * nz, *a = A + (size_t)n * nact;
+    ctrl_state_vector(s, comp_id, n_comp, count, target, SX(n), SV(n), z);
+    for (int j = 0; j < nact; ++j) {
+      double pre = b[j];
+      for (int i = 0; i < nz; ++i) pre += W[(size_t)j * nz + i] * z[i];
+      a[j] = tanh(pre);
+    }
+    rc = orc_step_fwd(s, act_id, a, SX(n), SV(n), SC(n), SF(n), SX(n + 1),
+                      SV(n + 1), SC(n + 1), SF(n + 1));
+  }
+  if (!rc) {
+    memcpy(xT, SX(T), sizeof(double) * vs);
+    memcpy(vT, SV(T), sizeof(double) * vs);
+    memcpy(CT, SC(T), sizeof(double) * ms);
+    memcpy(FT, SF(T), sizeof(double) * ms);
+    if (acts) memcpy(acts, A, sizeof(double) * (size_t)nact * T);
+  }
+  if (!rc && gxT) {
+    double *a1 = (double *)malloc(sizeof(double) * ss + 8);
+    double *a0 = (double *)malloc(sizeof(double) * ss + 8);
+    double *sb = (double *)malloc(sizeof(double) * nact + 8);
+    double *zb = (double *)malloc(sizeof(double) * nz + 8);
+    if (!a1 || !a0 || !sb || !zb) {
+      rc = ORC_ERR_OOM;
+    } else {
+      memcpy(a1, gxT, sizeof(double) * vs);
+      memcpy(a1 + vs, gvT, sizeof(double) * vs);
+      memcpy(a1 + 2 * vs, gCT, sizeof(double) * ms);
+      memcpy(a1 + 2 * vs + ms, gFT, sizeof(double) * ms);
+      memset(gW, 0, sizeof(double) * (size_t)nact * nz);
+      memset(gb, 0, sizeof(double) * nact);
+      for (int n = T - 1; n >= 0 && !rc; --n) {
+        const double *z = Z + (size_t)n * nz, *a = A + (size_t)n * nact;
+        memset(sb, 0, sizeof(double) * nact);
+        rc = orc_step_bwd(s, act_id, a, SX(n), SV(n), SC(n), SF(n), a1,
+                          a1 + vs, a1 + 2 * vs, a1 + 2 * vs + ms, a0, a0 + vs,
+                          a0 + 2 * vs, a0 + 2 * vs + ms, sb);
+        /* a = tanh(W z + b): dL/dpre = dL/da (1 - a^2) */
+        for (int i = 0; i < nz; ++i) zb[i] = 0.0;
+        for (int j = 0; j < nact; ++j) {
+          double g = sb[j] * (1.0 - a[j] * a[j]);
+          gb[j] += g;
+          for (int i = 0; i < nz; ++i) {
+            gW[(size_t)j * nz + i] += g * z[i];
+            zb[i] += W[(size_t)j * nz + i] * g;
+          }
+        }
+        /* z's means: each particle of component c gets dL/dz / N_c */
+        for (long p = 0; p < N; ++p) {
+          int c = comp_id[p];
+          if (c < 0) continue;
+          for (int k = 0; k < d; ++k) {
+            a0[(size_t)k * N + p] += zb[d + 2 * d * c + k] / (double)count[c];
+            a0[vs + (size_t)k * N + p] += zb[d + 2 * d * c + d + k] / (double)count[c];
+          }
+        }
+        double *t = a0;
+        a0 = a1;
+        a1 = t;
+      }
+      if (!rc) {
+        memcpy(gx0, a1, sizeof(double) * vs);
+        memcpy(gv0, a1 + vs, sizeof(double) * vs);
+        memcpy(gC0, a1 + 2 * vs, sizeof(double) * ms);
+        memcpy(gF0, a1 + 2 * vs + ms, sizeof(double) * ms);
+      }
+    }
+    free(a1), free(a0), free(sb), free(zb);
+  }
+#undef SX
+#undef SV
+#undef SC
+#undef SF
+  free(memo), free(Z), free(A), free(count);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* sinusoid actuation bank and its reverse                              */
 /* ------------------------------------------------------------------ */
 

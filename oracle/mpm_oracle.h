@@ -106,6 +106,27 @@ int orc_rollout(const orc_scene *s, const int32_t *act_id, int T,
                 const double *gCT, const double *gFT, double *gx0,
                 double *gv0, double *gC0, double *gF0, double *g_act);
 
+/* Closed-loop controller inside the rollout (section IV, Control): the
+ * actuation of substep n is a^n = tanh(W z^n + b) with the state vector
+ *   z^n = [target (d), then for each component c: the mean position and the
+ *          mean velocity of its particles in state n (d each)],
+ * nz = d (1 + 2 n_comp); comp_id[N] gives each particle's component (-1 =
+ * none; every component must hold a particle).  W is [n_act][nz] row-major,
+ * b [n_act], target [d].  Writes the final state and, if acts is non-NULL,
+ * acts[T][n_act].  When gxT is non-NULL the memo reverse pass also writes
+ * the adjoints of the initial state and dL/dW, dL/db (overwritten); the
+ * controller's dependence on state n adds (dL/dz) / N_c to the position and
+ * velocity adjoints of component c's particles. */
+int orc_rollout_ctrl(const orc_scene *s, const int32_t *act_id,
+                     const int32_t *comp_id, int n_comp, const double *W,
+                     const double *b, const double *target, int T,
+                     const double *x0, const double *v0, const double *C0,
+                     const double *F0, double *xT, double *vT, double *CT,
+                     double *FT, double *acts, const double *gxT,
+                     const double *gvT, const double *gCT, const double *gFT,
+                     double *gx0, double *gv0, double *gC0, double *gF0,
+                     double *gW, double *gb);
+
 /* Sinusoid actuation bank: act[n][j] = sum_k amp[j][k] sin(2 pi freq[k] t_n
  * + phase[j][k]) with t_n = n*dt. */
 void orc_act_bank_fwd(int T, int n_act, int n_freq, double dt,

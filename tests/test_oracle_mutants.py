@@ -42,6 +42,30 @@ MUTANTS = [
 ]
 
 
+# Mistakes in the controller rollout, caught by the controller pins.
+CTRL_MUTANTS = [
+    ("ctrl_tanh_derivative", "double g = sb[j] * (1.0 - a[j] * a[j]);", "double g = sb[j];"),
+    ("ctrl_mean_not_sum", "a0[(size_t)k * N + p] += zb[d + 2 * d * c + k] / (double)count[c];",
+     "a0[(size_t)k * N + p] += zb[d + 2 * d * c + k];"),
+    ("ctrl_velocity_slot", "z[d + 2 * d * c + d + a] += v[(size_t)a * N + p];",
+     "z[d + 2 * d * c + a] += v[(size_t)a * N + p];"),
+    ("ctrl_W_transposed", "zb[i] += W[(size_t)j * nz + i] * g;", "zb[i] += W[(size_t)i * nact + j] * g;"),
+]
+
+
+def _run_ctrl_pins():
+    from tests import test_oracle_ctrl as ctrl
+    failed = []
+    for name, fn in [("zero_gain", ctrl.test_zero_gain_controller_is_the_open_loop_rollout),
+                     ("means", ctrl.test_first_actuation_from_numpy_means),
+                     ("fd2", lambda: ctrl.test_controller_gradients_match_central_differences(2))]:
+        try:
+            fn()
+        except (AssertionError, oracle.OracleError, ValueError):
+            failed.append(name)
+    return failed
+
+
 def _run_pins():
     """Run a fast subset of the pins; return the names of those that fail."""
     failed = []
@@ -84,3 +108,17 @@ def test_mutant_is_caught(name, old, new, tmp_path):
     with oracle.use_library(str(lib)):
         failed = _run_pins()
     assert failed, f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("name,old,new", CTRL_MUTANTS, ids=[m[0] for m in CTRL_MUTANTS])
+def test_controller_mutant_is_caught(name, old, new, tmp_path):
+    assert SRC.count(old) == 1, f"mutation anchor for {name} not unique"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(old, new))
+    hdr = os.path.join(os.path.dirname(oracle.__file__), "mpm_oracle.h")
+    (tmp_path / "mpm_oracle.h").write_text(open(hdr).read())
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", *oracle.CFLAGS, "-o", str(lib), str(src), "-lm"], check=True)
+    with oracle.use_library(str(lib)):
+        failed = _run_ctrl_pins()
+    assert failed, f"mutant {name} passed every controller pin"
