@@ -168,6 +168,45 @@ int mpm_rollout(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
 int mpm_rollout_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
                          float *g_act);
 
+/* Closed-loop controller (section IV, Control: a neural-network controller
+ * fed with the positions and velocities of the robot's parts, here one dense
+ * layer with tanh).  At every substep n of a rollout
+ *   z^n = [target, for each component c: mean_{p in c} x_p^n,
+ *                                        mean_{p in c} v_p^n]   (d (1 + 2 n_comp))
+ *   a^n = tanh(W z^n + b)                                       ([n_act])
+ * and a^n is the actuation s^n of that substep.  All pointers DEVICE:
+ * comp_id int32 [N] (caller order; -1 = in no component; every component
+ * needs at least one particle), W [n_act][d (1 + 2 n_comp)] row-major,
+ * b [n_act], target [d].  Copied at the start of the rollout. */
+typedef struct mpm_controller {
+  int32_t n_comp;   /* 1 .. 48 / d */
+  int32_t reserved;
+  const int32_t *comp_id;
+  const float *W, *b, *target;
+} mpm_controller;
+
+/* mpm_rollout with the actuation from the controller `ctl` instead of a
+ * schedule.  One scene per context, 1 <= n_act <= 64.  `act` (DEVICE
+ * [T][n_act], nullable) receives the actuation the controller produced.
+ * With `gT` the reverse pass runs at once: `g0` = dL/dS^0 including the
+ * controller's dependence on the state, `g_act` [T][n_act] = dL/ds^n
+ * (partial, state held fixed), `g_W` [n_act][nz] and `g_b` [n_act] =
+ * dL/dW, dL/db (all DEVICE, overwritten, the last three nullable).  The
+ * G2P + P2G fusion of 3D rollouts is not used (a^{n+1} needs the means of
+ * S^{n+1} first).  Synchronises to read the component ids.  Errors:
+ * MPM_ERR_ARG (limits above, bad ids, empty component), MPM_ERR_OOM, the
+ * device errors. */
+int mpm_rollout_ctrl(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
+                     const mpm_controller *ctl, mpm_state *sT, float *act,
+                     const mpm_state *gT, mpm_state *g0, float *g_act,
+                     float *g_W, float *g_b);
+
+/* Reverse pass over the tape of the last mpm_rollout_ctrl (MPM_ERR_STATE if
+ * the last rollout had no controller).  mpm_rollout_backward on such a tape
+ * returns the same g0 and g_act without dL/dW, dL/db. */
+int mpm_rollout_ctrl_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
+                              float *g_act, float *g_W, float *g_b);
+
 /* Copy the grid of the last mpm_step_forward (DEVICE, caller-owned,
  * nullable): m [G], p [d][G], v [d][G] with G the total node count (scenes
  * concatenated in order, each n_s^d nodes).  Stream-ordered copy. */

@@ -43,11 +43,18 @@ class State(ctypes.Structure):
                 ("C", ctypes.c_void_p), ("F", ctypes.c_void_p)]
 
 
+class Controller(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("comp_id", ctypes.c_void_p), ("W", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("target", ctypes.c_void_p)]
+
+
 EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_step_forward", "mpm_step_backward", "mpm_rollout",
            "mpm_rollout_backward", "mpm_get_grid", "mpm_act_bank_forward",
            "mpm_act_bank_backward", "mpm_sync_errors", "mpm_strerror",
-           "mpm_profile", "mpm_profile_read"]
+           "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
+           "mpm_rollout_ctrl_backward"]
 
 KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
 
@@ -76,6 +83,9 @@ def lib():
     L.mpm_step_backward.argtypes = [vp, sp, vp, sp, sp, vp]
     L.mpm_rollout.argtypes = [vp, i32, i32, sp, vp, sp, sp, sp, vp]
     L.mpm_rollout_backward.argtypes = [vp, sp, sp, vp]
+    L.mpm_rollout_ctrl.argtypes = [vp, i32, i32, sp, ctypes.POINTER(Controller), sp, vp,
+                                   sp, sp, vp, vp, vp]
+    L.mpm_rollout_ctrl_backward.argtypes = [vp, sp, sp, vp, vp, vp]
     L.mpm_get_grid.argtypes = [vp, vp, vp, vp]
     L.mpm_act_bank_forward.argtypes = [vp, i32, i32, i32, ctypes.c_float,
                                        vp, vp, vp, vp]

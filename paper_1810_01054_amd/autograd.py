@@ -3,6 +3,8 @@ gradient evaluation, here a library-owned tape with checkpoint + recompute).
 
 ``rollout(sim, state0, act, T, ckpt_k)`` returns the final state; its
 backward runs ``mpm_rollout_backward`` over the tape of that same rollout.
+``rollout_ctrl`` is the closed-loop form (actuation from a tanh layer over
+the component means of the state, mpm_rollout_ctrl).
 A context keeps one tape, so a second rollout on the same simulator makes
 the first one's backward raise instead of returning wrong gradients.
 """
@@ -38,6 +40,31 @@ class MPMRolloutFn(torch.autograd.Function):
         return (None, None, None, *g0, g_act if ctx.has_act else None)
 
 
+class MPMRolloutCtrlFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, comp_id, n_comp: int,
+                x0, v0, C0, F0, W, b, target):
+        sT, act = sim.rollout_ctrl(tuple(t.contiguous() for t in (x0, v0, C0, F0)), T,
+                                   comp_id, n_comp, W.contiguous(), b.contiguous(),
+                                   target.contiguous(), ckpt_k)
+        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
+        ctx.sim, ctx.T, ctx.gen, ctx.nz = sim, T, sim._tape_gen, W.shape[1]
+        ctx.mark_non_differentiable(act)
+        return (*sT, act)
+
+    @staticmethod
+    def backward(ctx, gx, gv, gC, gF, _gact):
+        sim = ctx.sim
+        if getattr(sim, "_tape_gen", None) != ctx.gen:
+            raise RuntimeError("the simulator ran another rollout since this one; "
+                               "its tape is gone (use one Simulator per live graph)")
+        ref = sim.empty_state()
+        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
+                  for t, r in zip((gx, gv, gC, gF), ref))
+        g0, _, g_W, g_b = sim.rollout_ctrl_backward(g, ctx.T, ctx.nz)
+        return (None, None, None, None, None, *g0, g_W, g_b, None)
+
+
 class ActBankFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, T: int, dt: float, freq, amp, phase):
@@ -58,6 +85,16 @@ def rollout(sim: Simulator, state0, act: Optional[torch.Tensor], T: int,
     """Differentiable T-substep rollout: returns (xT, vT, CT, FT)."""
     x0, v0, C0, F0 = state0
     return MPMRolloutFn.apply(sim, T, ckpt_k, x0, v0, C0, F0, act)
+
+
+def rollout_ctrl(sim: Simulator, state0, T: int, comp_id, n_comp: int, W, b, target,
+                 ckpt_k: int = 32):
+    """Differentiable closed-loop rollout a^n = tanh(W z^n + b): returns
+    (xT, vT, CT, FT, act) with gradients to the initial state, W and b
+    (act, the controller's output, carries none)."""
+    x0, v0, C0, F0 = state0
+    return MPMRolloutCtrlFn.apply(sim, T, ckpt_k, comp_id, n_comp, x0, v0, C0, F0, W, b,
+                                  target)
 
 
 def act_bank(T: int, dt: float, freq, amp, phase):

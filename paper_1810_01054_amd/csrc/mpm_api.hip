@@ -18,6 +18,13 @@ using namespace mpm;
 
 namespace {
 
+// controller limits: 2 d n_comp state entries (component means) at most
+// CTL_MAX_ZS, at most CTL_MAX_ACT actuators
+constexpr int CTL_MAX_ZS = 96;
+constexpr int CTL_MAX_COMP = CTL_MAX_ZS / 4;
+constexpr int CTL_MAX_ACT = 64;
+constexpr int CTL_MAX_NZ = 3 + CTL_MAX_ZS;
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -39,11 +46,11 @@ struct mpm_ctx {
 
   // captured inner loops of rollouts (forward, reverse)
   struct GraphKey {
-    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0;
+    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0, ctl = 0;
     const void *p[8] = {};
     bool operator==(const GraphKey &o) const {
       if (T != o.T || k != o.k || memo != o.memo || grids_all != o.grids_all ||
-          sorted != o.sorted || nch != o.nch || nne != o.nne)
+          sorted != o.sorted || nch != o.nch || nne != o.nne || ctl != o.ctl)
         return false;
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
@@ -109,6 +116,21 @@ struct mpm_ctx {
     float *pp = nullptr;      // two ping-pong states
     float *adj = nullptr;     // two adjoint states
   } tape;
+
+  // closed-loop controller of the current tape (one scene; section IV)
+  struct Ctl {
+    int on = 0, n_comp = 0, nz = 0;
+    int *comp = nullptr;       // component of each particle (tape order) [N]
+    float *inv_cnt = nullptr;  // [CTL_MAX_COMP]
+    float *W = nullptr, *b = nullptr, *target = nullptr;  // copies
+    float *partial = nullptr;  // [ceil(N / 256)][2 d n_comp]
+    double *sums = nullptr;    // [CTL_MAX_ZS]
+    unsigned *done = nullptr;  // reduction counter (zero between launches)
+    float *zs = nullptr;       // [CTL_MAX_ZS]
+    double *gW = nullptr, *gb = nullptr;  // FP64 accumulators
+    float *Z = nullptr;        // tape of z^n [T][nz]
+    int64_t Z_cap = 0;
+  } ctl;
 
   // kernel timing (mpm_profile)
   struct Prof {
@@ -619,7 +641,60 @@ mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
   k.p[3] = t.pp;
   k.p[4] = t.adj;
   k.p[5] = c->gact;
+  k.p[7] = c->ctl.on ? c->ctl.Z : nullptr;
+  k.ctl = c->ctl.on ? c->ctl.nz : 0;
   return k;
+}
+
+// Controller at substep n: component means of state n -> z^n (tape) ->
+// a^n = tanh(W z^n + b) into the tape's actuation row n.
+int ctl_forward(mpm_ctx *c, const State &s, int n) {
+  const auto &k = c->ctl;
+  CtlArgs a;
+  a.dim = c->dim;
+  a.N = (int)c->N;
+  a.n_comp = k.n_comp;
+  a.n_act = c->n_act;
+  a.nz = k.nz;
+  a.comp = k.comp;
+  a.inv_cnt = k.inv_cnt;
+  a.x = s.x;
+  a.v = s.v;
+  a.ld = (int)c->N;
+  a.partial = k.partial;
+  a.sums = k.sums;
+  a.done = k.done;
+  a.W = k.W;
+  a.b = k.b;
+  a.target = k.target;
+  a.act = c->tape.act + (int64_t)n * c->n_act;
+  a.z = k.Z + (int64_t)n * k.nz;
+  return launch_ctl_forward(a, c->stream) ? MPM_ERR_HIP : MPM_OK;
+}
+
+// Reverse of the controller at substep n: adds its term to the adjoint of
+// state n (g) and to dL/dW, dL/db; sbar = dL/ds^n from the substep's reverse.
+int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g) {
+  const auto &k = c->ctl;
+  CtlAdjArgs a;
+  a.dim = c->dim;
+  a.N = (int)c->N;
+  a.n_comp = k.n_comp;
+  a.n_act = c->n_act;
+  a.nz = k.nz;
+  a.comp = k.comp;
+  a.inv_cnt = k.inv_cnt;
+  a.W = k.W;
+  a.act = c->tape.act + (int64_t)n * c->n_act;
+  a.z = k.Z + (int64_t)n * k.nz;
+  a.sbar = sbar;
+  a.gW = k.gW;
+  a.gb = k.gb;
+  a.zs = k.zs;
+  a.gx = g.x;
+  a.gv = g.v;
+  a.ld = (int)c->N;
+  return launch_ctl_adjoint(a, c->stream) ? MPM_ERR_HIP : MPM_OK;
 }
 
 int rollout_forward(mpm_ctx *c, const Layout &L) {
@@ -629,13 +704,16 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   const bool tiles = c->tape.sorted;
   // 3D binned rollouts with the sorted scatter fuse each G2P with the next
   // substep's P2G (state n+1 goes from registers to the scatter)
-  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3;
+  // (not with a closed-loop controller: the actuation of substep n+1 needs
+  // the component means of state n+1 first)
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on;
   auto act_of = [&](int n) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };
   for (int n = 0; n < L.T; ++n) {
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
+    if (c->ctl.on) RC(ctl_forward(c, s, n));
     if (!fuse || n == 0)
       RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp));
     if (c->tape.grids_all) {
@@ -668,6 +746,10 @@ int rollout_backward_core(mpm_ctx *c) {
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   const int64_t nga = (int64_t)t.T * c->n_act;
   if (nga > 0) RC(launch_fill_f64(c->gact, nga, c->stream));
+  if (c->ctl.on) {
+    RC(launch_fill_f64(c->ctl.gW, (int64_t)c->n_act * c->ctl.nz, c->stream));
+    RC(launch_fill_f64(c->ctl.gb, c->n_act, c->stream));
+  }
   const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
   const int seglen = t.memo ? 1 : t.k;
   const bool keep = !t.memo && t.grids_all;  // stored grids: G2P-only recompute
@@ -741,6 +823,8 @@ int rollout_backward_core(mpm_ctx *c) {
       const float *g = Gr(n0, n);
       RC(bwd_step(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G, cs(A1),
                   A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
+      // a^n = tanh(W z(S^n) + b): its dependence on state n
+      if (c->ctl.on) RC(ctl_adjoint(c, n, c->gact + (int64_t)n * c->n_act, A0));
       std::swap(A0, A1);
     }
     if (overlap) RC(hip_ok(hipEventRecord(c->ev_adj, c->stream)));
@@ -749,7 +833,7 @@ int rollout_backward_core(mpm_ctx *c) {
 }
 
 int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
-                     float *g_act) {
+                     float *g_act, float *g_W = nullptr, float *g_b = nullptr) {
   auto &t = c->tape;
   const int64_t sf = c->state_floats();
   const State A_in = state_at(c, t.adj);
@@ -763,6 +847,10 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   else RC(copy_state(c, ms(A_out), st(*g0)));
   if (g_act && nga > 0)
     RC(launch_gact_store(c->gact, g_act, nga, 0, c->stream));
+  if (c->ctl.on && g_W)
+    RC(launch_gact_store(c->ctl.gW, g_W, (int64_t)c->n_act * c->ctl.nz, 0, c->stream));
+  if (c->ctl.on && g_b)
+    RC(launch_gact_store(c->ctl.gb, g_b, c->n_act, 0, c->stream));
   return MPM_OK;
 }
 
@@ -814,6 +902,18 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_act_sorted, c->stream);
   dfree(c->d_chunks_sorted, c->stream);
   dfree(c->d_part, c->stream);
+  dfree(c->ctl.comp, c->stream);
+  dfree(c->ctl.inv_cnt, c->stream);
+  dfree(c->ctl.W, c->stream);
+  dfree(c->ctl.b, c->stream);
+  dfree(c->ctl.target, c->stream);
+  dfree(c->ctl.partial, c->stream);
+  dfree(c->ctl.sums, c->stream);
+  dfree(c->ctl.done, c->stream);
+  dfree(c->ctl.zs, c->stream);
+  dfree(c->ctl.gW, c->stream);
+  dfree(c->ctl.gb, c->stream);
+  dfree(c->ctl.Z, c->stream);
   dfree(c->d_tile_flag, c->stream);
   dfree(c->d_tile_pos, c->stream);
   dfree(c->d_tile_list, c->stream);
@@ -1110,16 +1210,78 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
   return MPM_OK;
 }
 
-int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
-                const float *act, mpm_state *sT, const mpm_state *gT,
-                mpm_state *g0, float *g_act) {
-  RC(check_ctx(c));
-  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) ||
-      (c->n_act && T > 0 && !act) || (gT && !state_ok(c, gT)) ||
-      (gT && !state_ok(c, g0)))
-    return MPM_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Controller set-up for a rollout of T substeps: checks the component ids
+// (on the host), copies W, b, target into library buffers and the ids into
+// the tape's particle order (after binning).
+int ctl_setup(mpm_ctx *c, const mpm_controller *u, int T) {
+  auto &k = c->ctl;
+  const int d = c->dim, N = (int)c->N;
+  std::vector<int32_t> h((size_t)N);
+  RC(hip_ok(hipMemcpyAsync(h.data(), u->comp_id, sizeof(int32_t) * N,
+                           hipMemcpyDeviceToHost, c->stream)));
+  RC(hip_ok(hipStreamSynchronize(c->stream)));
+  std::vector<int64_t> cnt((size_t)u->n_comp, 0);
+  for (int p = 0; p < N; ++p) {
+    const int q = h[(size_t)p];
+    if (q < -1 || q >= u->n_comp) return MPM_ERR_ARG;
+    if (q >= 0) ++cnt[(size_t)q];
+  }
+  float inv[CTL_MAX_COMP] = {};
+  for (int q = 0; q < u->n_comp; ++q) {
+    if (cnt[(size_t)q] == 0) return MPM_ERR_ARG;  // a mean over no particle
+    inv[q] = (float)(1.0 / (double)cnt[(size_t)q]);
+  }
+  hipStream_t s = c->stream;
+  if (!k.comp) {
+    const int64_t nwg = (c->N + 255) / 256;
+    RC(dmalloc(&k.comp, c->N, s));
+    RC(dmalloc(&k.inv_cnt, CTL_MAX_COMP, s));
+    RC(dmalloc(&k.W, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
+    RC(dmalloc(&k.b, CTL_MAX_ACT, s));
+    RC(dmalloc(&k.target, 3, s));
+    RC(dmalloc(&k.partial, nwg * CTL_MAX_ZS, s));
+    RC(dmalloc(&k.sums, CTL_MAX_ZS, s));
+    RC(dmalloc(&k.done, 1, s));
+    RC(launch_fill_i32((int *)k.done, 1, s));
+    RC(dmalloc(&k.zs, CTL_MAX_ZS, s));
+    RC(dmalloc(&k.gW, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
+    RC(dmalloc(&k.gb, CTL_MAX_ACT, s));
+  }
+  k.n_comp = u->n_comp;
+  k.nz = d * (1 + 2 * u->n_comp);
+  if ((int64_t)T * k.nz > k.Z_cap) {
+    dfree(k.Z, s);
+    k.Z_cap = 0;
+    RC(dmalloc(&k.Z, (int64_t)T * k.nz, s));
+    k.Z_cap = (int64_t)T * k.nz;
+  }
+  RC(hip_ok(hipMemcpyAsync(k.inv_cnt, inv, sizeof(inv), hipMemcpyHostToDevice, s)));
+  RC(hip_ok(hipMemcpyAsync(k.W, u->W, sizeof(float) * c->n_act * k.nz,
+                           hipMemcpyDeviceToDevice, s)));
+  RC(hip_ok(hipMemcpyAsync(k.b, u->b, sizeof(float) * c->n_act,
+                           hipMemcpyDeviceToDevice, s)));
+  RC(hip_ok(hipMemcpyAsync(k.target, u->target, sizeof(float) * d,
+                           hipMemcpyDeviceToDevice, s)));
+  if (c->tape.sorted)
+    RC(launch_permute_i32(u->comp_id, k.comp, c->d_perm, N, s));
+  else
+    RC(hip_ok(hipMemcpyAsync(k.comp, u->comp_id, sizeof(int32_t) * N,
+                             hipMemcpyDeviceToDevice, s)));
+  RC(hip_ok(hipStreamSynchronize(s)));  // `inv` is host memory
+  k.on = 1;
+  return MPM_OK;
+}
+
+// Body shared by the open-loop and closed-loop rollouts (arguments checked).
+int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
+                const float *act, const mpm_controller *ctl, mpm_state *sT) {
   auto &t = c->tape;
   t.valid = 0;
+  c->ctl.on = 0;
   const int memo = ckpt_k == 0;
   const int k = memo ? 1 : std::min(ckpt_k, std::max(T, 1));
   const int ncp = memo ? T + 1 : (T + k - 1) / k + 1;
@@ -1135,7 +1297,7 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   t.memo = memo;
   t.grids_all = grids_all;
   t.sorted = c->sort && c->N > 0;
-  if (c->n_act && T > 0)
+  if (!ctl && c->n_act && T > 0)
     RC(hip_ok(hipMemcpyAsync(t.act, act, sizeof(float) * T * c->n_act,
                              hipMemcpyDeviceToDevice, c->stream)));
   const Layout L{T, k, memo, ncp};
@@ -1146,6 +1308,7 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   } else {
     RC(copy_state(c, *s0, S0));
   }
+  if (ctl) RC(ctl_setup(c, ctl, T));
   // the step calls leave their grid in gm/gp; rollouts start from zero
   RC(launch_fill_f32(c->gm, c->G, c->stream));
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
@@ -1154,8 +1317,52 @@ int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   if (t.sorted) RC(permute_state(c, ms(ST), st(*sT), 1));
   else RC(copy_state(c, ms(ST), st(*sT)));
   t.valid = 1;
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
+                const float *act, mpm_state *sT, const mpm_state *gT,
+                mpm_state *g0, float *g_act) {
+  RC(check_ctx(c));
+  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) ||
+      (c->n_act && T > 0 && !act) || (gT && !state_ok(c, gT)) ||
+      (gT && !state_ok(c, g0)))
+    return MPM_ERR_ARG;
+  RC(rollout_run(c, T, ckpt_k, s0, act, nullptr, sT));
   if (gT) return rollout_backward(c, gT, g0, g_act);
   return MPM_OK;
+}
+
+int mpm_rollout_ctrl(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
+                     const mpm_controller *ctl, mpm_state *sT, float *act,
+                     const mpm_state *gT, mpm_state *g0, float *g_act,
+                     float *g_W, float *g_b) {
+  RC(check_ctx(c));
+  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) || !ctl ||
+      (gT && !state_ok(c, gT)) || (gT && !state_ok(c, g0)))
+    return MPM_ERR_ARG;
+  if (c->n_scenes != 1 || c->N < 1 || c->n_act < 1 || c->n_act > CTL_MAX_ACT ||
+      ctl->n_comp < 1 || 2 * c->dim * ctl->n_comp > CTL_MAX_ZS || !ctl->comp_id ||
+      !ctl->W || !ctl->b || !ctl->target)
+    return MPM_ERR_ARG;
+  RC(rollout_run(c, T, ckpt_k, s0, nullptr, ctl, sT));
+  if (act && T > 0)
+    RC(hip_ok(hipMemcpyAsync(act, c->tape.act, sizeof(float) * T * c->n_act,
+                             hipMemcpyDeviceToDevice, c->stream)));
+  if (gT) return rollout_backward(c, gT, g0, g_act, g_W, g_b);
+  return MPM_OK;
+}
+
+int mpm_rollout_ctrl_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
+                              float *g_act, float *g_W, float *g_b) {
+  RC(check_ctx(c));
+  if (!c->tape.valid || !c->ctl.on) return MPM_ERR_STATE;
+  if (!state_ok(c, gT) || !state_ok(c, g0)) return MPM_ERR_ARG;
+  return rollout_backward(c, gT, g0, g_act, g_W, g_b);
 }
 
 int mpm_rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,

@@ -245,6 +245,34 @@ int launch_permute_rows(const float *in, float *out, const int *perm, int N,
                         int ld, int ncomp, int scatter, hipStream_t st);
 int launch_permute_i32(const int *in, int *out, const int *perm, int N,
                        hipStream_t st);
+// Closed-loop controller (section IV, Control), one scene: a = tanh(W z + b),
+// z = [target, mean x and mean v of each component].  nzs = 2 d n_comp.
+struct CtlArgs {
+  int dim, N, n_comp, n_act, nz;
+  const int *comp;        // component of each particle (binned order), -1 none
+  const float *inv_cnt;   // [n_comp] 1 / particles of the component
+  const float *x, *v;     // state n ([d][ld])
+  int ld;
+  float *partial;         // [n_wg][nzs] per-workgroup sums
+  double *sums;           // [nzs]
+  unsigned *done;         // workgroups of the reduction finished (reset by the last)
+  const float *W, *b, *target;  // [n_act][nz], [n_act], [d]
+  float *act;             // out: [n_act] actuation of this substep
+  float *z;               // out: [nz] state vector of this substep (tape)
+};
+int launch_ctl_forward(const CtlArgs &a, hipStream_t st);
+struct CtlAdjArgs {
+  int dim, N, n_comp, n_act, nz;
+  const int *comp;
+  const float *inv_cnt;
+  const float *W, *act, *z;  // W, a^n and z^n of this substep
+  const double *sbar;        // [n_act] dL/ds^n
+  double *gW, *gb;           // accumulated [n_act][nz], [n_act]
+  float *zs;                 // [nzs] dL/dz of the state part / N_c
+  float *gx, *gv;            // adjoint of state n ([d][ld]), += broadcast
+  int ld;
+};
+int launch_ctl_adjoint(const CtlAdjArgs &a, hipStream_t st);
 int launch_gact_store(const double *src, float *dst, int64_t n, int accumulate,
                       hipStream_t st);
 int launch_act_bank_fwd(int T, int n_act, int n_freq, float dt,

@@ -2379,6 +2379,137 @@ __global__ __launch_bounds__(256) void k_fill(T *p, int64_t n) {
   for (int64_t k = i; k < n; k += stride) p[k] = T(0);
 }
 
+// ---------------------------------------------------------------------------
+// closed-loop controller a = tanh(W z + b) (section IV, Control)
+// ---------------------------------------------------------------------------
+
+constexpr int CTL_MAX_NZS = 96;  // 2 d n_comp <= 96 (n_comp <= 16 in 3D)
+
+// Per-workgroup sums of x and v over each component (particles [256 b,
+// 256 b + 256)): each wave reduces the lanes of one component at a time with
+// shuffles; the four waves' sums are added by thread and stored.
+__global__ __launch_bounds__(256) void k_ctl_partial(CtlArgs A) {
+  __shared__ float s_w[4][CTL_MAX_NZS];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int d = A.dim, nzs = 2 * d * A.n_comp;
+  for (int i = lane; i < nzs; i += 64) s_w[wave][i] = 0.0f;
+  const int p = blockIdx.x * 256 + t;
+  const int c = p < A.N ? A.comp[p] : -1;
+  float val[6] = {0, 0, 0, 0, 0, 0};
+  if (c >= 0)
+    for (int a = 0; a < d; ++a) {
+      val[a] = A.x[a * A.ld + p];
+      val[3 + a] = A.v[a * A.ld + p];
+    }
+  unsigned long long todo = __ballot(c >= 0);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    const int cc = __shfl(c, src, 64);
+    const unsigned long long m = __ballot(c == cc);
+    float r[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float x = c == cc ? val[k] : 0.0f;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      r[k] = x;
+    }
+    if (lane == 0)
+      for (int a = 0; a < d; ++a) {
+        s_w[wave][2 * d * cc + a] = r[a];
+        s_w[wave][2 * d * cc + d + a] = r[3 + a];
+      }
+    todo &= ~m;
+  }
+  __syncthreads();
+  for (int i = t; i < nzs; i += 256)
+    A.partial[(int64_t)blockIdx.x * nzs + i] =
+        (s_w[0][i] + s_w[1][i]) + (s_w[2][i] + s_w[3][i]);
+}
+
+// One workgroup per component value: the sum over all workgroup partials
+// (FP64).  The last workgroup to finish evaluates the controller.
+__global__ __launch_bounds__(256) void k_ctl_reduce(CtlArgs A, int n_wg) {
+  __shared__ double s_red[256];
+  __shared__ bool s_last;
+  __shared__ double s_z[CTL_MAX_NZS + 3];
+  const int t = threadIdx.x, d = A.dim, nzs = 2 * d * A.n_comp;
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int w = t; w < n_wg; w += 256) acc += (double)A.partial[(int64_t)w * nzs + i];
+  s_red[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) s_red[t] += s_red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    A.sums[i] = s_red[0];
+    __threadfence();
+    s_last = atomicAdd(A.done, 1u) == (unsigned)(nzs - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // z = [target, per component: mean x, mean v]; a = tanh(W z + b)
+  for (int k = t; k < A.nz; k += 256) {
+    double zk;
+    if (k < d) {
+      zk = A.target[k];
+    } else {
+      const int c = (k - d) / (2 * d);
+      zk = ((volatile double *)A.sums)[k - d] * (double)A.inv_cnt[c];
+    }
+    s_z[k] = zk;
+    A.z[k] = (float)zk;
+  }
+  __syncthreads();
+  for (int j = t; j < A.n_act; j += 256) {
+    float pre = A.b[j];
+    for (int k = 0; k < A.nz; ++k) pre += A.W[j * A.nz + k] * (float)s_z[k];
+    A.act[j] = tanhf(pre);
+  }
+  if (t == 0) *A.done = 0u;  // for the next substep (stream-ordered)
+}
+
+// Reverse of the controller at one substep (one workgroup): g = dL/ds (1 -
+// a^2); dL/dW += g z^T, dL/db += g; the state part of W^T g, divided by each
+// component's particle count, for the broadcast below.
+__global__ __launch_bounds__(256) void k_ctl_adj(CtlAdjArgs A) {
+  __shared__ double s_g[64];
+  const int t = threadIdx.x, d = A.dim;
+  for (int j = t; j < A.n_act; j += 256) {
+    const double a = A.act[j];
+    s_g[j] = A.sbar[j] * (1.0 - a * a);
+    A.gb[j] += s_g[j];
+  }
+  __syncthreads();
+  for (int e = t; e < A.n_act * A.nz; e += 256) {
+    const int j = e / A.nz, k = e % A.nz;
+    A.gW[e] += s_g[j] * (double)A.z[k];
+  }
+  for (int k = d + t; k < A.nz; k += 256) {
+    double s = 0.0;
+    for (int j = 0; j < A.n_act; ++j) s += (double)A.W[j * A.nz + k] * s_g[j];
+    const int c = (k - d) / (2 * d);
+    A.zs[k - d] = (float)(s * (double)A.inv_cnt[c]);
+  }
+}
+
+// Adds the controller's dL/dz / N_c to the x and v adjoints of every
+// particle of a component.
+__global__ __launch_bounds__(256) void k_ctl_broadcast(CtlAdjArgs A) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= A.N) return;
+  const int c = A.comp[p];
+  if (c < 0) return;
+  const int d = A.dim;
+  for (int a = 0; a < d; ++a) {
+    A.gx[a * A.ld + p] += A.zs[2 * d * c + a];
+    A.gv[a * A.ld + p] += A.zs[2 * d * c + d + a];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_gact_store(const double *src,
                                                     float *dst, int64_t n,
                                                     int accumulate) {
@@ -2601,6 +2732,24 @@ int launch_permute_rows(const float *in, float *out, const int *perm, int N,
 int launch_permute_i32(const int *in, int *out, const int *perm, int N,
                        hipStream_t st) {
   MPM_LAUNCH(k_permute_i32, blocks_for(N), 256, st, in, out, perm, N);
+}
+
+int launch_ctl_forward(const CtlArgs &a, hipStream_t st) {
+  const int n_wg = (a.N + 255) / 256;
+  const int nzs = 2 * a.dim * a.n_comp;
+  if (n_wg == 0 || nzs == 0 || nzs > CTL_MAX_NZS || a.n_act > 64) return -1;
+  hipLaunchKernelGGL(k_ctl_partial, dim3(n_wg), dim3(256), 0, st, a);
+  int rc = hip_rc(hipGetLastError());
+  if (rc) return rc;
+  MPM_LAUNCH(k_ctl_reduce, nzs, 256, st, a, n_wg);
+}
+
+int launch_ctl_adjoint(const CtlAdjArgs &a, hipStream_t st) {
+  if (a.n_act > 64) return -1;
+  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(256), 0, st, a);
+  int rc = hip_rc(hipGetLastError());
+  if (rc) return rc;
+  MPM_LAUNCH(k_ctl_broadcast, (a.N + 255) / 256, 256, st, a);
 }
 
 int launch_gact_store(const double *src, float *dst, int64_t n, int accumulate,

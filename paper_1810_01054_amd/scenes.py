@@ -347,3 +347,29 @@ def shuffled(scene: Scene, seed: int) -> Scene:
     out.F = np.ascontiguousarray(scene.F[:, perm])
     out.act_id = np.ascontiguousarray(scene.act_id[perm])
     return out
+
+
+def controller_params(scene: Scene, seed: int, n_comp: Optional[int] = None,
+                      w_scale: float = 0.6, b_scale: float = 0.3):
+    """Seeded parameters of a closed-loop controller a = tanh(W z + b) over
+    ``scene``: components (the robot's parts whose mean position and velocity
+    the controller reads) are the actuator groups when ``n_comp`` is None
+    (passive particles in none), else uniform draws over n_comp components
+    with every component non-empty and the last particle in none.
+    W ~ N(0, w_scale^2) of shape [n_act][d (1 + 2 n_comp)], b ~ N(0,
+    b_scale^2), target ~ U[0.3, 0.7)^d.  Returns (comp_id int32 [N], n_comp,
+    W, b, target), all FP32."""
+    rng = np.random.default_rng(seed)
+    N, d = scene.n_particles, scene.dim
+    if n_comp is None:
+        comp = np.asarray(scene.act_id, np.int32).copy()
+        n_comp = scene.n_act
+    else:
+        comp = rng.integers(0, n_comp, size=N).astype(np.int32)
+        comp[:n_comp] = np.arange(n_comp, dtype=np.int32)
+        comp[-1] = -1
+    nz = d * (1 + 2 * n_comp)
+    W = (rng.normal(size=(scene.n_act, nz)) * w_scale).astype(F32)
+    b = (rng.normal(size=scene.n_act) * b_scale).astype(F32)
+    target = rng.uniform(0.3, 0.7, size=d).astype(F32)
+    return comp, n_comp, W, b, target

@@ -168,6 +168,55 @@ class Simulator:
                                           _ptr(g_act)), "mpm_rollout_backward")
         return g0, g_act
 
+    def _controller(self, comp_id: torch.Tensor, n_comp: int, W: torch.Tensor,
+                    b: torch.Tensor, target: torch.Tensor) -> _lib.Controller:
+        nz = self.dim * (1 + 2 * n_comp)
+        if comp_id.dtype != torch.int32 or not comp_id.is_cuda or \
+                not comp_id.is_contiguous() or tuple(comp_id.shape) != (self.N,):
+            raise ValueError(f"comp_id must be a contiguous cuda int32 tensor of shape ({self.N},)")
+        _check_tensor(W, (self.n_act, nz), "W")
+        _check_tensor(b, (self.n_act,), "b")
+        _check_tensor(target, (self.dim,), "target")
+        return _lib.Controller(n_comp, 0, comp_id.data_ptr(), W.data_ptr(), b.data_ptr(),
+                               target.data_ptr())
+
+    def rollout_ctrl(self, s0: StateT, T: int, comp_id: torch.Tensor, n_comp: int,
+                     W: torch.Tensor, b: torch.Tensor, target: torch.Tensor,
+                     ckpt_k: int = 0, gT: Optional[StateT] = None):
+        """Closed-loop rollout a^n = tanh(W z^n + b) (mpm_rollout_ctrl).
+        Returns (sT, act); with gT (sT, act, g0, g_act, g_W, g_b)."""
+        self._sync_stream()
+        ctl = self._controller(comp_id, n_comp, W, b, target)
+        sT = self.empty_state()
+        act = torch.empty(T, self.n_act, device="cuda")
+        a0, aT = self._state(s0, "s0"), self._state(sT, "sT")
+        if gT is None:
+            check(self.L.mpm_rollout_ctrl(self.ctx, T, ckpt_k, ctypes.byref(a0),
+                                          ctypes.byref(ctl), ctypes.byref(aT), _ptr(act),
+                                          None, None, None, None, None), "mpm_rollout_ctrl")
+            return sT, act
+        g0 = self.empty_state()
+        g_act = torch.empty(T, self.n_act, device="cuda")
+        g_W, g_b = torch.empty_like(W), torch.empty_like(b)
+        gg, g00 = self._state(gT, "gT"), self._state(g0, "g0")
+        check(self.L.mpm_rollout_ctrl(self.ctx, T, ckpt_k, ctypes.byref(a0), ctypes.byref(ctl),
+                                      ctypes.byref(aT), _ptr(act), ctypes.byref(gg),
+                                      ctypes.byref(g00), _ptr(g_act), _ptr(g_W), _ptr(g_b)),
+              "mpm_rollout_ctrl")
+        return sT, act, g0, g_act, g_W, g_b
+
+    def rollout_ctrl_backward(self, gT: StateT, T: int, nz: int):
+        self._sync_stream()
+        g0 = self.empty_state()
+        g_act = torch.empty(T, self.n_act, device="cuda")
+        g_W = torch.empty(self.n_act, nz, device="cuda")
+        g_b = torch.empty(self.n_act, device="cuda")
+        gg, g00 = self._state(gT, "gT"), self._state(g0, "g0")
+        check(self.L.mpm_rollout_ctrl_backward(self.ctx, ctypes.byref(gg), ctypes.byref(g00),
+                                               _ptr(g_act), _ptr(g_W), _ptr(g_b)),
+              "mpm_rollout_ctrl_backward")
+        return g0, g_act, g_W, g_b
+
     def get_grid(self):
         self._sync_stream()
         m = torch.empty(self.G, device="cuda")
