@@ -8,6 +8,10 @@ torch.autograd: actuation bank (HIP) -> MPM rollout (HIP, C ABI) ->
 loss = centroid x of the final state -> backward (HIP, C ABI).  Inputs are
 resident in HBM before the timed region.
 
+``--workload c3ctrl`` runs the same scene with its actuation from a
+closed-loop controller (mpm_rollout_ctrl); c4, c5 and copy are the batched,
+serving and byte-counter calibration workloads.
+
 Prints one JSON line.  Besides the throughput it reports the roofline of the
 dominant kernel (HIP events on the library's stream, algorithmic bytes per
 particle) and the FP64 oracle timed on a bounded sample on the host.
@@ -283,8 +287,9 @@ def main():
     ap.add_argument("--scatter", type=int, default=0,
                     help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
                          "2 per-cell in bin order, 3 per-cell after an LDS sort")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "copy"],
-                    help="c3: 3D quadruped (headline); c4: 64 batched 2D scenes; "
+    ap.add_argument("--workload", default="c3", choices=["c3", "c3ctrl", "c4", "c5", "copy"],
+                    help="c3: 3D quadruped (headline); c3ctrl: the same, closed-loop "
+                         "controller; c4: 64 batched 2D scenes; "
                          "c5: serving a Poisson request mix; copy: plain device copy "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
@@ -304,7 +309,7 @@ def main():
     import torch
 
     from paper_1810_01054_amd import scenes as S
-    from paper_1810_01054_amd.autograd import act_bank, rollout
+    from paper_1810_01054_amd.autograd import act_bank, rollout, rollout_ctrl
     from paper_1810_01054_amd.sim import Simulator
 
     if not torch.cuda.is_available():
@@ -330,9 +335,22 @@ def main():
     amp = t(sc.amp).requires_grad_(True)
     phase = t(sc.phase).requires_grad_(True)
 
+    ctrl = args.workload == "c3ctrl"
+    if ctrl:
+        # closed loop: a = tanh(W z + b) over the 16 actuated leg quadrants'
+        # mean positions and velocities (z has 3 + 96 entries)
+        comp, n_comp, W, b, target = S.controller_params(sc, seed=1816, w_scale=0.1)
+        comp_t = torch.tensor(comp, dtype=torch.int32, device=dev)
+        W_t, b_t = t(W).requires_grad_(True), t(b).requires_grad_(True)
+        target_t = t(target)
+
     def one_step():
-        act = act_bank(T, sc.dt, freq, amp, phase)
-        xT, vT, CT, FT = rollout(sim, (x0, v0, C0, F0), act, T, k)
+        if ctrl:
+            xT, vT, CT, FT, _ = rollout_ctrl(sim, (x0, v0, C0, F0), T, comp_t, n_comp, W_t,
+                                             b_t, target_t, k)
+        else:
+            act = act_bank(T, sc.dt, freq, amp, phase)
+            xT, vT, CT, FT = rollout(sim, (x0, v0, C0, F0), act, T, k)
         loss = xT[0].mean()              # centroid x of the final state
         loss.backward()
         return loss
@@ -421,8 +439,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: 3D quadruped, 64^3 grid, {N} particles, "
-                               f"16 actuators, T={T} substeps fwd+bwd, checkpoint k={k} "
+                               f"16 actuators "
+                               + ("driven by a closed-loop controller tanh(W z + b) over "
+                                  "16 component means" if ctrl else "")
+                               + f", T={T} substeps fwd+bwd, checkpoint k={k} "
                                f"with recompute, torch.autograd.Function",
+                   "controller": "closed loop" if ctrl else "open-loop sinusoid bank",
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
                    "scatter_mode": args.scatter,
                    "global_batch": 1, "parallelism": "single GPU"},
@@ -434,7 +456,7 @@ def main():
         "kernel_roofline": kernel_roof,
         "cpu_baseline": None,
     }
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 and not ctrl:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

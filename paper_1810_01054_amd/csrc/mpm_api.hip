@@ -123,10 +123,9 @@ struct mpm_ctx {
     int *comp = nullptr;       // component of each particle (tape order) [N]
     float *inv_cnt = nullptr;  // [CTL_MAX_COMP]
     float *W = nullptr, *b = nullptr, *target = nullptr;  // copies
-    float *partial = nullptr;  // [ceil(N / 256)][2 d n_comp]
+    float *partial = nullptr;  // [2 d n_comp][ctl_rows(N)]
     double *sums = nullptr;    // [CTL_MAX_ZS]
     unsigned *done = nullptr;  // reduction counter (zero between launches)
-    float *zs = nullptr;       // [CTL_MAX_ZS]
     double *gW = nullptr, *gb = nullptr;  // FP64 accumulators
     float *Z = nullptr;        // tape of z^n [T][nz]
     int64_t Z_cap = 0;
@@ -690,7 +689,6 @@ int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g) {
   a.sbar = sbar;
   a.gW = k.gW;
   a.gb = k.gb;
-  a.zs = k.zs;
   a.gx = g.x;
   a.gv = g.v;
   a.ld = (int)c->N;
@@ -910,7 +908,6 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->ctl.partial, c->stream);
   dfree(c->ctl.sums, c->stream);
   dfree(c->ctl.done, c->stream);
-  dfree(c->ctl.zs, c->stream);
   dfree(c->ctl.gW, c->stream);
   dfree(c->ctl.gb, c->stream);
   dfree(c->ctl.Z, c->stream);
@@ -1237,17 +1234,15 @@ int ctl_setup(mpm_ctx *c, const mpm_controller *u, int T) {
   }
   hipStream_t s = c->stream;
   if (!k.comp) {
-    const int64_t nwg = (c->N + 255) / 256;
     RC(dmalloc(&k.comp, c->N, s));
     RC(dmalloc(&k.inv_cnt, CTL_MAX_COMP, s));
     RC(dmalloc(&k.W, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
     RC(dmalloc(&k.b, CTL_MAX_ACT, s));
     RC(dmalloc(&k.target, 3, s));
-    RC(dmalloc(&k.partial, nwg * CTL_MAX_ZS, s));
+    RC(dmalloc(&k.partial, (int64_t)ctl_rows((int)c->N) * CTL_MAX_ZS, s));
     RC(dmalloc(&k.sums, CTL_MAX_ZS, s));
     RC(dmalloc(&k.done, 1, s));
     RC(launch_fill_i32((int *)k.done, 1, s));
-    RC(dmalloc(&k.zs, CTL_MAX_ZS, s));
     RC(dmalloc(&k.gW, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
     RC(dmalloc(&k.gb, CTL_MAX_ACT, s));
   }

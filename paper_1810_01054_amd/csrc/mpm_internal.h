@@ -253,14 +253,16 @@ struct CtlArgs {
   const float *inv_cnt;   // [n_comp] 1 / particles of the component
   const float *x, *v;     // state n ([d][ld])
   int ld;
-  float *partial;         // [n_wg][nzs] per-workgroup sums
+  float *partial;         // [nzs][ctl_rows(N)] per-workgroup sums
   double *sums;           // [nzs]
-  unsigned *done;         // workgroups of the reduction finished (reset by the last)
+  unsigned *done;         // workgroups finished (zero between launches)
   const float *W, *b, *target;  // [n_act][nz], [n_act], [d]
   float *act;             // out: [n_act] actuation of this substep
   float *z;               // out: [nz] state vector of this substep (tape)
 };
 int launch_ctl_forward(const CtlArgs &a, hipStream_t st);
+// Rows of partial sums the forward reduction uses for N particles.
+int ctl_rows(int N);
 struct CtlAdjArgs {
   int dim, N, n_comp, n_act, nz;
   const int *comp;
@@ -268,7 +270,6 @@ struct CtlAdjArgs {
   const float *W, *act, *z;  // W, a^n and z^n of this substep
   const double *sbar;        // [n_act] dL/ds^n
   double *gW, *gb;           // accumulated [n_act][nz], [n_act]
-  float *zs;                 // [nzs] dL/dz of the state part / N_c
   float *gx, *gv;            // adjoint of state n ([d][ld]), += broadcast
   int ld;
 };

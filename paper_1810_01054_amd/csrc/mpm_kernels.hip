@@ -2384,59 +2384,76 @@ __global__ __launch_bounds__(256) void k_fill(T *p, int64_t n) {
 // ---------------------------------------------------------------------------
 
 constexpr int CTL_MAX_NZS = 96;  // 2 d n_comp <= 96 (n_comp <= 16 in 3D)
+constexpr int CTL_WG = 1024;      // workgroups of the controller kernels at most
 
-// Per-workgroup sums of x and v over each component (particles [256 b,
-// 256 b + 256)): each wave reduces the lanes of one component at a time with
-// shuffles; the four waves' sums are added by thread and stored.
-__global__ __launch_bounds__(256) void k_ctl_partial(CtlArgs A) {
+// Sums of x and v over each component, one row of partial sums per
+// workgroup (grid-stride over the particles).  Per wave, the lanes of one
+// component at a time are reduced with a reduce-scatter butterfly (the 2d
+// values padded to 8: 10 cross-lane steps instead of 6 per value), lane
+// group v ending with the total of value v, which it adds to the wave's LDS
+// row (entry 2 d c + a: x_a of component c, 2 d c + d + a: v_a).  Rows are
+// stored entry-major so the reduction reads them contiguously.
+template <int D>
+__global__ __launch_bounds__(256) void k_ctl_partial(CtlArgs A, int n_rows) {
   __shared__ float s_w[4][CTL_MAX_NZS];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int d = A.dim, nzs = 2 * d * A.n_comp;
-  for (int i = lane; i < nzs; i += 64) s_w[wave][i] = 0.0f;
-  const int p = blockIdx.x * 256 + t;
-  const int c = p < A.N ? A.comp[p] : -1;
-  float val[6] = {0, 0, 0, 0, 0, 0};
-  if (c >= 0)
-    for (int a = 0; a < d; ++a) {
-      val[a] = A.x[a * A.ld + p];
-      val[3 + a] = A.v[a * A.ld + p];
-    }
-  unsigned long long todo = __ballot(c >= 0);
-  while (todo) {
-    const int src = __ffsll((long long)todo) - 1;
-    const int cc = __shfl(c, src, 64);
-    const unsigned long long m = __ballot(c == cc);
-    float r[6];
+  const int nzs = 2 * D * A.n_comp;
+  for (int i = lane; i < CTL_MAX_NZS; i += 64) s_w[wave][i] = 0.0f;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  const int vi = (h5 ? 4 : 0) + (h4 ? 2 : 0) + (h3 ? 1 : 0);
+  for (int p0 = blockIdx.x * 256; p0 < A.N; p0 += n_rows * 256) {
+    const int p = p0 + t;
+    const bool in = p < A.N;
+    // loads independent of the component id: one memory round trip
+    const int c = in ? A.comp[p] : -1;
+    float val[8];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      float x = c == cc ? val[k] : 0.0f;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-      r[k] = x;
+    for (int a = 0; a < D; ++a) {
+      val[a] = in ? A.x[a * A.ld + p] : 0.0f;
+      val[D + a] = in ? A.v[a * A.ld + p] : 0.0f;
     }
-    if (lane == 0)
-      for (int a = 0; a < d; ++a) {
-        s_w[wave][2 * d * cc + a] = r[a];
-        s_w[wave][2 * d * cc + d + a] = r[3 + a];
+#pragma unroll
+    for (int k = 2 * D; k < 8; ++k) val[k] = 0.0f;
+    unsigned long long todo = __ballot(c >= 0);
+    while (todo) {
+      const int src = __ffsll((long long)todo) - 1;
+      const int cc = __shfl(c, src, 64);
+      const bool mine = c == cc;
+      float q[4], u[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float lo = mine ? val[k] : 0.0f, hi = mine ? val[k + 4] : 0.0f;
+        q[k] = (h5 ? hi : lo) + __shfl_xor(h5 ? lo : hi, 32, 64);
       }
-    todo &= ~m;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        u[k] = (h4 ? q[k + 2] : q[k]) + __shfl_xor(h4 ? q[k] : q[k + 2], 16, 64);
+      float w = (h3 ? u[1] : u[0]) + __shfl_xor(h3 ? u[0] : u[1], 8, 64);
+      w += __shfl_xor(w, 4, 64);
+      w += __shfl_xor(w, 2, 64);
+      w += __shfl_xor(w, 1, 64);
+      if ((lane & 7) == 0 && vi < 2 * D) s_w[wave][2 * D * cc + vi] += w;
+      todo &= ~__ballot(mine);
+    }
   }
   __syncthreads();
   for (int i = t; i < nzs; i += 256)
-    A.partial[(int64_t)blockIdx.x * nzs + i] =
+    A.partial[(int64_t)i * n_rows + blockIdx.x] =
         (s_w[0][i] + s_w[1][i]) + (s_w[2][i] + s_w[3][i]);
 }
 
-// One workgroup per component value: the sum over all workgroup partials
-// (FP64).  The last workgroup to finish evaluates the controller.
-__global__ __launch_bounds__(256) void k_ctl_reduce(CtlArgs A, int n_wg) {
+// One workgroup per entry: the sum over the partial rows (FP64).  The last
+// workgroup to finish forms z = [target, component means] and evaluates
+// a = tanh(W z + b) (one wave per row).
+__global__ __launch_bounds__(256) void k_ctl_reduce(CtlArgs A, int n_rows) {
   __shared__ double s_red[256];
   __shared__ bool s_last;
   __shared__ double s_z[CTL_MAX_NZS + 3];
-  const int t = threadIdx.x, d = A.dim, nzs = 2 * d * A.n_comp;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, d = A.dim;
+  const int nzs = 2 * d * A.n_comp;
   const int i = blockIdx.x;
   double acc = 0.0;
-  for (int w = t; w < n_wg; w += 256) acc += (double)A.partial[(int64_t)w * nzs + i];
+  for (int w = t; w < n_rows; w += 256) acc += (double)A.partial[(int64_t)i * n_rows + w];
   s_red[t] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -2451,7 +2468,6 @@ __global__ __launch_bounds__(256) void k_ctl_reduce(CtlArgs A, int n_wg) {
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  // z = [target, per component: mean x, mean v]; a = tanh(W z + b)
   for (int k = t; k < A.nz; k += 256) {
     double zk;
     if (k < d) {
@@ -2464,49 +2480,53 @@ __global__ __launch_bounds__(256) void k_ctl_reduce(CtlArgs A, int n_wg) {
     A.z[k] = (float)zk;
   }
   __syncthreads();
-  for (int j = t; j < A.n_act; j += 256) {
-    float pre = A.b[j];
-    for (int k = 0; k < A.nz; ++k) pre += A.W[j * A.nz + k] * (float)s_z[k];
-    A.act[j] = tanhf(pre);
+  // W z + b: one wave per row, lanes over z (nz <= 99 < 128)
+  for (int j = wave; j < A.n_act; j += 4) {
+    float x = 0.0f;
+    if (lane < A.nz) x = A.W[j * A.nz + lane] * (float)s_z[lane];
+    if (lane + 64 < A.nz) x += A.W[j * A.nz + lane + 64] * (float)s_z[lane + 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) A.act[j] = tanhf(A.b[j] + x);
   }
   if (t == 0) *A.done = 0u;  // for the next substep (stream-ordered)
 }
 
-// Reverse of the controller at one substep (one workgroup): g = dL/ds (1 -
-// a^2); dL/dW += g z^T, dL/db += g; the state part of W^T g, divided by each
-// component's particle count, for the broadcast below.
-__global__ __launch_bounds__(256) void k_ctl_adj(CtlAdjArgs A) {
+// Reverse of the controller at one substep.  Every workgroup forms
+// g = dL/ds (1 - a^2) and the state part of W^T g divided by each
+// component's particle count, then adds it to the x and v adjoints of the
+// component's particles (grid-stride); workgroup 0 also accumulates
+// dL/dW += g z^T and dL/db += g.
+__global__ __launch_bounds__(256) void k_ctl_adjoint(CtlAdjArgs A, int n_wg) {
   __shared__ double s_g[64];
-  const int t = threadIdx.x, d = A.dim;
+  __shared__ float s_zs[CTL_MAX_NZS];
+  const int t = threadIdx.x, d = A.dim, nzs = 2 * d * A.n_comp;
   for (int j = t; j < A.n_act; j += 256) {
     const double a = A.act[j];
-    s_g[j] = A.sbar[j] * (1.0 - a * a);
-    A.gb[j] += s_g[j];
+    const double g = A.sbar[j] * (1.0 - a * a);
+    s_g[j] = g;
+    if (blockIdx.x == 0) A.gb[j] += g;
   }
   __syncthreads();
-  for (int e = t; e < A.n_act * A.nz; e += 256) {
-    const int j = e / A.nz, k = e % A.nz;
-    A.gW[e] += s_g[j] * (double)A.z[k];
-  }
-  for (int k = d + t; k < A.nz; k += 256) {
+  if (blockIdx.x == 0)
+    for (int e = t; e < A.n_act * A.nz; e += 256) {
+      const int j = e / A.nz, k = e % A.nz;
+      A.gW[e] += s_g[j] * (double)A.z[k];
+    }
+  for (int k = t; k < nzs; k += 256) {
     double s = 0.0;
-    for (int j = 0; j < A.n_act; ++j) s += (double)A.W[j * A.nz + k] * s_g[j];
-    const int c = (k - d) / (2 * d);
-    A.zs[k - d] = (float)(s * (double)A.inv_cnt[c]);
+#pragma unroll 8
+    for (int j = 0; j < A.n_act; ++j) s += (double)A.W[j * A.nz + d + k] * s_g[j];
+    s_zs[k] = (float)(s * (double)A.inv_cnt[k / (2 * d)]);
   }
-}
-
-// Adds the controller's dL/dz / N_c to the x and v adjoints of every
-// particle of a component.
-__global__ __launch_bounds__(256) void k_ctl_broadcast(CtlAdjArgs A) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= A.N) return;
-  const int c = A.comp[p];
-  if (c < 0) return;
-  const int d = A.dim;
-  for (int a = 0; a < d; ++a) {
-    A.gx[a * A.ld + p] += A.zs[2 * d * c + a];
-    A.gv[a * A.ld + p] += A.zs[2 * d * c + d + a];
+  __syncthreads();
+  for (int p = blockIdx.x * 256 + t; p < A.N; p += n_wg * 256) {
+    const int c = A.comp[p];
+    if (c < 0) continue;
+    for (int a = 0; a < d; ++a) {
+      A.gx[a * A.ld + p] += s_zs[2 * d * c + a];
+      A.gv[a * A.ld + p] += s_zs[2 * d * c + d + a];
+    }
   }
 }
 
@@ -2735,21 +2755,26 @@ int launch_permute_i32(const int *in, int *out, const int *perm, int N,
 }
 
 int launch_ctl_forward(const CtlArgs &a, hipStream_t st) {
-  const int n_wg = (a.N + 255) / 256;
   const int nzs = 2 * a.dim * a.n_comp;
-  if (n_wg == 0 || nzs == 0 || nzs > CTL_MAX_NZS || a.n_act > 64) return -1;
-  hipLaunchKernelGGL(k_ctl_partial, dim3(n_wg), dim3(256), 0, st, a);
-  int rc = hip_rc(hipGetLastError());
+  if (a.N < 1 || nzs == 0 || nzs > CTL_MAX_NZS || a.n_act > 64) return -1;
+  const int rows = ctl_rows(a.N);
+  if (a.dim == 2)
+    hipLaunchKernelGGL(k_ctl_partial<2>, dim3(rows), dim3(256), 0, st, a, rows);
+  else if (a.dim == 3)
+    hipLaunchKernelGGL(k_ctl_partial<3>, dim3(rows), dim3(256), 0, st, a, rows);
+  else
+    return -1;
+  const int rc = hip_rc(hipGetLastError());
   if (rc) return rc;
-  MPM_LAUNCH(k_ctl_reduce, nzs, 256, st, a, n_wg);
+  MPM_LAUNCH(k_ctl_reduce, nzs, 256, st, a, rows);
 }
 
+int ctl_rows(int N) { return std::min((N + 255) / 256, 2048); }
+
 int launch_ctl_adjoint(const CtlAdjArgs &a, hipStream_t st) {
-  if (a.n_act > 64) return -1;
-  hipLaunchKernelGGL(k_ctl_adj, dim3(1), dim3(256), 0, st, a);
-  int rc = hip_rc(hipGetLastError());
-  if (rc) return rc;
-  MPM_LAUNCH(k_ctl_broadcast, (a.N + 255) / 256, 256, st, a);
+  if (a.N < 1 || a.n_act > 64 || 2 * a.dim * a.n_comp > CTL_MAX_NZS) return -1;
+  const int n_wg = std::min((a.N + 255) / 256, CTL_WG);
+  MPM_LAUNCH(k_ctl_adjoint, n_wg, 256, st, a, n_wg);
 }
 
 int launch_gact_store(const double *src, float *dst, int64_t n, int accumulate,
