@@ -53,12 +53,13 @@ def build(force: bool = True) -> str:
 class _Scene(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_grid", ctypes.c_int32),
                 ("n_particles", ctypes.c_int32), ("n_act", ctypes.c_int32),
-                ("wall", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("wall", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("E", ctypes.c_double),
                 ("nu", ctypes.c_double), ("rho", ctypes.c_double),
                 ("V0", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3),
-                ("act_axis", ctypes.c_double * 3)]
+                ("act_axis", ctypes.c_double * 3),
+                ("friction", ctypes.c_double)]
 
 
 _lib = None
@@ -107,6 +108,10 @@ def _load(path: str):
     L.orc_lame.restype = None
     L.orc_p2g.argtypes = [sp, ip, dp, dp, dp, dp, dp, dp, dp]
     L.orc_grid_update.argtypes = [sp, dp, dp, dp]
+    L.orc_friction_project.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
+    L.orc_friction_project.restype = None
+    L.orc_friction_project_bwd.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp, dp]
+    L.orc_friction_project_bwd.restype = None
     L.orc_g2p.argtypes = [sp, dp, dp, dp, dp, dp, dp, dp]
     L.orc_step_fwd.argtypes = [sp, ip, dp] + [dp] * 8
     L.orc_step_bwd.argtypes = [sp, ip, dp] + [dp] * 13
@@ -155,11 +160,14 @@ class Scene:
     V0: float = 0.0
     gravity: tuple = (0.0, -9.8, 0.0)
     act_axis: tuple = (0.0, 1.0, 0.0)
+    bc: int = 0              # wall nodes: 0 sticky, 1 friction projection (L)
+    friction: float = 0.0    # coefficient c of (L)
 
     def c(self) -> _Scene:
         s = _Scene()
         s.dim, s.n_grid, s.n_particles = self.dim, self.n_grid, self.n_particles
-        s.n_act, s.wall, s.reserved = self.n_act, self.wall, 0
+        s.n_act, s.wall, s.bc = self.n_act, self.wall, self.bc
+        s.friction = self.friction
         s.dt, s.E, s.nu, s.rho, s.V0 = (self.dt, self.E, self.nu, self.rho,
                                         self.V0)
         for k in range(3):
@@ -227,6 +235,23 @@ def grid_update(scene: Scene, gm, gp):
     gv = np.zeros((scene.dim, scene.n_nodes))
     _check(lib().orc_grid_update(ctypes.byref(scene.c()), _d(gm), _d(gp), _d(gv)))
     return gv
+
+
+def friction_project(nrm, c: float, v):
+    """(L) forward: v* of one node velocity v against a wall with unit
+    normal nrm and friction coefficient c."""
+    nrm, v = _f64(nrm).copy(), _f64(v).copy()
+    out = np.zeros(v.size)
+    lib().orc_friction_project(v.size, _d(nrm), c, _d(v), _d(out))
+    return out
+
+
+def friction_project_bwd(nrm, c: float, v, vbs):
+    """(L) reverse: dL/dv from dL/dv* at the same v."""
+    nrm, v, vbs = _f64(nrm).copy(), _f64(v).copy(), _f64(vbs).copy()
+    out = np.zeros(v.size)
+    lib().orc_friction_project_bwd(v.size, _d(nrm), c, _d(v), _d(vbs), _d(out))
+    return out
 
 
 def g2p(scene: Scene, gv, x, F):

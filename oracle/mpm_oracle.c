@@ -18,9 +18,15 @@
  *       P   = mu (F - F^-T) + la ln J F^-T;
  *   - node i sits at i*dx with dx = 1/n; stencil base = floor(x/dx - 0.5);
  *   - grid operations, in order: v^ = p/m (only where m > 0, else 0),
- *     v = v^ + dt g, then v = 0 on nodes with any index < wall or >= n-wall
- *     (sticky box walls; the paper omits gravity and boundaries "for
- *     simplicity");
+ *     v = v^ + dt g, then the boundary condition on wall nodes (any index
+ *     < wall or >= n-wall; the paper omits gravity and boundaries in its
+ *     main text): bc = 0 sets v = 0 (sticky walls); bc = 1 applies the
+ *     friction projection of the supplement's section on friction
+ *     projection gradients, (L), once per axis whose wall band holds the
+ *     node, in axis order, low face before high face, with the inward
+ *     normal of that face (+e_a at the low face, -e_a at the high face),
+ *     friction coefficient c = s->friction and epsilon = 1e-12 in
+ *     l_t = sqrt(|v_t|^2 + epsilon) (the paper gives no value);
  *   - actuation: sigma_pa = s_j * diag(axis) for the particle's actuator j;
  *     the total first Piola-Kirchhoff stress is P(F) + F sigma_pa;
  *   - in adjoint (J) the derivative of N is taken with respect to the
@@ -247,6 +253,8 @@ static int scene_ok(const orc_scene *s) {
   if (s->dim != 2 && s->dim != 3) return 0;
   if (s->n_grid < 3 || s->n_particles < 0 || s->n_act < 0 || s->wall < 0)
     return 0;
+  if (s->bc != 0 && s->bc != 1) return 0;
+  if (s->bc == 1 && !(s->friction >= 0.0)) return 0;
   return 1;
 }
 
@@ -336,23 +344,146 @@ static int is_wall_node(const orc_scene *s, long i) {
   return 0;
 }
 
+/* (L) forward: friction projection of the node velocity v against a wall
+ * with unit normal nrm and friction coefficient c:
+ *   l_n = v . n,  v_t = v - l_n n,  l_t = sqrt(|v_t|^2 + eps),
+ *   v^_t = v_t / l_t,  l*_t = max(l_t + c min(l_n, 0), 0),
+ *   v* = l*_t v^_t + max(l_n, 0) n. */
+#define ORC_FRICTION_EPS 1e-12
+void orc_friction_project(int d, const double *nrm, double c, const double *v,
+                          double *vs) {
+  double ln = 0.0;
+  for (int a = 0; a < d; ++a) ln += v[a] * nrm[a];
+  double vt[3], lt2 = 0.0;
+  for (int a = 0; a < d; ++a) {
+    vt[a] = v[a] - ln * nrm[a];
+    lt2 += vt[a] * vt[a];
+  }
+  double lt = sqrt(lt2 + ORC_FRICTION_EPS);
+  double lts = fmax(lt + c * fmin(ln, 0.0), 0.0);
+  for (int a = 0; a < d; ++a) vs[a] = lts * (vt[a] / lt) + fmax(ln, 0.0) * nrm[a];
+}
+
+/* (L) reverse: dL/dv (vb) from dL/dv* (vbs) at the same v, with
+ * H(x) = [x >= 0] and R = l_t + c min(l_n, 0). */
+void orc_friction_project_bwd(int d, const double *nrm, double c,
+                              const double *v, const double *vbs, double *vb) {
+  double ln = 0.0;
+  for (int a = 0; a < d; ++a) ln += v[a] * nrm[a];
+  double vt[3], lt2 = 0.0;
+  for (int a = 0; a < d; ++a) {
+    vt[a] = v[a] - ln * nrm[a];
+    lt2 += vt[a] * vt[a];
+  }
+  double lt = sqrt(lt2 + ORC_FRICTION_EPS);
+  double vth[3];
+  for (int a = 0; a < d; ++a) vth[a] = vt[a] / lt;
+  double R = lt + c * fmin(ln, 0.0);
+  double lts = fmax(R, 0.0);
+  double HR = R >= 0.0 ? 1.0 : 0.0;
+  /* dL/dl*_t and dL/dv^_t */
+  double ltsb = 0.0, vthb[3];
+  for (int a = 0; a < d; ++a) {
+    ltsb += vbs[a] * vth[a];
+    vthb[a] = vbs[a] * lts;
+  }
+  /* dL/dl_t */
+  double s = 0.0;
+  for (int a = 0; a < d; ++a) s += vt[a] * vthb[a];
+  double ltb = -s / (lt * lt) + ltsb * HR;
+  /* dL/dv_t */
+  double vtb[3];
+  for (int a = 0; a < d; ++a) vtb[a] = (ltb * vt[a] + vthb[a]) / lt;
+  /* dL/dl_n */
+  double lnb = 0.0, nv = 0.0;
+  for (int a = 0; a < d; ++a) {
+    lnb -= vtb[a] * nrm[a];
+    nv += nrm[a] * vbs[a];
+  }
+  lnb += ltsb * HR * c * (-ln >= 0.0 ? 1.0 : 0.0);
+  lnb += (ln >= 0.0 ? 1.0 : 0.0) * nv;
+  for (int a = 0; a < d; ++a) vb[a] = lnb * nrm[a] + vtb[a];
+}
+
+/* The boundary faces of node i in the order the projection visits them
+ * (axis order, low face before high face): their count, and the inward
+ * normal of each (stage k: axis ax[k], sign sg[k]). */
+static int wall_faces(const orc_scene *s, long i, int *ax, double *sg) {
+  int n = s->n_grid, d = s->dim, idx[3], k = 0;
+  for (int a = d - 1; a >= 0; --a) {
+    idx[a] = (int)(i % n);
+    i /= n;
+  }
+  for (int a = 0; a < d; ++a) {
+    if (idx[a] < s->wall) {
+      ax[k] = a;
+      sg[k++] = 1.0;
+    }
+    if (idx[a] >= n - s->wall) {
+      ax[k] = a;
+      sg[k++] = -1.0;
+    }
+  }
+  return k;
+}
+
+/* Boundary condition on one wall node: v (in place). */
+static void wall_bc(const orc_scene *s, long i, double *v) {
+  if (s->bc == 0) {
+    for (int a = 0; a < s->dim; ++a) v[a] = 0.0;
+    return;
+  }
+  int ax[6];
+  double sg[6];
+  int nf = wall_faces(s, i, ax, sg);
+  for (int k = 0; k < nf; ++k) {
+    double nrm[3] = {0.0, 0.0, 0.0}, out[3];
+    nrm[ax[k]] = sg[k];
+    orc_friction_project(s->dim, nrm, s->friction, v, out);
+    for (int a = 0; a < s->dim; ++a) v[a] = out[a];
+  }
+}
+
+/* Reverse of wall_bc: vb (dL/dv after the condition) -> dL/dv before it,
+ * in place; v is the velocity before the condition. */
+static void wall_bc_bwd(const orc_scene *s, long i, const double *v, double *vb) {
+  if (s->bc == 0) {
+    for (int a = 0; a < s->dim; ++a) vb[a] = 0.0;
+    return;
+  }
+  int ax[6];
+  double sg[6], vin[7][3];
+  int nf = wall_faces(s, i, ax, sg);
+  for (int a = 0; a < s->dim; ++a) vin[0][a] = v[a];
+  for (int k = 0; k < nf; ++k) {
+    double nrm[3] = {0.0, 0.0, 0.0};
+    nrm[ax[k]] = sg[k];
+    orc_friction_project(s->dim, nrm, s->friction, vin[k], vin[k + 1]);
+  }
+  for (int k = nf - 1; k >= 0; --k) {
+    double nrm[3] = {0.0, 0.0, 0.0}, out[3];
+    nrm[ax[k]] = sg[k];
+    orc_friction_project_bwd(s->dim, nrm, s->friction, vin[k], vb, out);
+    for (int a = 0; a < s->dim; ++a) vb[a] = out[a];
+  }
+}
+
 int orc_grid_update(const orc_scene *s, const double *gm, const double *gp,
                     double *gv) {
   if (!scene_ok(s)) return ORC_ERR_ARG;
   int d = s->dim;
   long nn = n_nodes(s);
   for (long i = 0; i < nn; ++i) {
-    int wall = is_wall_node(s, i);
+    double v[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < d; ++a) {
-      double vi = 0.0;
       if (gm[i] > 0.0) {
         /* v_i = p_i / m_i, then gravity */
-        vi = gp[a * nn + i] / gm[i];
-        vi = vi + s->dt * s->gravity[a];
+        v[a] = gp[a * nn + i] / gm[i];
+        v[a] = v[a] + s->dt * s->gravity[a];
       }
-      if (wall) vi = 0.0;
-      gv[a * nn + i] = vi;
     }
+    if (is_wall_node(s, i)) wall_bc(s, i, v);
+    for (int a = 0; a < d; ++a) gv[a * nn + i] = v[a];
   }
   return ORC_OK;
 }
@@ -500,17 +631,25 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
   for (long i = 0; i < nn; ++i) {
     int wall = is_wall_node(s, i);
     double m = gm[i];
-    if (wall || !(m > 0.0)) {
+    if ((wall && s->bc == 0) || !(m > 0.0)) {
       for (int a = 0; a < d; ++a) pbar[a * nn + i] = 0.0;
       mbar[i] = 0.0;
       continue;
     }
+    /* dL/dv before the boundary condition: (L) on wall nodes */
+    double vb[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) vb[a] = vbar[a * nn + i];
+    if (wall) {
+      double v[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < d; ++a) v[a] = gpm[a * nn + i] / m + s->dt * s->gravity[a];
+      wall_bc_bwd(s, i, v, vb);
+    }
     double vdot = 0.0;
     for (int a = 0; a < d; ++a) {
       /* (D) dL/dp_i = dL/dv_i / m_i  (gravity passes dL/dv_i unchanged) */
-      pbar[a * nn + i] = vbar[a * nn + i] / m;
+      pbar[a * nn + i] = vb[a] / m;
       double vhat = gpm[a * nn + i] / m;
-      vdot += vhat * vbar[a * nn + i];
+      vdot += vhat * vb[a];
     }
     /* (E) dL/dm_i = -(1/m_i) sum_a v^_ia dL/dv_ia, v^ = p/m before gravity */
     mbar[i] = -vdot / m;

@@ -44,13 +44,22 @@ typedef struct orc_scene {
   int32_t n_grid;      /* nodes per axis n; dx = 1/n, node i sits at i*dx */
   int32_t n_particles; /* N */
   int32_t n_act;       /* number of actuators */
-  int32_t wall;        /* sticky-wall thickness in nodes */
-  int32_t reserved;
+  int32_t wall;        /* wall thickness in nodes */
+  int32_t bc;          /* wall nodes: 0 sticky (v = 0), 1 friction projection (L) */
   double dt, E, nu, rho, V0; /* time step, Young's modulus, Poisson ratio,
                                 density, initial particle volume */
   double gravity[3];
   double act_axis[3];  /* sigma_pa = s_j * diag(act_axis) */
+  double friction;     /* friction coefficient c of (L), bc = 1 */
 } orc_scene;
+
+/* (L) friction projection of one node velocity v (d entries) against a wall
+ * with unit normal nrm and coefficient c (forward: vs = v*), and its reverse
+ * (vb = dL/dv from vbs = dL/dv* at the same v). */
+void orc_friction_project(int d, const double *nrm, double c, const double *v,
+                          double *vs);
+void orc_friction_project_bwd(int d, const double *nrm, double c,
+                              const double *v, const double *vbs, double *vb);
 
 /* Quadratic B-spline along one axis: stencil base, weights w[3] of the three
  * nodes base..base+2 and their derivatives dw[3] with respect to the particle

@@ -50,6 +50,8 @@ class Scene:
     gravity: tuple = (0.0, float(F32(-9.8)), 0.0)
     act_axis: tuple = (0.0, 1.0, 0.0)
     name: str = ""
+    bc: int = 0                    # wall nodes: 0 sticky, 1 friction projection
+    friction: float = 0.0          # friction coefficient of the projection
 
     @property
     def n_particles(self) -> int:
@@ -65,7 +67,8 @@ class Scene:
                     n_particles=self.n_particles, n_act=self.n_act,
                     wall=self.wall, dt=self.dt, E=self.E, nu=self.nu,
                     rho=self.rho, V0=self.V0, gravity=tuple(self.gravity),
-                    act_axis=tuple(self.act_axis))
+                    act_axis=tuple(self.act_axis), bc=self.bc,
+                    friction=self.friction)
 
 
 def _f32(a) -> float:
@@ -373,3 +376,27 @@ def controller_params(scene: Scene, seed: int, n_comp: Optional[int] = None,
     b = (rng.normal(size=scene.n_act) * b_scale).astype(F32)
     target = rng.uniform(0.3, 0.7, size=d).astype(F32)
     return comp, n_comp, W, b, target
+
+
+def wall_contact(dim: int = 2, n: int = 16, n_particles: int = 40, seed: int = 9,
+                 friction: float = 0.3, speed: float = 1.5, n_act: int = 2) -> Scene:
+    """A small body pressed into the corner of the floor and the low-x wall,
+    with the friction-projection boundary (bc = 1): particles uniform over
+    cells [2.6, 5.5) on every axis (so their stencils reach the 3-node wall
+    bands of the floor and of the x = 0 wall), velocity toward the floor and
+    the wall with a tangential part, v ~ speed * (-0.6, -1, 0.4) + N(0,
+    0.1^2) per component, C = 0, F = I + N(0, 0.02^2); actuators by x half."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(2.6, 5.5, size=(dim, n_particles))   # in cells
+    dirn = np.array([-0.6, -1.0, 0.4][:dim])
+    v = speed * dirn[:, None] + rng.normal(scale=0.1, size=(dim, n_particles))
+    F = np.tile(np.eye(dim).reshape(-1, 1), (1, n_particles))
+    F = F + rng.normal(scale=0.02, size=F.shape)
+    act_id = (pos[0] >= 4.05).astype(np.int32) % max(n_act, 1)
+    amp = rng.uniform(0.5, 2.0, size=(n_act, 1))
+    phase = rng.uniform(0.0, 2 * np.pi, size=(n_act, 1))
+    sc = _finish(dim, n, pos, act_id, n_act, amp, phase, [10.0], f"contact{dim}d")
+    sc.v = v.astype(F32)
+    sc.F = F.astype(F32)
+    sc.bc, sc.friction = 1, _f32(friction)
+    return sc

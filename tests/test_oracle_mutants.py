@@ -20,7 +20,7 @@ MUTANTS = [
     ("stress_transposed", "matmul_nt_d(d, out->Pt, Fp, PFt);", "matmul_tn_d(d, out->Pt, Fp, PFt);"),
     ("actuation_sigma_F", "Fp[a * d + b] * out->sigma[b];", "Fp[a * d + b] * out->sigma[a];"),
     ("lame_mu", "*mu = E / (2.0 * (1.0 + nu));", "*mu = E / (1.0 + nu);"),
-    ("gravity_dropped", "vi = vi + s->dt * s->gravity[a];", "vi = vi + 0.0 * s->gravity[a];"),
+    ("gravity_dropped", "v[a] = v[a] + s->dt * s->gravity[a];", "v[a] = v[a] + 0.0 * s->gravity[a];"),
     ("wall_off_by_one", "ia >= n - s->wall", "ia > n - s->wall"),
     ("g2p_C_transposed", "B[a * d + b] += Nw * via * delta[b];", "B[b * d + a] += Nw * via * delta[b];"),
     ("F_update_order", "matmul_d(d, Ipc, Fp, Fn);", "matmul_d(d, Fp, Ipc, Fn);"),
@@ -51,6 +51,42 @@ CTRL_MUTANTS = [
      "z[d + 2 * d * c + a] += v[(size_t)a * N + p];"),
     ("ctrl_W_transposed", "zb[i] += W[(size_t)j * nz + i] * g;", "zb[i] += W[(size_t)i * nact + j] * g;"),
 ]
+
+
+# Mistakes in the friction projection (L) and the wall condition built on
+# it, caught by the friction pins.
+FRICTION_MUTANTS = [
+    ("fric_coulomb_sign", "double lts = fmax(lt + c * fmin(ln, 0.0), 0.0);",
+     "double lts = fmax(lt - c * fmin(ln, 0.0), 0.0);"),
+    ("fric_separating_dropped",
+     "vs[a] = lts * (vt[a] / lt) + fmax(ln, 0.0) * nrm[a];", "vs[a] = lts * (vt[a] / lt);"),
+    ("fric_high_face_normal", "sg[k++] = -1.0;", "sg[k++] = 1.0;"),
+    ("fric_rev_HR_dropped", "double ltb = -s / (lt * lt) + ltsb * HR;",
+     "double ltb = -s / (lt * lt) + ltsb;"),
+    ("fric_rev_c_term_sign", "lnb += ltsb * HR * c * (-ln >= 0.0 ? 1.0 : 0.0);",
+     "lnb -= ltsb * HR * c * (-ln >= 0.0 ? 1.0 : 0.0);"),
+    ("fric_rev_normal_pass_dropped", "lnb += (ln >= 0.0 ? 1.0 : 0.0) * nv;", ""),
+    ("fric_rev_vt_scale", "vtb[a] = (ltb * vt[a] + vthb[a]) / lt;",
+     "vtb[a] = ltb * vt[a] + vthb[a];"),
+    ("fric_rev_grid_skipped", "wall_bc_bwd(s, i, v, vb);", ""),
+]
+
+
+def _run_friction_pins():
+    from tests import test_oracle_friction as fr
+    failed = []
+    for name, fn in [
+            ("frictionless", lambda: fr.test_frictionless_wall_removes_only_an_approaching_normal_component(3)),
+            ("coulomb", lambda: fr.test_coulomb_friction_shortens_the_tangential_velocity(2)),
+            ("separating", lambda: fr.test_separating_velocity_passes_and_energy_never_grows(3)),
+            ("reverse_fd", lambda: fr.test_projection_reverse_matches_central_differences(3)),
+            ("grid_clamp", lambda: fr.test_grid_frictionless_walls_clamp_each_face_normal(2)),
+            ("rollout_fd", lambda: fr.test_contact_rollout_gradients_match_central_differences(2, 0.4))]:
+        try:
+            fn()
+        except (AssertionError, oracle.OracleError, ValueError):
+            failed.append(name)
+    return failed
 
 
 def _run_ctrl_pins():
@@ -122,3 +158,17 @@ def test_controller_mutant_is_caught(name, old, new, tmp_path):
     with oracle.use_library(str(lib)):
         failed = _run_ctrl_pins()
     assert failed, f"mutant {name} passed every controller pin"
+
+
+@pytest.mark.parametrize("name,old,new", FRICTION_MUTANTS, ids=[m[0] for m in FRICTION_MUTANTS])
+def test_friction_mutant_is_caught(name, old, new, tmp_path):
+    assert SRC.count(old) == 1, f"mutation anchor for {name} not unique"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(old, new))
+    hdr = os.path.join(os.path.dirname(oracle.__file__), "mpm_oracle.h")
+    (tmp_path / "mpm_oracle.h").write_text(open(hdr).read())
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", *oracle.CFLAGS, "-o", str(lib), str(src), "-lm"], check=True)
+    with oracle.use_library(str(lib)):
+        failed = _run_friction_pins()
+    assert failed, f"mutant {name} passed every friction pin"
