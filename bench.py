@@ -295,6 +295,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--requests", type=int, default=60, help="c5: requests per load point")
     ap.add_argument("--slots", type=int, default=8, help="c5: concurrent requests")
+    ap.add_argument("--friction", type=float, default=None,
+                    help="c3/c3ctrl: walls with the friction projection and this "
+                         "coefficient instead of sticky walls")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -325,6 +328,8 @@ def main():
         return run_copy(args)
 
     sc = S.config_3()
+    if args.friction is not None:
+        sc.bc, sc.friction = 1, float(np.float32(args.friction))
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
     sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter)
@@ -445,6 +450,8 @@ def main():
                                + f", T={T} substeps fwd+bwd, checkpoint k={k} "
                                f"with recompute, torch.autograd.Function",
                    "controller": "closed loop" if ctrl else "open-loop sinusoid bank",
+                   "walls": ("sticky" if args.friction is None
+                             else f"friction projection, c = {args.friction}"),
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
                    "scatter_mode": args.scatter,
                    "global_batch": 1, "parallelism": "single GPU"},
@@ -456,7 +463,7 @@ def main():
         "kernel_roofline": kernel_roof,
         "cpu_baseline": None,
     }
-    if args.cpu_sample > 0 and not ctrl:
+    if args.cpu_sample > 0 and not ctrl and args.friction is None:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

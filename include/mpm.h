@@ -61,17 +61,26 @@ typedef struct mpm_ctx mpm_ctx;
 /* One scene (HOST).  Physical meaning as in Table I: dt, E, nu, rho, V0 =
  * V_p^0 (equal for all particles), particle mass m_p = rho * V0.  Nodes
  * closer than `wall` to the box faces (index < wall or >= n - wall on any
- * axis) are sticky walls: their velocity is set to zero after gravity. */
+ * axis) are wall nodes; after gravity their velocity is
+ *   bc = 0: set to zero (sticky walls);
+ *   bc = 1: passed through the friction projection of the supplement's
+ *           friction projection gradients, (L), with coefficient `friction`
+ *           (0 = frictionless slip): once per face whose band holds the
+ *           node, in axis order, low face first, with the face's inward
+ *           normal (+e_a at the low face, -e_a at the high face) and
+ *           epsilon = 1e-12 under the tangential norm.
+ * The reverse pass applies the reverse of (L) on those nodes. */
 typedef struct mpm_scene {
   int32_t dim;         /* 2 or 3 (all scenes of a context alike)           */
   int32_t n_grid;      /* n: nodes per axis, dx = 1/n; n >= 3               */
   int32_t n_particles; /* N_s >= 0                                          */
   int32_t n_act;       /* actuators of this scene, 0..MPM_MAX_ACT           */
-  int32_t wall;        /* sticky-wall thickness in nodes, >= 0              */
-  int32_t reserved;    /* must be 0                                         */
+  int32_t wall;        /* wall thickness in nodes, >= 0                     */
+  int32_t bc;          /* wall condition: 0 sticky, 1 friction projection   */
   float dt, E, nu, rho, V0;
   float gravity[3];    /* acceleration (only the first d entries are used)  */
   float act_axis[3];   /* sigma_pa = s_j diag(act_axis)                     */
+  float friction;      /* coefficient c of (L), >= 0 (bc = 1)               */
 } mpm_scene;
 
 #define MPM_MAX_ACT 4096

@@ -25,11 +25,11 @@ class MPMError(RuntimeError):
 class Scene(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_grid", ctypes.c_int32),
                 ("n_particles", ctypes.c_int32), ("n_act", ctypes.c_int32),
-                ("wall", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("wall", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("dt", ctypes.c_float), ("E", ctypes.c_float),
                 ("nu", ctypes.c_float), ("rho", ctypes.c_float),
                 ("V0", ctypes.c_float), ("gravity", ctypes.c_float * 3),
-                ("act_axis", ctypes.c_float * 3)]
+                ("act_axis", ctypes.c_float * 3), ("friction", ctypes.c_float)]
 
 
 class Opts(ctypes.Structure):

@@ -960,7 +960,9 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   for (int s = 0; s < n_scenes; ++s) {
     const mpm_scene &S = scenes[s];
     if (S.dim != dim || S.n_grid < 3 || S.n_particles < 0 || S.n_act < 0 ||
-        S.n_act > MPM_MAX_ACT || S.wall < 0 || S.reserved != 0)
+        S.n_act > MPM_MAX_ACT || S.wall < 0 || (S.bc != 0 && S.bc != 1))
+      return MPM_ERR_ARG;
+    if (S.bc == 1 && !(S.friction >= 0.0f && std::isfinite(S.friction)))
       return MPM_ERR_ARG;
     if (!(S.dt > 0.0f) || !(S.V0 > 0.0f) || !(S.rho > 0.0f) || !(S.E >= 0.0f) ||
         !(S.nu > -1.0f && S.nu < 0.5f) || !std::isfinite(S.dt) ||
@@ -1015,6 +1017,8 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
     d.n_act = S.n_act;
     d.act_off = aoff;
     d.wall = S.wall;
+    d.bc = S.bc;
+    d.fric = S.bc == 1 ? S.friction : 0.0f;
     d.tile_off = (int)toff;
     d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
     d.dt = S.dt;

@@ -30,7 +30,9 @@ struct DevScene {
   int wall;     // sticky-wall thickness in nodes
   int tile_off; // first tile of the scene (binning)
   int nt;       // tiles per axis (binning)
-  int pad_[3];
+  int bc;       // wall nodes: 0 sticky, 1 friction projection
+  float fric;   // friction coefficient (bc = 1)
+  int pad_;
   float dt, dx, inv_dx, Dinv;  // Dinv = 4 / dx^2
   float mu, la, mp, V0;        // Lame parameters, particle mass and volume
   float kG;                    // -Dinv * dt * V0 (stress part of G_p)

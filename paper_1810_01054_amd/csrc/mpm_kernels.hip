@@ -1523,8 +1523,122 @@ __device__ __forceinline__ bool is_wall(int li, int n, int wall) {
   return w;
 }
 
-// Grid operations at one node (section III step 2 with gravity and sticky
-// walls): v = p/m + dt g where m > 0, else 0; 0 on wall nodes.
+// Friction projection (supplement, friction projection gradients (L)) of a
+// node velocity against the face with inward normal s e_a (s = +-1), in
+// place: l_n = s v_a, v_t = v without its a component, l_t =
+// sqrt(|v_t|^2 + eps), l*_t = max(l_t + c min(l_n, 0), 0),
+// v* = l*_t v_t / l_t + max(l_n, 0) s e_a.
+constexpr float FRICTION_EPS = 1e-12f;
+
+template <int D>
+__device__ __forceinline__ void friction_face(float *v, int a, float s, float c) {
+  const float ln = s * v[a];
+  float lt2 = 0.0f;
+#pragma unroll
+  for (int b = 0; b < D; ++b)
+    if (b != a) lt2 += v[b] * v[b];
+  const float lt = sqrtf(lt2 + FRICTION_EPS);
+  const float lts = fmaxf(lt + c * fminf(ln, 0.0f), 0.0f);
+#pragma unroll
+  for (int b = 0; b < D; ++b)
+    v[b] = b == a ? fmaxf(ln, 0.0f) * s : lts * (v[b] / lt);
+}
+
+// Reverse of friction_face at input velocity v: vb = dL/dv* in, dL/dv out.
+// H(x) = [x >= 0], R = l_t + c min(l_n, 0); the normal component of the
+// reverse collapses to s (c H(R) H(-l_n) dL/dl*_t + H(l_n) s vb_a) because
+// v_t has no a component.
+template <int D>
+__device__ __forceinline__ void friction_face_bwd(const float *v, int a, float s,
+                                                  float c, float *vb) {
+  const float ln = s * v[a];
+  float lt2 = 0.0f;
+#pragma unroll
+  for (int b = 0; b < D; ++b)
+    if (b != a) lt2 += v[b] * v[b];
+  const float lt = sqrtf(lt2 + FRICTION_EPS);
+  const float R = lt + c * fminf(ln, 0.0f);
+  const float lts = fmaxf(R, 0.0f);
+  const float HR = R >= 0.0f ? 1.0f : 0.0f;
+  float ltsb = 0.0f, sdot = 0.0f;
+#pragma unroll
+  for (int b = 0; b < D; ++b)
+    if (b != a) {
+      ltsb += vb[b] * (v[b] / lt);   // dL/dl*_t
+      sdot += v[b] * (vb[b] * lts);  // v_t . dL/dv^_t
+    }
+  const float ltb = -sdot / (lt * lt) + ltsb * HR;
+  const float na = s * (ltsb * HR * c * (-ln >= 0.0f ? 1.0f : 0.0f) +
+                        (ln >= 0.0f ? 1.0f : 0.0f) * s * vb[a]);
+#pragma unroll
+  for (int b = 0; b < D; ++b)
+    vb[b] = b == a ? na : (ltb * v[b] + vb[b] * lts) / lt;
+}
+
+template <int D>
+__device__ __forceinline__ void node_coords(int li, int n, int *idx) {
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a) {
+    idx[a] = li % n;
+    li /= n;
+  }
+}
+
+// Boundary condition on a wall node, in place (bc = 1: one projection per
+// face whose band holds the node, axis order, low face first).
+template <int D>
+__device__ __forceinline__ void wall_bc(const DevScene &sc, int li, float *v) {
+  if (sc.bc == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = 0.0f;
+    return;
+  }
+  int idx[D];
+  node_coords<D>(li, sc.n, idx);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    if (idx[a] < sc.wall) friction_face<D>(v, a, 1.0f, sc.fric);
+    if (idx[a] >= sc.n - sc.wall) friction_face<D>(v, a, -1.0f, sc.fric);
+  }
+}
+
+// Reverse of wall_bc: v = velocity before the condition (overwritten with
+// the velocity after it), vb = dL/dv after -> dL/dv before.
+template <int D>
+__device__ __forceinline__ void wall_bc_bwd(const DevScene &sc, int li, float *v,
+                                            float *vb) {
+  if (sc.bc == 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = vb[a] = 0.0f;
+    return;
+  }
+  int idx[D];
+  node_coords<D>(li, sc.n, idx);
+  // inputs of the (at most 2 D) face stages
+  float vin[2 * D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool on = h == 0 ? idx[a] < sc.wall : idx[a] >= sc.n - sc.wall;
+      if (on) {
+#pragma unroll
+        for (int b = 0; b < D; ++b) vin[2 * a + h][b] = v[b];
+        friction_face<D>(v, a, h == 0 ? 1.0f : -1.0f, sc.fric);
+      }
+    }
+#pragma unroll
+  for (int a = D - 1; a >= 0; --a)
+#pragma unroll
+    for (int h = 1; h >= 0; --h) {
+      const bool on = h == 0 ? idx[a] < sc.wall : idx[a] >= sc.n - sc.wall;
+      if (on) friction_face_bwd<D>(vin[2 * a + h], a, h == 0 ? 1.0f : -1.0f, sc.fric, vb);
+    }
+}
+
+// Grid operations at one node (section III step 2 with gravity and the wall
+// condition): v = p/m + dt g where m > 0, else 0; then wall_bc on wall
+// nodes.
 template <int D>
 __device__ __forceinline__ void node_velocity(const DevScene &sc, int li,
                                               float m, const float *p,
@@ -1534,8 +1648,9 @@ __device__ __forceinline__ void node_velocity(const DevScene &sc, int li,
   for (int a = 0; a < D; ++a) {
     float va = 0.0f;
     if (m > 0.0f) va = p[a] / m + sc.dt * sc.g[a];
-    v[a] = wall ? 0.0f : va;
+    v[a] = va;
   }
+  if (wall) wall_bc<D>(sc, li, v);
 }
 
 template <int D>
@@ -1872,15 +1987,21 @@ __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
   float mb = 0.0f;
   if (m > 0.0f) {
     const float im = 1.0f / m;
+    float vhat[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      vhat[a] = A.gp[a * A.G + gi] / m;  // before gravity (E)
+      v[a] = vhat[a] + sc.dt * sc.g[a];
+    }
+    // wall nodes: v after the condition, dL/dv before it (sticky: 0; (L))
+    if (wall) wall_bc_bwd<D>(sc, li, v, vb);
     float dot = 0.0f;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const float vhat = A.gp[a * A.G + gi] / m;  // before gravity (E)
-      v[a] = wall ? 0.0f : vhat + sc.dt * sc.g[a];
-      pb[a] = wall ? 0.0f : vb[a] * im;          // (D)
-      dot += vhat * vb[a];
+      pb[a] = vb[a] * im;                // (D)
+      dot += vhat[a] * vb[a];
     }
-    mb = wall ? 0.0f : -dot * im;                // (E)
+    mb = -dot * im;                      // (E)
   } else {
 #pragma unroll
     for (int a = 0; a < D; ++a) v[a] = pb[a] = 0.0f;

@@ -38,7 +38,8 @@ def _check_tensor(t: torch.Tensor, shape, name):
 def scene_struct(p: dict) -> _lib.Scene:
     s = _lib.Scene()
     s.dim, s.n_grid, s.n_particles = p["dim"], p["n_grid"], p["n_particles"]
-    s.n_act, s.wall, s.reserved = p.get("n_act", 0), p.get("wall", 3), 0
+    s.n_act, s.wall, s.bc = p.get("n_act", 0), p.get("wall", 3), p.get("bc", 0)
+    s.friction = p.get("friction", 0.0)
     s.dt, s.E, s.nu = p["dt"], p["E"], p["nu"]
     s.rho, s.V0 = p["rho"], p["V0"]
     g = p.get("gravity", (0.0, -9.8, 0.0))
