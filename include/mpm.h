@@ -159,7 +159,12 @@ int mpm_step_backward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
  *   ckpt_k >= 1 every k-th state is stored and each segment of k substeps is
  *               recomputed from its checkpoint during the reverse pass (with
  *               the grids kept, on a second library stream, one segment
- *               ahead of the adjoint kernels).
+ *               ahead of the adjoint kernels);
+ *   ckpt_k = -s (1 <= s <= MPM_MAX_REVOLVE_SLOTS) binomial checkpointing:
+ *               s + 3 states and one grid whatever T (memory O(s N)); the
+ *               reverse pass follows the schedule with the fewest recomputed
+ *               substeps for s slots (mpm_revolve_steps), each substep's
+ *               grid recomputed before its adjoint.
  * If `gT` is non-NULL the reverse pass runs at once and writes the adjoint
  * of s0 to `g0` and dL/ds [T][n_act_tot] to `g_act` (DEVICE, overwritten,
  * nullable); otherwise the tape is kept for mpm_rollout_backward.  The tape
@@ -169,6 +174,20 @@ int mpm_step_backward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
 int mpm_rollout(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
                 const float *act, mpm_state *sT, const mpm_state *gT,
                 mpm_state *g0, float *g_act);
+
+#define MPM_MAX_REVOLVE_SLOTS 4096
+
+/* Binomial checkpointing schedule (host-only, no context).  Reversing L
+ * substeps from a held state with `slots` further state slots either
+ * recomputes every state from the held one (slots = 0) or advances m
+ * substeps, stores that state, reverses the last L - m with slots - 1 and
+ * then the first m with `slots`.  mpm_revolve_steps returns the fewest
+ * substeps this recomputes, F(L, c) = t L - C(c + 1 + t, t - 1) with
+ * t = min{t : C(c + 1 + t, t) >= L} (Griewank's binomial count with c + 1
+ * checkpoints); mpm_revolve_split the first split m attaining it (L >= 2,
+ * slots >= 1).  -1 on invalid arguments. */
+int64_t mpm_revolve_steps(int64_t L, int32_t slots);
+int64_t mpm_revolve_split(int64_t L, int32_t slots);
 
 /* Reverse pass over the tape of the last mpm_rollout: chain rule across the
  * T substeps from dL/ds^T (`gT`) to dL/ds^0 (`g0`) and dL/ds [T][n_act_tot]

@@ -46,11 +46,12 @@ struct mpm_ctx {
 
   // captured inner loops of rollouts (forward, reverse)
   struct GraphKey {
-    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0, ctl = 0;
+    int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0, ctl = 0, rev = 0;
     const void *p[8] = {};
     bool operator==(const GraphKey &o) const {
       if (T != o.T || k != o.k || memo != o.memo || grids_all != o.grids_all ||
-          sorted != o.sorted || nch != o.nch || nne != o.nne || ctl != o.ctl)
+          sorted != o.sorted || nch != o.nch || nne != o.nne || ctl != o.ctl ||
+          rev != o.rev)
         return false;
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
@@ -107,6 +108,8 @@ struct mpm_ctx {
   // tape
   struct Tape {
     int valid = 0, T = 0, k = 0, memo = 0, sorted = 0, grids_all = 0;
+    int rev = 0;              // > 0: binomial checkpointing with rev slots
+    int rev_spine = 0;        // its first-descent checkpoints are intact
     float *states = nullptr;  // slots of one state each
     int64_t state_cap = 0;    // slots allocated
     float *grids = nullptr;   // slots of (1 + d) * G floats (m, p)
@@ -580,6 +583,7 @@ const int *cur_act_id(mpm_ctx *c) {
 // forward state S^n for the rollout (ckpt mode; n is a checkpoint or lives in
 // the ping-pong pair)
 float *fwd_slot(mpm_ctx *c, const Layout &L, int n) {
+  if (c->tape.rev) return slot_state(c, n == L.T && n > 0 ? c->tape.rev + 2 : 0);
   if (L.memo) return slot_state(c, n);
   if (n % L.k == 0) return slot_state(c, n / L.k);
   if (n == L.T) return slot_state(c, L.ncp - 1);
@@ -642,8 +646,144 @@ mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
   k.p[5] = c->gact;
   k.p[7] = c->ctl.on ? c->ctl.Z : nullptr;
   k.ctl = c->ctl.on ? c->ctl.nz : 0;
+  k.rev = t.rev ? 2 * t.rev + t.rev_spine : 0;
   return k;
 }
+
+// ---- binomial checkpointing ------------------------------------------------
+// Reversing L substeps from a held state with c further state slots: either
+// recompute every state from the held one (c = 0: L (L - 1) / 2 substeps) or
+// advance m substeps, store that state, reverse the last L - m substeps with
+// c - 1 slots and then the first m with c slots.  The fewest substeps this
+// takes is the binomial count of Griewank's checkpointing analysis,
+//   F(L, c) = t L - beta(c + 2, t - 1),  t = min{t : beta(c + 1, t) >= L},
+//   beta(c, t) = (c + t)! / (c! t!),
+// and the split taken is the first m that attains it.
+
+int64_t rev_beta(int64_t c, int64_t t) {
+  if (t < 0) return 0;
+  // C(c + t, t) with saturation (the values compared against are < 2^62)
+  double b = 1.0;
+  for (int64_t i = 1; i <= t; ++i) {
+    b = b * (double)(c + i) / (double)i;
+    if (b > 4.0e18) return (int64_t)4e18;
+  }
+  return (int64_t)std::llround(b);
+}
+
+int64_t rev_cost(int64_t L, int64_t c) {
+  if (L <= 1) return 0;
+  if (c <= 0) return L * (L - 1) / 2;
+  int64_t t = 0;
+  while (rev_beta(c + 1, t) < L) ++t;
+  return t * L - rev_beta(c + 2, t - 1);
+}
+
+int64_t rev_split(int64_t L, int64_t c) {
+  const int64_t best = rev_cost(L, c);
+  for (int64_t m = 1; m < L; ++m)
+    if (m + rev_cost(L - m, c - 1) + rev_cost(m, c) == best) return m;
+  return L / 2;  // not reached when the closed form holds
+}
+
+// Forward substep n of a rollout: state `in` -> state `out` (must differ).
+int fwd_substep(mpm_ctx *c, int n, const State &in, const State &out) {
+  int nch = 0;
+  const Chunk *chunks = cur_chunks(c, &nch);
+  const bool tiles = c->tape.sorted;
+  const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
+  RC(fwd_p2g(c, tiles, chunks, nch, cs(in), cur_act_id(c), act, c->gm, c->gp));
+  RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
+  return fwd_g2p(c, chunks, nch, cs(in), out, c->gv);
+}
+
+int ctl_forward(mpm_ctx *c, const State &s, int n);
+int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g);
+
+// Binomial tapes: slot 0 = S^0, slots 1..rev = checkpoints, slot rev + 1 =
+// work state, slot rev + 2 = S^T.  The forward sweep stores the checkpoints
+// of the reverse schedule's first descent (its rightmost path).
+int rollout_forward_revolve(mpm_ctx *c, int T) {
+  const int64_t sf = c->state_floats();
+  const int R = c->tape.rev;
+  std::vector<int> slot_at((size_t)T + 1, -1);
+  int64_t lo = 0, cf = R;
+  int slot = 0;
+  while (T - lo > 1 && cf > 0) {
+    lo += rev_split(T - lo, cf);
+    slot_at[(size_t)lo] = ++slot;
+    --cf;
+  }
+  float *cur = slot_state(c, 0);
+  for (int n = 0; n < T; ++n) {
+    float *dst = n + 1 == T ? slot_state(c, R + 2)
+                 : slot_at[(size_t)n + 1] >= 0 ? slot_state(c, slot_at[(size_t)n + 1])
+                 : c->tape.pp + (int64_t)((n + 1) & 1) * sf;
+    if (c->ctl.on) RC(ctl_forward(c, state_at(c, cur), n));
+    RC(fwd_substep(c, n, state_at(c, cur), state_at(c, dst)));
+    cur = dst;
+  }
+  return MPM_OK;
+}
+
+// Reverse pass of a binomial tape.  A0/A1: the adjoint ping-pong pair (the
+// adjoint of S^T in A1 on entry).
+struct RevolveRun {
+  mpm_ctx *c;
+  State A0, A1;
+  int nga;
+
+  // S^{n0} in `src` -> S^{n1} in `dst` (n1 > n0), intermediates in the tape's
+  // ping-pong pair
+  int advance(float *src, int n0, int n1, float *dst) {
+    const int64_t sf = c->state_floats();
+    for (int n = n0; n < n1; ++n) {
+      float *in = n == n0 ? src : c->tape.pp + (int64_t)((n - n0) & 1) * sf;
+      float *out = n + 1 == n1 ? dst : c->tape.pp + (int64_t)((n + 1 - n0) & 1) * sf;
+      RC(fwd_substep(c, n, state_at(c, in), state_at(c, out)));
+    }
+    return MPM_OK;
+  }
+  // adjoint of substep n from S^n: the grid of step n is recomputed first
+  int leaf(int n, float *sbuf) {
+    int nch = 0;
+    const Chunk *chunks = cur_chunks(c, &nch);
+    const bool tiles = c->tape.sorted;
+    const State s = state_at(c, sbuf);
+    const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
+    float *g = slot_grid(c, 0);
+    RC(fwd_p2g(c, tiles, chunks, nch, cs(s), cur_act_id(c), act, c->gm, c->gp));
+    RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
+    double *ga = nga ? c->gact + (int64_t)n * c->n_act : nullptr;
+    RC(bwd_step(c, tiles, chunks, nch, cs(s), cur_act_id(c), act, g, g + c->G,
+                cs(A1), A0, ga));
+    if (c->ctl.on) RC(ctl_adjoint(c, n, ga, A0));
+    std::swap(A0, A1);
+    return MPM_OK;
+  }
+  // reverse substeps [lo, hi) from S^lo in slot `slot`, cf free slots above
+  // it; `stored`: the first-descent checkpoints are already in place
+  int run(int lo, int hi, int64_t cf, int slot, bool stored) {
+    const int L = hi - lo;
+    if (L == 1) return leaf(lo, slot_state(c, slot));
+    if (cf == 0) {
+      float *work = slot_state(c, c->tape.rev + 1);
+      for (int n = hi - 1; n >= lo; --n) {
+        float *sb = slot_state(c, slot);
+        if (n > lo) {
+          RC(advance(sb, lo, n, work));
+          sb = work;
+        }
+        RC(leaf(n, sb));
+      }
+      return MPM_OK;
+    }
+    const int m = lo + (int)rev_split(L, cf);
+    if (!stored) RC(advance(slot_state(c, slot), lo, m, slot_state(c, slot + 1)));
+    RC(run(m, hi, cf - 1, slot + 1, stored));
+    return run(lo, m, cf, slot, false);
+  }
+};
 
 // Controller at substep n: component means of state n -> z^n (tape) ->
 // a^n = tanh(W z^n + b) into the tape's actuation row n.
@@ -696,6 +836,7 @@ int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g) {
 }
 
 int rollout_forward(mpm_ctx *c, const Layout &L) {
+  if (c->tape.rev) return rollout_forward_revolve(c, L.T);
   int nch = 0;
   const Chunk *chunks = cur_chunks(c, &nch);
   const int *ids = cur_act_id(c);
@@ -747,6 +888,13 @@ int rollout_backward_core(mpm_ctx *c) {
   if (c->ctl.on) {
     RC(launch_fill_f64(c->ctl.gW, (int64_t)c->n_act * c->ctl.nz, c->stream));
     RC(launch_fill_f64(c->ctl.gb, c->n_act, c->stream));
+  }
+  if (t.rev) {
+    // A1 holds the adjoint of S^T (adj slot 0): the first leaf reads it.
+    // The schedule overwrites the first-descent checkpoints; a later reverse
+    // pass over the same tape advances them again from S^0.
+    RevolveRun r{c, A0, A1, nga > 0 ? 1 : 0};
+    return t.T > 0 ? r.run(0, t.T, t.rev, 0, t.rev_spine != 0) : MPM_OK;
   }
   const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
   const int seglen = t.memo ? 1 : t.k;
@@ -840,6 +988,7 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   const int64_t nga = (int64_t)t.T * c->n_act;
   if (nga > 0) RC(ensure_gact(c, nga));
   RC(run_maybe_graph(c, c->gbwd, graph_key(c), [&] { return rollout_backward_core(c); }));
+  t.rev_spine = 0;  // (outside the captured body: replays skip the body)
   const State A_out = state_at(c, t.adj + (t.T & 1) * sf);
   if (t.sorted) RC(permute_state(c, ms(A_out), st(*g0), 1));
   else RC(copy_state(c, ms(A_out), st(*g0)));
@@ -1280,20 +1429,23 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
                 const float *act, const mpm_controller *ctl, mpm_state *sT) {
   auto &t = c->tape;
   t.valid = 0;
+  t.rev_spine = 0;
   c->ctl.on = 0;
+  const int rev = ckpt_k < 0 ? -ckpt_k : 0;
   const int memo = ckpt_k == 0;
-  const int k = memo ? 1 : std::min(ckpt_k, std::max(T, 1));
-  const int ncp = memo ? T + 1 : (T + k - 1) / k + 1;
-  const int grids_all = memo || c->keep_grids;
+  const int k = memo || rev ? 1 : std::min(ckpt_k, std::max(T, 1));
+  const int ncp = rev ? rev + 3 : memo ? T + 1 : (T + k - 1) / k + 1;
+  const int grids_all = !rev && (memo || c->keep_grids);
   // checkpointed tapes with stored grids keep two banks of segment states:
   // the reverse pass recomputes one segment while it runs the adjoint of
-  // the next
-  const int64_t nstates = memo ? T + 1 : ncp + (grids_all ? 2 * k : k);
-  const int64_t ngrids = grids_all ? T : k;
+  // the next; binomial tapes hold rev + 3 states and one grid
+  const int64_t nstates = rev ? ncp : memo ? T + 1 : ncp + (grids_all ? 2 * k : k);
+  const int64_t ngrids = rev ? 1 : grids_all ? T : k;
   RC(ensure_tape(c, nstates, ngrids, (int64_t)T * c->n_act));
   t.T = T;
   t.k = k;
   t.memo = memo;
+  t.rev = rev;
   t.grids_all = grids_all;
   t.sorted = c->sort && c->N > 0;
   if (!ctl && c->n_act && T > 0)
@@ -1315,6 +1467,7 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   const State ST = state_at(c, fwd_slot(c, L, T));
   if (t.sorted) RC(permute_state(c, ms(ST), st(*sT), 1));
   else RC(copy_state(c, ms(ST), st(*sT)));
+  t.rev_spine = rev ? 1 : 0;
   t.valid = 1;
   return MPM_OK;
 }
@@ -1323,11 +1476,21 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
 
 extern "C" {
 
+int64_t mpm_revolve_steps(int64_t L, int32_t slots) {
+  if (L < 0 || slots < 0) return -1;
+  return rev_cost(L, slots);
+}
+
+int64_t mpm_revolve_split(int64_t L, int32_t slots) {
+  if (L < 2 || slots < 1) return -1;
+  return rev_split(L, slots);
+}
+
 int mpm_rollout(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
                 const float *act, mpm_state *sT, const mpm_state *gT,
                 mpm_state *g0, float *g_act) {
   RC(check_ctx(c));
-  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) ||
+  if (T < 0 || ckpt_k < -MPM_MAX_REVOLVE_SLOTS || !state_ok(c, s0) || !state_ok(c, sT) ||
       (c->n_act && T > 0 && !act) || (gT && !state_ok(c, gT)) ||
       (gT && !state_ok(c, g0)))
     return MPM_ERR_ARG;
@@ -1341,7 +1504,7 @@ int mpm_rollout_ctrl(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
                      const mpm_state *gT, mpm_state *g0, float *g_act,
                      float *g_W, float *g_b) {
   RC(check_ctx(c));
-  if (T < 0 || ckpt_k < 0 || !state_ok(c, s0) || !state_ok(c, sT) || !ctl ||
+  if (T < 0 || ckpt_k < -MPM_MAX_REVOLVE_SLOTS || !state_ok(c, s0) || !state_ok(c, sT) || !ctl ||
       (gT && !state_ok(c, gT)) || (gT && !state_ok(c, g0)))
     return MPM_ERR_ARG;
   if (c->n_scenes != 1 || c->N < 1 || c->n_act < 1 || c->n_act > CTL_MAX_ACT ||

@@ -1,0 +1,130 @@
+"""GPU parity of binomial checkpointing (mpm_rollout with ckpt_k = -s: s
+state slots whatever T, the reverse pass recomputing states by the schedule
+with the fewest recomputed substeps) against the oracle's memo rollout and
+against the library's own memo tape.  Tolerances: positions 1e-5 and
+gradients 1e-3 against the oracle; against the memo tape 1e-5 (states) and
+1e-4 (adjoints), the two differing only in FP32 rounding (the binned
+scatter orders each cell's particles by arrival)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1810_01054_amd import scenes as S
+from tests.helpers import oscene, f64, rel_err
+from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, gpu_act_bank
+
+pytestmark = pytest.mark.gpu
+
+POS_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _seed(sc, seed):
+    rng = np.random.default_rng(seed)
+    N, d = sc.n_particles, sc.dim
+    return [(rng.normal(size=(d, N)) / N).astype(np.float32),
+            (rng.normal(size=(d, N)) / N).astype(np.float32),
+            np.zeros((d * d, N), np.float32), np.zeros((d * d, N), np.float32)]
+
+
+def _cases():
+    return [
+        ("c1b", S.config_1b(), 60, (1, 3, 8)),
+        ("box3d_contact", S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=31), 40, (2, 5)),
+        ("contact2d_friction", S.wall_contact(2, n=32, n_particles=800, seed=27, friction=0.3),
+         30, (4,)),
+    ]
+
+
+@pytest.mark.parametrize("name,sc,T,slots", _cases(), ids=[c[0] for c in _cases()])
+def test_revolve_rollout_matches_oracle(name, sc, T, slots):
+    acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    gT = _seed(sc, 51)
+    refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                         acts.astype(np.float64), f64(gT))
+    sim = sim_for(sc)
+    for s in slots:
+        say("revolve", name, sc.n_particles, "T", T, "slots", s)
+        sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
+                                   ckpt_k=-s, gT=to_gpu(gT))
+        sim.sync_errors()
+        assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+        for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
+            assert rel_err(a, r) < GRAD_TOL, (s, c, rel_err(a, r))
+        assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+        # the tape can be reversed again (its checkpoints are re-advanced)
+        g0b, gactb = sim.rollout_backward(to_gpu(gT), T)
+        sim.sync_errors()
+        for a, b in zip(to_np(g0b), to_np(g0)):
+            assert rel_err(a, b) < 1e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("T,s", [(1, 1), (2, 1), (3, 10), (7, 2)])
+def test_revolve_short_rollouts(T, s):
+    sc = S.tiny_3d(n=12, n_particles=24)
+    acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    gT = _seed(sc, 52)
+    refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                         acts.astype(np.float64), f64(gT))
+    sim = sim_for(sc)
+    say("revolve_short", T, s)
+    sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
+                               ckpt_k=-s, gT=to_gpu(gT))
+    sim.sync_errors()
+    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    for a, r in zip(to_np(g0), ref0):
+        assert rel_err(a, r) < GRAD_TOL
+    sim.close()
+
+
+def test_revolve_c2_300_steps_equals_memo():
+    sc = S.config_2()
+    T = 300
+    act = gpu_act_bank(sc, T)
+    gT = _seed(sc, 53)
+    sim = sim_for(sc)
+    outs = []
+    for k in (0, -6):
+        say("revolve_c2", k)
+        sT, g0, gact = sim.rollout(to_gpu(sc.state), act, T, ckpt_k=k, gT=to_gpu(gT))
+        sim.sync_errors()
+        outs.append((to_np(sT), to_np(g0), gact.cpu().numpy()))
+    (sa, ga, aa), (sb, gb, ab) = outs
+    for c in range(4):
+        assert rel_err(sb[c], sa[c]) < 1e-5
+        assert rel_err(gb[c], ga[c]) < 1e-4, (c, rel_err(gb[c], ga[c]))
+    assert rel_err(ab, aa) < 1e-4
+    sim.close()
+
+
+def test_revolve_with_controller_and_graphs():
+    sc = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=38)
+    T = 24
+    comp, nc, W, b, target = S.controller_params(sc, seed=14)
+    gT = _seed(sc, 54)
+    refT, racts, r0, rW, rb = oracle.rollout_ctrl(
+        oscene(sc), f64(sc.state), T, comp, nc, W.astype(np.float64), b.astype(np.float64),
+        target.astype(np.float64), act_id=sc.act_id, gradT=f64(gT))
+    cu = lambda a, dt=torch.float32: torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    for graphs in (False, True):
+        sim = sim_for(sc, graphs=graphs)
+        for rep in range(2 if graphs else 1):
+            say("revolve_ctrl", graphs, rep)
+            sT, act, g0, gact, gW, gb = sim.rollout_ctrl(
+                to_gpu(sc.state), T, cu(comp, torch.int32), nc, cu(W), cu(b), cu(target),
+                ckpt_k=-3, gT=to_gpu(gT))
+            sim.sync_errors()
+            assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+            assert rel_err(act.cpu().numpy(), racts) < POS_TOL
+            for a, r in zip(to_np(g0), r0):
+                assert rel_err(a, r) < GRAD_TOL
+            assert rel_err(gW.cpu().numpy(), rW) < GRAD_TOL
+            assert rel_err(gb.cpu().numpy(), rb) < GRAD_TOL
+        sim.close()
