@@ -16,6 +16,7 @@ x, v ``[d][N]``, C, F ``[d*d][N]`` (entry (a, b) at row ``a*d+b``), grids
 from __future__ import annotations
 
 import ctypes
+from typing import Optional
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -59,7 +60,9 @@ class _Scene(ctypes.Structure):
                 ("V0", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3),
                 ("act_axis", ctypes.c_double * 3),
-                ("friction", ctypes.c_double)]
+                ("friction", ctypes.c_double),
+                ("E_p", ctypes.c_void_p), ("rho_p", ctypes.c_void_p),
+                ("gE_p", ctypes.c_void_p), ("grho_p", ctypes.c_void_p)]
 
 
 _lib = None
@@ -162,12 +165,32 @@ class Scene:
     act_axis: tuple = (0.0, 1.0, 0.0)
     bc: int = 0              # wall nodes: 0 sticky, 1 friction projection (L)
     friction: float = 0.0    # coefficient c of (L)
+    E_p: Optional[np.ndarray] = None     # per-particle Young's modulus [N]
+    rho_p: Optional[np.ndarray] = None   # per-particle density [N]
+    gE_p: Optional[np.ndarray] = None    # reverse passes ADD dL/dE_p here [N]
+    grho_p: Optional[np.ndarray] = None  # reverse passes ADD dL/drho_p here [N]
 
     def c(self) -> _Scene:
         s = _Scene()
         s.dim, s.n_grid, s.n_particles = self.dim, self.n_grid, self.n_particles
         s.n_act, s.wall, s.bc = self.n_act, self.wall, self.bc
         s.friction = self.friction
+        # per-particle arrays: FP64 contiguous buffers kept alive on self
+        N = self.n_particles
+        for name in ("E_p", "rho_p", "gE_p", "grho_p"):
+            a = getattr(self, name)
+            if a is None:
+                setattr(s, name, None)
+                continue
+            if name in ("gE_p", "grho_p"):
+                if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and
+                        a.flags.c_contiguous and a.shape == (N,)):
+                    raise ValueError(f"{name} must be a contiguous float64 array of shape ({N},)")
+                buf = a
+            else:
+                buf = np.ascontiguousarray(a, dtype=np.float64).reshape(N)
+                object.__setattr__(self, "_keep_" + name, buf)
+            setattr(s, name, buf.ctypes.data)
         s.dt, s.E, s.nu, s.rho, s.V0 = (self.dt, self.E, self.nu, self.rho,
                                         self.V0)
         for k in range(3):

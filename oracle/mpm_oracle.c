@@ -33,7 +33,10 @@
  *     particle position x_p (the printed derivative with respect to the node
  *     position would flip the sign of every such term);
  *   - in (E) the velocity multiplying dL/dv_i is the normalised momentum
- *     p_i/m_i before gravity is added.
+ *     p_i/m_i before gravity is added;
+ *   - per-particle materials (the paper's co-design and system
+ *     identification): E_p and rho_p replace the scene's E and rho for
+ *     particle p (nu and V0 stay per scene), m_p = rho_p V0.
  */
 #include "mpm_oracle.h"
 
@@ -264,15 +267,22 @@ typedef struct stress {
   double J, lnJ;
 } stress;
 
+/* Material of particle p: Lame parameters from E_p (or the scene's E) and
+ * the scene's nu; mass m_p = rho_p V0 (or the scene's rho). */
+static void particle_material(const orc_scene *s, long p, double *mu, double *la,
+                              double *mp) {
+  orc_lame(s->E_p ? s->E_p[p] : s->E, s->nu, mu, la);
+  *mp = (s->rho_p ? s->rho_p[p] : s->rho) * s->V0;
+}
+
 static int particle_stress(const orc_scene *s, const int32_t *act_id,
                            const double *act, long p, const double *Cp,
                            const double *Fp, stress *out) {
   int d = s->dim;
-  double mu, la;
-  orc_lame(s->E, s->nu, &mu, &la);
+  double mu, la, mp;
+  particle_material(s, p, &mu, &la, &mp);
   double dx = 1.0 / (double)s->n_grid;
   double Dinv = 4.0 / (dx * dx);
-  double mp = s->rho * s->V0;
   int rc = orc_neohookean_P(d, mu, la, Fp, out->P);
   if (rc) return rc;
   out->J = det_d(d, Fp);
@@ -303,11 +313,11 @@ int orc_p2g(const orc_scene *s, const int32_t *act_id, const double *act,
   if (!scene_ok(s)) return ORC_ERR_ARG;
   int d = s->dim;
   long nn = n_nodes(s);
-  double mp = s->rho * s->V0;
   memset(gm, 0, sizeof(double) * nn);
   memset(gp, 0, sizeof(double) * nn * d);
   for (long p = 0; p < s->n_particles; ++p) {
-    double xp[3], vp[3], Cp[9], Fp[9];
+    double xp[3], vp[3], Cp[9], Fp[9], mu, la, mp;
+    particle_material(s, p, &mu, &la, &mp);
     load_particle(s, p, x, v, C, F, xp, vp, Cp, Fp);
     stencil st;
     int rc = stencil_setup(s, xp, &st);
@@ -578,9 +588,10 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
   long N = s->n_particles, nn = n_nodes(s);
   double dx = 1.0 / (double)s->n_grid;
   double Dinv = 4.0 / (dx * dx);
-  double mp = s->rho * s->V0, dt = s->dt;
-  double mu, la;
-  orc_lame(s->E, s->nu, &mu, &la);
+  double dt = s->dt;
+  /* d mu / dE and d la / dE (Lame parameters are linear in E) */
+  double dmu_dE, dla_dE;
+  orc_lame(1.0, s->nu, &dmu_dE, &dla_dE);
 
   double *gm = (double *)malloc(sizeof(double) * nn);
   double *gpm = (double *)malloc(sizeof(double) * nn * d);
@@ -666,6 +677,8 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
     stress sp;
     rc = particle_stress(s, act_id, act, p, Cp, Fp, &sp);
     if (rc) goto done;
+    double mu, la, mp;
+    particle_material(s, p, &mu, &la, &mp);
 
     /* C_p^{n+1}, recomputed as in the forward G2P */
     double B[9] = {0};
@@ -688,6 +701,7 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
     for (int k = 0; k < d * d; ++k) Ct[k] = gC1p[k] + dt * GFt[k];
 
     double xb[3], vb[3] = {0, 0, 0}, Gb[9] = {0};
+    double Spb[3] = {0, 0, 0}, Nmb = 0.0;  /* sum N dL/dp_i, sum N dL/dm_i */
     /* x_p^{n+1} = x_p^n + dt v^{n+1}: the direct term of (J) */
     for (int a = 0; a < d; ++a) xb[a] = gx1p[a];
 
@@ -705,6 +719,7 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
       for (int a = 0; a < d; ++a) {
         /* (F) dL/dv_p^n += N m_p dL/dp_i */
         vb[a] += Nw * mp * pb[a];
+        Spb[a] += Nw * pb[a];
         /* dL/dG_p += N dL/dp_i (x_i - x_p)^T, used by (G), (H), (I) */
         for (int b = 0; b < d; ++b) Gb[a * d + b] += Nw * pb[a] * delta[b];
       }
@@ -721,6 +736,7 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
         s_p += pb[a] * q;
       }
       double s_all = s_v + Dinv * s_C + s_p + mp * mb;
+      Nmb += Nw * mb;
       for (int c = 0; c < d; ++c) {
         /* (J): dN/dx_p terms of v^{n+1}, C^{n+1}, p_i and m_i */
         xb[c] += gradN[c] * s_all;
@@ -764,6 +780,23 @@ int orc_step_bwd(const orc_scene *s, const int32_t *act_id, const double *act,
     for (int k = 0; k < d * d; ++k) inner += Ptb[k] * sp.FiT[k];
     for (int k = 0; k < d * d; ++k)
       Fb[k] += mu * Ptb[k] + (mu - la * sp.lnJ) * T2[k] + la * inner * sp.FiT[k];
+
+    /* per-particle materials (co-design, system identification):
+     *   dL/dm_p = sum_i N [dL/dm_i + dL/dp_i . (v_p + C_p (x_i - x_p))]
+     *           (m_p enters m_i, m_p v_p and G_p = ... + m_p C_p),
+     *   dL/dmu_p = <dL/dP, F - F^-T>,  dL/dla_p = <dL/dP, ln J F^-T>,
+     *   dL/dE_p = dL/dmu dmu/dE + dL/dla dla/dE,  dL/drho_p = V0 dL/dm_p */
+    if (s->gE_p) {
+      double mub = 0.0;
+      for (int k = 0; k < d * d; ++k) mub += Ptb[k] * (Fp[k] - sp.FiT[k]);
+      s->gE_p[p] += mub * dmu_dE + sp.lnJ * inner * dla_dE;
+    }
+    if (s->grho_p) {
+      double mbp = Nmb;
+      for (int a = 0; a < d; ++a) mbp += vp[a] * Spb[a];
+      for (int k = 0; k < d * d; ++k) mbp += Cp[k] * Gb[k];
+      s->grho_p[p] += s->V0 * mbp;
+    }
 
     /* (K) dL/dsigma = F^T dL/dP; sigma = s_j diag(axis) */
     int j = act_id ? act_id[p] : -1;

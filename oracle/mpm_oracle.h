@@ -51,6 +51,11 @@ typedef struct orc_scene {
   double gravity[3];
   double act_axis[3];  /* sigma_pa = s_j * diag(act_axis) */
   double friction;     /* friction coefficient c of (L), bc = 1 */
+  /* per-particle materials (nullable [N]): E_p, rho_p replace E, rho for
+   * particle p; the reverse pass ADDS dL/dE_p, dL/drho_p to gE_p, grho_p
+   * (nullable [N]) */
+  const double *E_p, *rho_p;
+  double *gE_p, *grho_p;
 } orc_scene;
 
 /* (L) friction projection of one node velocity v (d entries) against a wall

@@ -400,3 +400,15 @@ def wall_contact(dim: int = 2, n: int = 16, n_particles: int = 40, seed: int = 9
     sc.F = F.astype(F32)
     sc.bc, sc.friction = 1, _f32(friction)
     return sc
+
+
+def material_field(scene: Scene, seed: int, E_spread: float = 0.5,
+                   rho_spread: float = 0.3):
+    """Seeded per-particle materials (a stiffness and density field for
+    co-design / identification): E_p = E (1 + U[-E_spread, E_spread)),
+    rho_p = rho (1 + U[-rho_spread, rho_spread)), FP32 [N] each."""
+    rng = np.random.default_rng(seed)
+    N = scene.n_particles
+    E_p = scene.E * (1.0 + rng.uniform(-E_spread, E_spread, size=N))
+    rho_p = scene.rho * (1.0 + rng.uniform(-rho_spread, rho_spread, size=N))
+    return E_p.astype(F32), rho_p.astype(F32)

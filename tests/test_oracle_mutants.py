@@ -89,6 +89,35 @@ def _run_friction_pins():
     return failed
 
 
+# Mistakes in the per-particle material gradients, caught by the material
+# pins (Euler relation, central differences).
+MATERIAL_MUTANTS = [
+    ("mat_mass_grid_term_dropped", "double mbp = Nmb;", "double mbp = 0.0;"),
+    ("mat_mass_apic_term_dropped", "for (int k = 0; k < d * d; ++k) mbp += Cp[k] * Gb[k];", ""),
+    ("mat_mass_velocity_term_dropped", "for (int a = 0; a < d; ++a) mbp += vp[a] * Spb[a];", ""),
+    ("mat_mu_without_inverse", "mub += Ptb[k] * (Fp[k] - sp.FiT[k]);", "mub += Ptb[k] * Fp[k];"),
+    ("mat_lambda_without_lnJ", "s->gE_p[p] += mub * dmu_dE + sp.lnJ * inner * dla_dE;",
+     "s->gE_p[p] += mub * dmu_dE + inner * dla_dE;"),
+    ("mat_rho_without_V0", "s->grho_p[p] += s->V0 * mbp;", "s->grho_p[p] += mbp;"),
+    ("mat_forward_mass_scene", "*mp = (s->rho_p ? s->rho_p[p] : s->rho) * s->V0;",
+     "*mp = s->rho * s->V0;"),
+]
+
+
+def _run_material_pins():
+    from tests import test_oracle_materials as mt
+    failed = []
+    for name, fn in [("uniform", mt.test_uniform_fields_reproduce_the_scene_rollout),
+                     ("scaling", lambda: mt.test_scaling_mass_and_stiffness_together_leaves_the_motion(2)),
+                     ("euler", lambda: mt.test_euler_relation_of_the_material_gradients(2)),
+                     ("fd", lambda: mt.test_material_gradients_match_central_differences(2))]:
+        try:
+            fn()
+        except (AssertionError, oracle.OracleError, ValueError):
+            failed.append(name)
+    return failed
+
+
 def _run_ctrl_pins():
     from tests import test_oracle_ctrl as ctrl
     failed = []
@@ -172,3 +201,17 @@ def test_friction_mutant_is_caught(name, old, new, tmp_path):
     with oracle.use_library(str(lib)):
         failed = _run_friction_pins()
     assert failed, f"mutant {name} passed every friction pin"
+
+
+@pytest.mark.parametrize("name,old,new", MATERIAL_MUTANTS, ids=[m[0] for m in MATERIAL_MUTANTS])
+def test_material_mutant_is_caught(name, old, new, tmp_path):
+    assert SRC.count(old) == 1, f"mutation anchor for {name} not unique"
+    src = tmp_path / "mutant.c"
+    src.write_text(SRC.replace(old, new))
+    hdr = os.path.join(os.path.dirname(oracle.__file__), "mpm_oracle.h")
+    (tmp_path / "mpm_oracle.h").write_text(open(hdr).read())
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", *oracle.CFLAGS, "-o", str(lib), str(src), "-lm"], check=True)
+    with oracle.use_library(str(lib)):
+        failed = _run_material_pins()
+    assert failed, f"mutant {name} passed every material pin"
