@@ -235,6 +235,26 @@ int mpm_rollout_ctrl(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
 int mpm_rollout_ctrl_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
                               float *g_act, float *g_W, float *g_b);
 
+/* Per-particle materials (the co-design and system-identification uses of
+ * section IV: a stiffness or density field instead of one material per
+ * scene).  E_p, rho_p: DEVICE float [N_tot] in caller order, each nullable
+ * (NULL = the scene's E or rho); both NULL switches the field off.  The
+ * particle's Lame parameters follow from E_p and its scene's nu, its mass is
+ * rho_p V0.  The values are copied; they apply to every later forward and
+ * reverse call (set them before a rollout and keep them until its reverse
+ * pass).  With a field, the binned P2G scatters with per-particle LDS
+ * atomics (the mass rides with each particle) and 3D rollouts do not fuse
+ * G2P with the next P2G. */
+int mpm_set_materials(mpm_ctx *ctx, const float *E_p, const float *rho_p);
+
+/* dL/dE_p and dL/drho_p (DEVICE float [N_tot], caller order, overwritten,
+ * each nullable) accumulated by the last reverse pass (mpm_rollout with gT,
+ * mpm_rollout_backward, mpm_rollout_ctrl(_backward) or mpm_step_backward):
+ * summed over its substeps, through the stress (mu_p, la_p) and the mass
+ * (m_i, m_p v_p and the m_p C_p part of G_p).  MPM_ERR_STATE without a
+ * material field or before any reverse pass since it was set. */
+int mpm_material_grad(mpm_ctx *ctx, float *g_E, float *g_rho);
+
 /* Copy the grid of the last mpm_step_forward (DEVICE, caller-owned,
  * nullable): m [G], p [d][G], v [d][G] with G the total node count (scenes
  * concatenated in order, each n_s^d nodes).  Stream-ordered copy. */

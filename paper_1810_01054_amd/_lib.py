@@ -54,7 +54,8 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_rollout_backward", "mpm_get_grid", "mpm_act_bank_forward",
            "mpm_act_bank_backward", "mpm_sync_errors", "mpm_strerror",
            "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
-           "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split"]
+           "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split",
+           "mpm_set_materials", "mpm_material_grad"]
 
 KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
 
@@ -86,6 +87,8 @@ def lib():
     L.mpm_rollout_ctrl.argtypes = [vp, i32, i32, sp, ctypes.POINTER(Controller), sp, vp,
                                    sp, sp, vp, vp, vp]
     L.mpm_rollout_ctrl_backward.argtypes = [vp, sp, sp, vp, vp, vp]
+    L.mpm_set_materials.argtypes = [vp, vp, vp]
+    L.mpm_material_grad.argtypes = [vp, vp, vp]
     L.mpm_revolve_steps.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.mpm_revolve_steps.restype = ctypes.c_int64
     L.mpm_revolve_split.argtypes = [ctypes.c_int64, ctypes.c_int32]

@@ -120,6 +120,11 @@ struct mpm_ctx {
     float *adj = nullptr;     // two adjoint states
   } tape;
 
+  // per-particle materials: (mu, la, m_p) [3][N] in caller and tape order,
+  // and the reverse pass's dL/dmu, dL/dla, dL/dm_p [3][N]
+  float *mat_user = nullptr, *mat_sorted = nullptr, *gmat = nullptr;
+  int has_mat = 0, gmat_sorted = 0, gmat_valid = 0;
+
   // closed-loop controller of the current tape (one scene; section IV)
   struct Ctl {
     int on = 0, n_comp = 0, nz = 0;
@@ -287,11 +292,14 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   a.G = c->G;
   a.err = c->d_err;
   a.tiles = tile_info(c);
+  // per-particle materials: the scatters that keep each particle's mass in
+  // registers (caller order: global atomics; binned: LDS atomics per tile)
+  a.mat = c->has_mat ? (tiles ? c->mat_sorted : c->mat_user) : nullptr;
   ProfScope ps(c, MPM_K_P2G);
-  if (tiles && c->scatter_mode == 3)
+  if (tiles && c->scatter_mode == 3 && !c->has_mat)
     return launch_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
   a.tiles.list = nullptr;  // the other binned modes launch one block per tile
-  if (tiles && c->scatter_mode == 2)
+  if (tiles && c->scatter_mode == 2 && !c->has_mat)
     return launch_p2g_cell(c->dim, a, c->d_cell_cnt, c->n_tiles, c->stream);
   if (tiles) return launch_p2g_tile(c->dim, a, c->n_tiles, c->stream);
   return launch_p2g(c->dim, a, c->stream);
@@ -423,6 +431,8 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r3.G = c->G;
   r3.gact = gact;
   r3.err = c->d_err;
+  r3.mat = c->has_mat ? (tiles ? c->mat_sorted : c->mat_user) : nullptr;
+  r3.gmat = c->has_mat ? c->gmat : nullptr;
   ProfScope ps(c, MPM_K_ADJ_GATHER);
   return launch_adj_gather(c->dim, r3, c->stream);
 }
@@ -467,6 +477,9 @@ int bin_particles(mpm_ctx *c, const float *x) {
   RC(launch_build_chunks(c->d_tile_cnt, c->d_tile_start, c->d_chunk_start,
                          c->d_tile_scene, c->n_tiles, c->d_chunks_sorted, s));
   RC(launch_permute_i32(c->d_act_id, c->d_act_sorted, c->d_perm, (int)c->N, s));
+  if (c->has_mat)
+    RC(launch_permute_rows(c->mat_user, c->mat_sorted, c->d_perm, (int)c->N,
+                           (int)c->N, 3, 0, s));
   RC(launch_nonempty_flag(c->d_tile_cnt, c->n_tiles, c->d_tile_flag, s));
   RC(launch_scan_i32(c->d_tile_flag, c->d_tile_pos, c->n_tiles, s));
   RC(launch_compact(c->d_tile_flag, c->d_tile_pos, c->n_tiles, c->d_tile_list, s));
@@ -845,7 +858,8 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   // substep's P2G (state n+1 goes from registers to the scatter)
   // (not with a closed-loop controller: the actuation of substep n+1 needs
   // the component means of state n+1 first)
-  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on;
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on &&
+                    !c->has_mat;
   auto act_of = [&](int n) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };
@@ -885,6 +899,7 @@ int rollout_backward_core(mpm_ctx *c) {
   RC(launch_fill_f32(c->gp, c->dim * c->G, c->stream));
   const int64_t nga = (int64_t)t.T * c->n_act;
   if (nga > 0) RC(launch_fill_f64(c->gact, nga, c->stream));
+  if (c->has_mat) RC(launch_fill_f32(c->gmat, 3 * c->N, c->stream));
   if (c->ctl.on) {
     RC(launch_fill_f64(c->ctl.gW, (int64_t)c->n_act * c->ctl.nz, c->stream));
     RC(launch_fill_f64(c->ctl.gb, c->n_act, c->stream));
@@ -989,6 +1004,8 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   if (nga > 0) RC(ensure_gact(c, nga));
   RC(run_maybe_graph(c, c->gbwd, graph_key(c), [&] { return rollout_backward_core(c); }));
   t.rev_spine = 0;  // (outside the captured body: replays skip the body)
+  c->gmat_sorted = t.sorted;
+  c->gmat_valid = c->has_mat;
   const State A_out = state_at(c, t.adj + (t.T & 1) * sf);
   if (t.sorted) RC(permute_state(c, ms(A_out), st(*g0), 1));
   else RC(copy_state(c, ms(A_out), st(*g0)));
@@ -1049,6 +1066,9 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_act_sorted, c->stream);
   dfree(c->d_chunks_sorted, c->stream);
   dfree(c->d_part, c->stream);
+  dfree(c->mat_user, c->stream);
+  dfree(c->mat_sorted, c->stream);
+  dfree(c->gmat, c->stream);
   dfree(c->ctl.comp, c->stream);
   dfree(c->ctl.inv_cnt, c->stream);
   dfree(c->ctl.W, c->stream);
@@ -1167,6 +1187,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
     d.act_off = aoff;
     d.wall = S.wall;
     d.bc = S.bc;
+    d.nu = S.nu;
     d.fric = S.bc == 1 ? S.friction : 0.0f;
     d.tile_off = (int)toff;
     d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
@@ -1354,10 +1375,45 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
     RC(launch_fill_f64(c->gact, c->n_act, c->stream));
     gact = c->gact;
   }
+  if (c->has_mat) RC(launch_fill_f32(c->gmat, 3 * c->N, c->stream));
   RC(bwd_step(c, false, c->d_chunks_user, c->n_chunks_user, cs(*s_n),
               c->d_act_id, act_n, c->gm, c->gp, cs(*g_np1), st(*g_n), gact));
   if (gact) RC(launch_gact_store(gact, g_act_n, c->n_act, 1, c->stream));
+  c->gmat_sorted = 0;
+  c->gmat_valid = c->has_mat;
   return MPM_OK;
+}
+
+int mpm_set_materials(mpm_ctx *c, const float *E_p, const float *rho_p) {
+  RC(check_ctx(c));
+  c->gmat_valid = 0;
+  if (!E_p && !rho_p) {
+    c->has_mat = 0;
+    return MPM_OK;
+  }
+  if (c->N == 0) return MPM_OK;
+  hipStream_t s = c->stream;
+  if (!c->mat_user) {
+    RC(dmalloc(&c->mat_user, 3 * c->N, s));
+    RC(dmalloc(&c->mat_sorted, 3 * c->N, s));
+    RC(dmalloc(&c->gmat, 3 * c->N, s));
+  }
+  RC(launch_mat_field(c->d_scenes, c->d_pscene, (int)c->N, E_p, rho_p, c->mat_user, s));
+  // a tape already binned reads its materials in its own order
+  if (c->tape.valid && c->tape.sorted)
+    RC(launch_permute_rows(c->mat_user, c->mat_sorted, c->d_perm, (int)c->N,
+                           (int)c->N, 3, 0, s));
+  c->has_mat = 1;
+  return MPM_OK;
+}
+
+int mpm_material_grad(mpm_ctx *c, float *g_E, float *g_rho) {
+  RC(check_ctx(c));
+  if (!c->has_mat || !c->gmat_valid) return MPM_ERR_STATE;
+  if (c->N == 0) return MPM_OK;
+  return launch_mat_grad(c->d_scenes, c->d_pscene, (int)c->N,
+                         c->gmat_sorted ? c->d_perm : nullptr, c->gmat, g_E, g_rho,
+                         c->stream);
 }
 
 }  // extern "C"

@@ -32,7 +32,7 @@ struct DevScene {
   int nt;       // tiles per axis (binning)
   int bc;       // wall nodes: 0 sticky, 1 friction projection
   float fric;   // friction coefficient (bc = 1)
-  int pad_;
+  float nu;     // Poisson ratio (per-particle Lame parameters from E_p)
   float dt, dx, inv_dx, Dinv;  // Dinv = 4 / dx^2
   float mu, la, mp, V0;        // Lame parameters, particle mass and volume
   float kG;                    // -Dinv * dt * V0 (stress part of G_p)
@@ -95,6 +95,7 @@ struct P2GArgs {
   int64_t G;
   unsigned *err;
   TileInfo tiles;     // tile path only
+  const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
 };
 
 struct GridArgs {
@@ -180,6 +181,8 @@ struct AdjGatherArgs {
   int64_t G;
   double *gact;      // [n_act_tot] accumulated dL/ds
   unsigned *err;
+  const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
+  float *gmat = nullptr;       // += dL/dmu, dL/dla, dL/dm_p [3][ld] (with mat)
 };
 
 struct SortArgs {
@@ -222,6 +225,10 @@ int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st);
 int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st);
 int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st);
 
+int launch_mat_field(const DevScene *scenes, const int *pscene, int N,
+                     const float *E_p, const float *rho_p, float *mat, hipStream_t st);
+int launch_mat_grad(const DevScene *scenes, const int *pscene, int N, const int *perm,
+                    const float *gmat, float *g_E, float *g_rho, hipStream_t st);
 int launch_fill_f32(float *p, int64_t n, hipStream_t st);
 int launch_fill_f64(double *p, int64_t n, hipStream_t st);
 int launch_fill_i32(int *p, int64_t n, hipStream_t st);

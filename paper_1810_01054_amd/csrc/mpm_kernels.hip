@@ -269,10 +269,25 @@ struct Stress {
   float lnJ;
 };
 
+// Material of one particle: Lame parameters and mass (the scene's, or the
+// per-particle field [3][ld]: mu, la, m_p).
+struct Mat {
+  float mu, la, mp;
+};
+__device__ __forceinline__ Mat scene_mat(const DevScene &sc) {
+  return Mat{sc.mu, sc.la, sc.mp};
+}
+__device__ __forceinline__ Mat particle_mat(const float *mat, int ld,
+                                            const DevScene &sc, int p) {
+  if (mat) return Mat{mat[p], mat[ld + p], mat[2 * ld + p]};
+  return scene_mat(sc);
+}
+
 // Returns false (and sets eb) when det F <= 0 or is not finite.
 template <int D>
-__device__ __forceinline__ bool stress(const DevScene &sc, const float *F,
-                                       float s_act, bool has_act, Stress<D> &S,
+__device__ __forceinline__ bool stress(const DevScene &sc, const Mat &m,
+                                       const float *F, float s_act,
+                                       bool has_act, Stress<D> &S,
                                        unsigned &eb) {
   const float J = det<D>(F);
   if (!isfinite(J)) {
@@ -293,7 +308,7 @@ __device__ __forceinline__ bool stress(const DevScene &sc, const float *F,
     for (int b = 0; b < D; ++b) {
       const int k = a * D + b;
       // P = mu (F - F^-T) + la ln J F^-T;  P_t = P + F sigma
-      S.Pt[k] = sc.mu * (F[k] - S.FiT[k]) + sc.la * S.lnJ * S.FiT[k] +
+      S.Pt[k] = m.mu * (F[k] - S.FiT[k]) + m.la * S.lnJ * S.FiT[k] +
                 F[k] * S.sigma[b];
     }
   return true;
@@ -301,9 +316,9 @@ __device__ __forceinline__ bool stress(const DevScene &sc, const float *F,
 
 // G = kG P_t F^T + m_p C with kG = -(4/dx^2) dt V0.
 template <int D>
-__device__ __forceinline__ void affine_G(const DevScene &sc, const float *Pt,
-                                         const float *F, const float *C,
-                                         float *G) {
+__device__ __forceinline__ void affine_G(const DevScene &sc, const Mat &m,
+                                         const float *Pt, const float *F,
+                                         const float *C, float *G) {
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -311,7 +326,7 @@ __device__ __forceinline__ void affine_G(const DevScene &sc, const float *Pt,
       float s = 0.0f;
 #pragma unroll
       for (int g = 0; g < D; ++g) s += Pt[a * D + g] * F[b * D + g];
-      G[a * D + b] = sc.kG * s + sc.mp * C[a * D + b];
+      G[a * D + b] = sc.kG * s + m.mp * C[a * D + b];
     }
 }
 
@@ -379,21 +394,21 @@ __device__ __forceinline__ void scatter_stencil(const float (&w)[D][3],
 // affine form of m_p v_p + G_p (x_i - x_p) = c0 + sum_b Gdx[.][b] o_b.
 // Returns false (with eb set) for an invalid particle.
 template <int D>
-__device__ __forceinline__ bool p2g_record(const DevScene &sc, const float *F,
-                                           const float *C, const float *v,
-                                           float s_act, bool has_act,
-                                           const float *f, float (&w)[D][3],
-                                           float *c0, float (&Gdx)[D][D],
-                                           unsigned &eb) {
+__device__ __forceinline__ bool p2g_record(const DevScene &sc, const Mat &m,
+                                           const float *F, const float *C,
+                                           const float *v, float s_act,
+                                           bool has_act, const float *f,
+                                           float (&w)[D][3], float *c0,
+                                           float (&Gdx)[D][D], unsigned &eb) {
   float G[D * D];
   Stress<D> S;
-  if (!stress<D>(sc, F, s_act, has_act, S, eb)) return false;
-  affine_G<D>(sc, S.Pt, F, C, G);
+  if (!stress<D>(sc, m, F, s_act, has_act, S, eb)) return false;
+  affine_G<D>(sc, m, S.Pt, F, C, G);
 #pragma unroll
   for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    float s = sc.mp * v[a];
+    float s = m.mp * v[a];
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       Gdx[a][b] = G[a * D + b] * sc.dx;
@@ -417,7 +432,27 @@ __device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
   load_vec<D>(A.s.v, A.ld, p, v);
   const int j = A.act_id[p];
   const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
-  return p2g_record<D>(sc, F, C, v, s_act, j >= 0, f, w, c0, Gdx, eb);
+  return p2g_record<D>(sc, scene_mat(sc), F, C, v, s_act, j >= 0, f, w, c0, Gdx, eb);
+}
+
+// The same with the particle's own material (per-particle field when the
+// context has one); mpp: its mass, for the scatter's mass channel.
+template <int D>
+__device__ __forceinline__ bool p2g_particle_m(const P2GArgs &A,
+                                               const DevScene &sc, int p,
+                                               const float *xp, const float *f,
+                                               float (&w)[D][3], float *c0,
+                                               float (&Gdx)[D][D], float &mpp,
+                                               unsigned &eb) {
+  float F[D * D], C[D * D], v[D];
+  load_mat<D>(A.s.F, A.ld, p, F);
+  load_mat<D>(A.s.C, A.ld, p, C);
+  load_vec<D>(A.s.v, A.ld, p, v);
+  const int j = A.act_id[p];
+  const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
+  const Mat m = particle_mat(A.mat, A.ld, sc, p);
+  mpp = m.mp;
+  return p2g_record<D>(sc, m, F, C, v, s_act, j >= 0, f, w, c0, Gdx, eb);
 }
 
 // Per-particle adjoint-scatter quantities (supplement (A)-(C)):
@@ -501,8 +536,8 @@ __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
   const Box<D> box = chunk_box<D>(ok, base);
-  float w[D][3], c0[D], Gdx[D][D];
-  if (ok) ok = p2g_particle<D>(A, sc, p, xp, f, w, c0, Gdx, eb);
+  float w[D][3], c0[D], Gdx[D][D], mpp = 0.0f;
+  if (ok) ok = p2g_particle_m<D>(A, sc, p, xp, f, w, c0, Gdx, mpp, eb);
   if (box.lds) {
     for (int i = t; i < (D + 1) * LDS_NODES; i += CH) s_grid[i] = 0.0f;
     __syncthreads();
@@ -510,7 +545,7 @@ __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
   if (ok) {
     if (box.lds) {
       const int lbase = box_index<D>(box, base);
-      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+      scatter_stencil<D, true>(w, mpp, c0, Gdx,
                                [&](int o0, int o1, int o2, const float *val) {
         const int li = D == 2 ? lbase + o0 * box.e[1] + o1
                               : lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
@@ -519,7 +554,7 @@ __global__ __launch_bounds__(CH) void k_p2g(P2GArgs A) {
       });
     } else {
       const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+      scatter_stencil<D, true>(w, mpp, c0, Gdx,
                                [&](int o0, int o1, int o2, const float *val) {
         add_global<D, 1>(A.gm, A.gp, A.G,
                          stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
@@ -577,8 +612,8 @@ __global__ __launch_bounds__(256) void k_p2g_tile(P2GArgs A) {
     int base[D];
     load_vec<D>(A.s.x, A.ld, p, xp);
     if (!stencil_base<D>(xp, sc, base, f, eb)) continue;
-    float w[D][3], c0[D], Gdx[D][D];
-    if (!p2g_particle<D>(A, sc, p, xp, f, w, c0, Gdx, eb)) continue;
+    float w[D][3], c0[D], Gdx[D][D], mpp;
+    if (!p2g_particle_m<D>(A, sc, p, xp, f, w, c0, Gdx, mpp, eb)) continue;
     int l[D];
     bool inbox = true;
 #pragma unroll
@@ -588,7 +623,7 @@ __global__ __launch_bounds__(256) void k_p2g_tile(P2GArgs A) {
     }
     if (inbox) {
       const int lbase = D == 2 ? l[0] * S + l[1] : (l[0] * S + l[1]) * S + l[2];
-      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+      scatter_stencil<D, true>(w, mpp, c0, Gdx,
                                [&](int o0, int o1, int o2, const float *val) {
         const int li = D == 2 ? lbase + o0 * S + o1 : lbase + (o0 * S + o1) * S + o2;
 #pragma unroll
@@ -596,7 +631,7 @@ __global__ __launch_bounds__(256) void k_p2g_tile(P2GArgs A) {
       });
     } else {
       const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-      scatter_stencil<D, true>(w, sc.mp, c0, Gdx,
+      scatter_stencil<D, true>(w, mpp, c0, Gdx,
                                [&](int o0, int o1, int o2, const float *val) {
         add_global<D, 1>(A.gm, A.gp, A.G,
                          stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
@@ -1397,7 +1432,7 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
         if (!stencil_base<D>(xn, sc, base, f, eb)) return false;
         const int j = A.act_id[p];
         const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
-        return p2g_record<D>(sc, Fn, Cn, vn, s_act, j >= 0, f, w, c0, L, eb);
+        return p2g_record<D>(sc, scene_mat(sc), Fn, Cn, vn, s_act, j >= 0, f, w, c0, L, eb);
       });
 }
 
@@ -2047,7 +2082,9 @@ __device__ __forceinline__ AdjNode adj_node_global(const AdjGatherArgs &A,
 
 // Launched for three waves per SIMD (at most 168 VGPRs): with F and dL/dF
 // parked in LDS across the stencil loop the 3D kernel fits without spills.
-template <int D>
+// PM: the context has per-particle materials (mu, la, m_p per particle);
+// their gradients dL/dmu_p, dL/dla_p, dL/dm_p are added to A.gmat.
+template <int D, bool PM>
 __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   __shared__ AdjNode s_n[LDS_NODES];
   __shared__ double s_act[LDS_ACT];
@@ -2078,6 +2115,8 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     j_act = A.act_id[p];
     ok = stencil_base<D>(xp, sc, base, f, eb);
   }
+  Mat m = scene_mat(sc);
+  if (PM && active) m = particle_mat(A.mat, A.ld, sc, p);
   const Box<D> box = chunk_box<D>(ok, base);
   const bool act_lds = sc.n_act <= LDS_ACT && A.gact != nullptr;
   if (act_lds)
@@ -2099,9 +2138,9 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
     {
       Stress<D> S;
-      ok = stress<D>(sc, F, s_act, j_act >= 0, S, eb);
+      ok = stress<D>(sc, m, F, s_act, j_act >= 0, S, eb);
       float G[D * D];
-      affine_G<D>(sc, S.Pt, F, C, G);
+      affine_G<D>(sc, m, S.Pt, F, C, G);
       if constexpr (D == 3) {
 #pragma unroll
         for (int q = 0; q < D * D; ++q) {
@@ -2112,7 +2151,7 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         float s1 = gv1[a] + sc.dt * gx1[a];  // (A) vt
-        float s2 = sc.mp * v[a];
+        float s2 = m.mp * v[a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
           float ct = 0.0f;  // (B) Ct = gC1 + dt gF1 F^T
@@ -2140,10 +2179,12 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     const int lbase = box.lds ? box_index<D>(box, base) : 0;
     const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
 
+    float Nmb = 0.0f;  // PM: sum N dL/dm_i
     auto node = [&](const AdjNode &nd, float N, const float *gN, const float *o) {
       const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
       const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
-      float s_all = sc.mp * nd.a.w;  // (J) m-term
+      float s_all = m.mp * nd.a.w;  // (J) m-term
+      if constexpr (PM) Nmb += N * nd.a.w;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         float cv = cV[a], q = cq[a];
@@ -2237,14 +2278,28 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     }
     Stress<D> S;
     unsigned eb2 = 0;
-    stress<D>(sc, F, s_act, j_act >= 0, S, eb2);
+    stress<D>(sc, m, F, s_act, j_act >= 0, S, eb2);
     float vb[D], Cb[D * D], Ptb[D * D], Fb[D * D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) vb[a] = sc.mp * Spb[a];  // (F)
+    for (int a = 0; a < D; ++a) vb[a] = m.mp * Spb[a];  // (F)
 #pragma unroll
     for (int k = 0; k < D * D; ++k) {
-      Gb[k] *= sc.dx;         // dL/dG = sum N p_i (x_i - x_p)^T
-      Cb[k] = sc.mp * Gb[k];  // (I)
+      Gb[k] *= sc.dx;        // dL/dG = sum N p_i (x_i - x_p)^T
+      Cb[k] = m.mp * Gb[k];  // (I)
+    }
+    if constexpr (PM) {
+      // dL/dm_p = sum N [dL/dm_i + dL/dp_i . (v_p + C_p (x_i - x_p))]
+      if (A.gmat && ok) {
+        float vv[D], CC[D * D];
+        load_vec<D>(A.s.v, A.ld, p, vv);
+        load_mat<D>(A.s.C, A.ld, p, CC);
+        float mbp = Nmb;
+#pragma unroll
+        for (int a = 0; a < D; ++a) mbp += vv[a] * Spb[a];
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) mbp += CC[k] * Gb[k];
+        A.gmat[2 * (int64_t)A.ld + p] += mbp;
+      }
     }
     // x, v and C adjoints are final: store them now (frees their registers)
     if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D)))
@@ -2298,7 +2353,7 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
         for (int g = 0; g < D; ++g) s += S.FiT[a * D + g] * Ptb[b * D + g];
         T1[a * D + b] = s;
       }
-    const float cmu = sc.mu - sc.la * S.lnJ;
+    const float cmu = m.mu - m.la * S.lnJ;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -2306,8 +2361,18 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
         float s = 0.0f;
 #pragma unroll
         for (int g = 0; g < D; ++g) s += T1[a * D + g] * S.FiT[g * D + b];
-        Fb[a * D + b] += sc.mu * Ptb[a * D + b] + cmu * s + sc.la * inner * S.FiT[a * D + b];
+        Fb[a * D + b] += m.mu * Ptb[a * D + b] + cmu * s + m.la * inner * S.FiT[a * D + b];
       }
+    if constexpr (PM) {
+      // dL/dmu_p = <dL/dP, F - F^-T>, dL/dla_p = ln J <dL/dP, F^-T>
+      if (A.gmat && ok) {
+        float mub = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) mub += Ptb[k] * (F[k] - S.FiT[k]);
+        A.gmat[p] += mub;
+        A.gmat[(int64_t)A.ld + p] += S.lnJ * inner;
+      }
+    }
     // (K) dL/dsigma_aa = (F^T dL/dP_t)_aa;  s-bar = sum_a axis_a sigma-bar_aa
     if (j_act >= 0) {
 #pragma unroll
@@ -2808,8 +2873,50 @@ int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st) {
 }
 
 int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st) {
-  if (dim == 2) MPM_LAUNCH(k_adj_gather<2>, a.n_chunks, CH, st, a);
-  MPM_LAUNCH(k_adj_gather<3>, a.n_chunks, CH, st, a);
+  if (a.mat) {
+    if (dim == 2) MPM_LAUNCH((k_adj_gather<2, true>), a.n_chunks, CH, st, a);
+    MPM_LAUNCH((k_adj_gather<3, true>), a.n_chunks, CH, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_adj_gather<2, false>), a.n_chunks, CH, st, a);
+  MPM_LAUNCH((k_adj_gather<3, false>), a.n_chunks, CH, st, a);
+}
+
+// Per-particle material field [3][N] (mu, la, m_p) from E_p and rho_p
+// (nullable: the scene's E or rho), caller order.
+__global__ __launch_bounds__(256) void k_mat_field(const DevScene *scenes,
+                                                   const int *pscene, int N,
+                                                   const float *E_p,
+                                                   const float *rho_p, float *mat) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const DevScene sc = scenes[pscene[p]];
+  float mu = sc.mu, la = sc.la;
+  if (E_p) {
+    const float E = E_p[p];
+    mu = E / (2.0f * (1.0f + sc.nu));
+    la = E * sc.nu / ((1.0f + sc.nu) * (1.0f - 2.0f * sc.nu));
+  }
+  mat[p] = mu;
+  mat[N + p] = la;
+  mat[2 * N + p] = rho_p ? rho_p[p] * sc.V0 : sc.mp;
+}
+
+// dL/dE_p, dL/drho_p (caller order) from the accumulated dL/dmu, dL/dla,
+// dL/dm_p [3][N] of the reverse pass (tape order; perm: tape -> caller,
+// null when the tape is in caller order).
+__global__ __launch_bounds__(256) void k_mat_grad(const DevScene *scenes,
+                                                  const int *pscene, int N,
+                                                  const int *perm, const float *gmat,
+                                                  float *g_E, float *g_rho) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  const int p = perm ? perm[i] : i;
+  if (p < 0 || p >= N) return;
+  const DevScene sc = scenes[pscene[p]];
+  const float dmu = 1.0f / (2.0f * (1.0f + sc.nu));
+  const float dla = sc.nu / ((1.0f + sc.nu) * (1.0f - 2.0f * sc.nu));
+  if (g_E) g_E[p] = gmat[i] * dmu + gmat[N + i] * dla;
+  if (g_rho) g_rho[p] = gmat[2 * N + i] * sc.V0;
 }
 
 int launch_fill_f32(float *p, int64_t n, hipStream_t st) {
@@ -2918,4 +3025,15 @@ int launch_act_bank_bwd(int T, int n_act, int n_freq, float dt,
              freq, amp, phase, g_act, g_amp, g_phase);
 }
 
+}  // namespace mpm
+
+namespace mpm {
+int launch_mat_field(const DevScene *scenes, const int *pscene, int N,
+                     const float *E_p, const float *rho_p, float *mat, hipStream_t st) {
+  MPM_LAUNCH(k_mat_field, (N + 255) / 256, 256, st, scenes, pscene, N, E_p, rho_p, mat);
+}
+int launch_mat_grad(const DevScene *scenes, const int *pscene, int N, const int *perm,
+                    const float *gmat, float *g_E, float *g_rho, hipStream_t st) {
+  MPM_LAUNCH(k_mat_grad, (N + 255) / 256, 256, st, scenes, pscene, N, perm, gmat, g_E, g_rho);
+}
 }  // namespace mpm

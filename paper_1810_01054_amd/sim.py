@@ -218,6 +218,24 @@ class Simulator:
               "mpm_rollout_ctrl_backward")
         return g0, g_act, g_W, g_b
 
+    def set_materials(self, E_p: Optional[torch.Tensor] = None,
+                      rho_p: Optional[torch.Tensor] = None):
+        """Per-particle Young's modulus / density [N] (None: the scene's)."""
+        self._sync_stream()
+        for t, nm in ((E_p, "E_p"), (rho_p, "rho_p")):
+            if t is not None:
+                _check_tensor(t, (self.N,), nm)
+        self._mat = (E_p, rho_p)  # kept alive until the library has copied them
+        check(self.L.mpm_set_materials(self.ctx, _ptr(E_p), _ptr(rho_p)), "mpm_set_materials")
+
+    def material_grad(self):
+        """(dL/dE_p, dL/drho_p) [N] of the last reverse pass."""
+        self._sync_stream()
+        gE = torch.empty(self.N, device="cuda")
+        grho = torch.empty(self.N, device="cuda")
+        check(self.L.mpm_material_grad(self.ctx, _ptr(gE), _ptr(grho)), "mpm_material_grad")
+        return gE, grho
+
     def get_grid(self):
         self._sync_stream()
         m = torch.empty(self.G, device="cuda")
