@@ -298,6 +298,9 @@ def main():
     ap.add_argument("--friction", type=float, default=None,
                     help="c3/c3ctrl: walls with the friction projection and this "
                          "coefficient instead of sticky walls")
+    ap.add_argument("--materials", action="store_true",
+                    help="c3: a per-particle stiffness and density field (E, rho "
+                         "x U[0.5, 1.5) / U[0.7, 1.3)) with their gradients")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -312,7 +315,8 @@ def main():
     import torch
 
     from paper_1810_01054_amd import scenes as S
-    from paper_1810_01054_amd.autograd import act_bank, rollout, rollout_ctrl
+    from paper_1810_01054_amd.autograd import (act_bank, rollout, rollout_ctrl,
+                                               rollout_materials)
     from paper_1810_01054_amd.sim import Simulator
 
     if not torch.cuda.is_available():
@@ -349,7 +353,17 @@ def main():
         W_t, b_t = t(W).requires_grad_(True), t(b).requires_grad_(True)
         target_t = t(target)
 
+    if args.materials:
+        E_p, rho_p = S.material_field(sc, 1817)
+        E_t, rho_t = t(E_p).requires_grad_(True), t(rho_p).requires_grad_(True)
+
     def one_step():
+        if args.materials:
+            act = act_bank(T, sc.dt, freq, amp, phase)
+            xT, vT, CT, FT = rollout_materials(sim, (x0, v0, C0, F0), act, T, E_t, rho_t, k)
+            loss = xT[0].mean()
+            loss.backward()
+            return loss
         if ctrl:
             xT, vT, CT, FT, _ = rollout_ctrl(sim, (x0, v0, C0, F0), T, comp_t, n_comp, W_t,
                                              b_t, target_t, k)
@@ -450,6 +464,8 @@ def main():
                                + f", T={T} substeps fwd+bwd, checkpoint k={k} "
                                f"with recompute, torch.autograd.Function",
                    "controller": "closed loop" if ctrl else "open-loop sinusoid bank",
+                   "materials": ("per-particle E, rho field with gradients"
+                                 if args.materials else "one per scene"),
                    "walls": ("sticky" if args.friction is None
                              else f"friction projection, c = {args.friction}"),
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
@@ -463,7 +479,7 @@ def main():
         "kernel_roofline": kernel_roof,
         "cpu_baseline": None,
     }
-    if args.cpu_sample > 0 and not ctrl and args.friction is None:
+    if args.cpu_sample > 0 and not ctrl and args.friction is None and not args.materials:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     print(json.dumps(out), flush=True)
 

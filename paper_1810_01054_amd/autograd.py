@@ -4,7 +4,8 @@ gradient evaluation, here a library-owned tape with checkpoint + recompute).
 ``rollout(sim, state0, act, T, ckpt_k)`` returns the final state; its
 backward runs ``mpm_rollout_backward`` over the tape of that same rollout.
 ``rollout_ctrl`` is the closed-loop form (actuation from a tanh layer over
-the component means of the state, mpm_rollout_ctrl).
+the component means of the state, mpm_rollout_ctrl); ``rollout_materials``
+also differentiates a per-particle material field (mpm_set_materials).
 A context keeps one tape, so a second rollout on the same simulator makes
 the first one's backward raise instead of returning wrong gradients.
 """
@@ -65,6 +66,31 @@ class MPMRolloutCtrlFn(torch.autograd.Function):
         return (None, None, None, None, None, *g0, g_W, g_b, None)
 
 
+class MPMRolloutMatFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, x0, v0, C0, F0, act, E_p, rho_p):
+        sim.set_materials(E_p.contiguous(), rho_p.contiguous())
+        sT = sim.rollout(tuple(t.contiguous() for t in (x0, v0, C0, F0)),
+                         act.contiguous() if act is not None else None, T, ckpt_k)
+        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
+        ctx.sim, ctx.T, ctx.gen = sim, T, sim._tape_gen
+        ctx.has_act = act is not None
+        return sT
+
+    @staticmethod
+    def backward(ctx, gx, gv, gC, gF):
+        sim = ctx.sim
+        if getattr(sim, "_tape_gen", None) != ctx.gen:
+            raise RuntimeError("the simulator ran another rollout since this one; "
+                               "its tape is gone (use one Simulator per live graph)")
+        ref = sim.empty_state()
+        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
+                  for t, r in zip((gx, gv, gC, gF), ref))
+        g0, g_act = sim.rollout_backward(g, ctx.T)
+        g_E, g_rho = sim.material_grad()
+        return (None, None, None, *g0, g_act if ctx.has_act else None, g_E, g_rho)
+
+
 class ActBankFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, T: int, dt: float, freq, amp, phase):
@@ -95,6 +121,15 @@ def rollout_ctrl(sim: Simulator, state0, T: int, comp_id, n_comp: int, W, b, tar
     x0, v0, C0, F0 = state0
     return MPMRolloutCtrlFn.apply(sim, T, ckpt_k, comp_id, n_comp, x0, v0, C0, F0, W, b,
                                   target)
+
+
+def rollout_materials(sim: Simulator, state0, act: Optional[torch.Tensor], T: int,
+                      E_p, rho_p, ckpt_k: int = 32):
+    """Differentiable rollout over a per-particle material field (E_p,
+    rho_p [N]): returns (xT, vT, CT, FT) with gradients to the initial
+    state, the actuation, E_p and rho_p (system identification, co-design)."""
+    x0, v0, C0, F0 = state0
+    return MPMRolloutMatFn.apply(sim, T, ckpt_k, x0, v0, C0, F0, act, E_p, rho_p)
 
 
 def act_bank(T: int, dt: float, freq, amp, phase):

@@ -132,3 +132,28 @@ def test_uniform_field_equals_scene_materials_and_switching_off():
     with pytest.raises(MPMError):
         sim.material_grad()
     sim.close()
+
+
+def test_materials_autograd_wrapper():
+    # system identification: the gradient of a loss on the final state with
+    # respect to the stiffness and density fields, through torch.autograd
+    from paper_1810_01054_amd.autograd import rollout_materials
+    sc = S.perturb(S.tiny_3d(n=12, n_particles=30), 8, v_scale=0.3, C_scale=1.0, F_scale=0.05)
+    T = 12
+    E_p, rho_p = S.material_field(sc, 65)
+    acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    rng = np.random.default_rng(66)
+    gx = rng.normal(size=sc.x.shape).astype(np.float32)
+    os_, gE, grho = _ocase(sc, E_p, rho_p)
+    z = [np.zeros_like(a, dtype=np.float64) for a in sc.state]
+    oracle.rollout(os_, f64(sc.state), T, sc.act_id, acts.astype(np.float64),
+                   [gx.astype(np.float64)] + z[1:])
+    sim = sim_for(sc)
+    Et, rt = _cu(E_p).requires_grad_(True), _cu(rho_p).requires_grad_(True)
+    say("materials_autograd")
+    out = rollout_materials(sim, to_gpu(sc.state), _cu(acts), T, Et, rt, ckpt_k=4)
+    (out[0] * _cu(gx)).sum().backward()
+    sim.sync_errors()
+    assert rel_err(Et.grad.cpu().numpy(), gE) < GRAD_TOL
+    assert rel_err(rt.grad.cpu().numpy(), grho) < GRAD_TOL
+    sim.close()
