@@ -242,9 +242,9 @@ int mpm_rollout_ctrl_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
  * particle's Lame parameters follow from E_p and its scene's nu, its mass is
  * rho_p V0.  The values are copied; they apply to every later forward and
  * reverse call (set them before a rollout and keep them until its reverse
- * pass).  With a field, the binned P2G scatters with per-particle LDS
- * atomics (the mass rides with each particle) and 3D rollouts do not fuse
- * G2P with the next P2G. */
+ * pass).  With a field, the binned P2G's records carry each particle's
+ * mass, the adjoint gather reads each particle's material, and 3D rollouts
+ * do not fuse G2P with the next P2G. */
 int mpm_set_materials(mpm_ctx *ctx, const float *E_p, const float *rho_p);
 
 /* dL/dE_p and dL/drho_p (DEVICE float [N_tot], caller order, overwritten,

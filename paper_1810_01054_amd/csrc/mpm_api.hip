@@ -292,11 +292,11 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   a.G = c->G;
   a.err = c->d_err;
   a.tiles = tile_info(c);
-  // per-particle materials: the scatters that keep each particle's mass in
-  // registers (caller order: global atomics; binned: LDS atomics per tile)
+  // per-particle materials: the sorted scatter's records then carry each
+  // particle's mass (the per-cell mode falls back to per-tile LDS atomics)
   a.mat = c->has_mat ? (tiles ? c->mat_sorted : c->mat_user) : nullptr;
   ProfScope ps(c, MPM_K_P2G);
-  if (tiles && c->scatter_mode == 3 && !c->has_mat)
+  if (tiles && c->scatter_mode == 3)
     return launch_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
   a.tiles.list = nullptr;  // the other binned modes launch one block per tile
   if (tiles && c->scatter_mode == 2 && !c->has_mat)

@@ -814,11 +814,12 @@ struct SortedCell {
   static constexpr int NQ = (NO + WS - 1) / WS;  // offsets per wave (at most)
 };
 
-template <int D, int NCH, int PER, bool V4>
+// PM: records carry the particle's mass (per-particle materials).
+template <int D, int NCH, int PER, bool V4, bool PM = false>
 struct SortedCellSmem {
   static constexpr int SV = SortedCell<D>::SV;
   float box[V4 ? 4 * SV : NCH * SV];
-  float rec[SortedCell<D>::REC * PER * 256];  // field-major, swizzled slots
+  float rec[(SortedCell<D>::REC + (PM ? 1 : 0)) * PER * 256];  // field-major, swizzled slots
   int cnt[256];
   int off[256];
   short order[256];  // the tile's own cells, then the occupied ring cells
@@ -892,7 +893,7 @@ __device__ __forceinline__ int box_slot(int li) {
 
 // The n records of a cell (first slot o; NR slots per field), summed into
 // acc at offsets W, W+4, ...
-template <int D, int NCH, bool HAS_MASS, int W>
+template <int D, int NCH, bool HAS_MASS, int W, bool PM = false>
 __device__ __forceinline__ void cell_offsets_sum(const float *rec, int NR,
                                                  int o, int n, float mp,
                                                  float *acc) {
@@ -906,7 +907,8 @@ __device__ __forceinline__ void cell_offsets_sum(const float *rec, int NR,
 #pragma unroll
       for (int b = 0; b < D; ++b) L[a][b] = rec[(2 * D + a * D + b) * NR + ps];
     }
-    offsets_add<D, NCH, HAS_MASS, W>(w, mp, c0, L, acc);
+    const float mk = PM ? rec[SortedCell<D>::REC * NR + ps] : mp;
+    offsets_add<D, NCH, HAS_MASS, W>(w, mk, c0, L, acc);
   }
 }
 
@@ -940,14 +942,17 @@ __device__ __forceinline__ void offsets_flush(float *box, int lcell,
   }
 }
 
-template <int D, int NCH, bool HAS_MASS, int PER, bool V4, typename Args,
-          typename Part>
+// PM: the part callback also returns the particle's mass, which the
+// records carry (per-particle materials); otherwise the scene's mass.
+template <int D, int NCH, bool HAS_MASS, int PER, bool V4, bool PM = false,
+          typename Args, typename Part>
 __device__ __forceinline__ void sorted_cell_scatter(
-    const Args &A, int tile, SortedCellSmem<D, NCH, PER, V4> &sm, float *gm,
+    const Args &A, int tile, SortedCellSmem<D, NCH, PER, V4, PM> &sm, float *gm,
     float *gp, Part &&part) {
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
                 NIN = SC::NIN, REC = SC::REC, B = SC::B, NQ = SC::NQ;
+  constexpr int RECP = REC + (PM ? 1 : 0);
   constexpr int BOXF = V4 ? 4 * SV : NCH * SV;  // floats in the box
   constexpr int NR = PER * 256;                 // record slots per field
   static_assert(!V4 || NCH <= 4, "V4 holds at most four channels");
@@ -984,16 +989,21 @@ __device__ __forceinline__ void sorted_cell_scatter(
   for (int b0 = 0; b0 < cnt; b0 += PER * 256) {
     // 1. records, cells and ranks of up to PER particles per thread
     int lc[PER], rank[PER];
-    float rec[PER][REC];
+    float rec[PER][RECP];
 #pragma unroll
     for (int h = 0; h < PER; ++h) {
       lc[h] = -1;
       rank[h] = 0;
       const int j = b0 + h * 256 + t;
       const int p = start + j;
-      float f[D], w[D][3], c0[D], L[D][D];
+      float f[D], w[D][3], c0[D], L[D][D], mpp = sc.mp;
       int base[D];
-      if (!(j < cnt && part(p, base, f, w, c0, L, eb))) continue;
+      bool got = false;
+      if (j < cnt) {
+        if constexpr (PM) got = part(p, base, f, w, c0, L, mpp, eb);
+        else got = part(p, base, f, w, c0, L, eb);
+      }
+      if (!got) continue;
       int l[D];
       bool inbox = true;
 #pragma unroll
@@ -1010,10 +1020,11 @@ __device__ __forceinline__ void sorted_cell_scatter(
 #pragma unroll
           for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
         }
+        if constexpr (PM) rec[h][REC] = mpp;
         rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
       } else {
         const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+        scatter_stencil<D, HAS_MASS>(w, mpp, c0, L,
                                      [&](int o0, int o1, int o2, const float *val) {
           add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
                                           stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
@@ -1040,7 +1051,7 @@ __device__ __forceinline__ void sorted_cell_scatter(
       if (lc[h] < 0) continue;
       const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
 #pragma unroll
-      for (int k = 0; k < REC; ++k) sm.rec[k * NR + ps] = rec[h][k];
+      for (int k = 0; k < RECP; ++k) sm.rec[k * NR + ps] = rec[h][k];
     }
     __syncthreads();
     // 3. per-cell sums of this wave's offsets, then the waves' read-add-write
@@ -1055,10 +1066,10 @@ __device__ __forceinline__ void sorted_cell_scatter(
 #pragma unroll
       for (int k = 0; k < NQ * NCH; ++k) acc[k] = 0.0f;
       switch (wave) {
-        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0>(sm.rec, NR, o, n, sc.mp, acc); break;
-        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1>(sm.rec, NR, o, n, sc.mp, acc); break;
-        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2>(sm.rec, NR, o, n, sc.mp, acc); break;
-        default: cell_offsets_sum<D, NCH, HAS_MASS, 3>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
+        default: cell_offsets_sum<D, NCH, HAS_MASS, 3, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
       }
       int cc[D];
       {
@@ -1109,23 +1120,25 @@ __device__ __forceinline__ void sorted_cell_scatter(
 // keep two waves busy), and each wave adds its lanes' sums into its own LDS
 // box (read-add-write, the four chains run in parallel); the four boxes are
 // summed at the end.  On the 64-scene 2D batch this beats the offset split.
-template <int D, int NCH>
+template <int D, int NCH, bool PM = false>
 struct WaveBoxSmem {
   float box[4][NCH * SortedCell<D>::SV];
-  float rec[512 * SortedCell<D>::REC];
+  float rec[512 * (SortedCell<D>::REC + (PM ? 1 : 0))];
   int cnt[256];
   int off[256];
   int wsum[4];
 };
 
-template <int D, int NCH, bool HAS_MASS, typename Args, typename Part>
+template <int D, int NCH, bool HAS_MASS, bool PM = false, typename Args,
+          typename Part>
 __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
-                                                       WaveBoxSmem<D, NCH> &sm,
+                                                       WaveBoxSmem<D, NCH, PM> &sm,
                                                     float *gm, float *gp,
                                                     Part &&part) {
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
-                REC = SC::REC, B = SC::B;
+                B = SC::B;
+  constexpr int REC = SC::REC + (PM ? 1 : 0);  // record floats (PM: + mass)
   constexpr int NO = D == 2 ? 9 : 27;
   constexpr int PER = 2;  // particles prepared per thread and batch
   const int t = threadIdx.x, wave = t >> 6;
@@ -1162,11 +1175,14 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
       const int j = b0 + h * 256 + t;
       if (j >= cnt) continue;
       const int p = start + j;
-      float xp[D], f[D], w[D][3], c0[D], L[D][D];
+      float xp[D], f[D], w[D][3], c0[D], L[D][D], mpp = sc.mp;
       int base[D];
       load_vec<D>(A.s.x, A.ld, p, xp);
-      if (!(stencil_base<D>(xp, sc, base, f, eb) && part(p, xp, f, w, c0, L, eb)))
-        continue;
+      if (!stencil_base<D>(xp, sc, base, f, eb)) continue;
+      bool got;
+      if constexpr (PM) got = part(p, xp, f, w, c0, L, mpp, eb);
+      else got = part(p, xp, f, w, c0, L, eb);
+      if (!got) continue;
       int l[D];
       bool inbox = true;
 #pragma unroll
@@ -1183,10 +1199,11 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
 #pragma unroll
           for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
         }
+        if constexpr (PM) rec[h][REC - 1] = mpp;
         rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
       } else {
         const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+        scatter_stencil<D, HAS_MASS>(w, mpp, c0, L,
                                      [&](int o0, int o1, int o2, const float *val) {
           add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
                                           stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
@@ -1219,7 +1236,7 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
           for (int b = 0; b < D; ++b) L[a][b] = r[2 * D + a * D + b];
         }
         int oi = 0;
-        scatter_stencil<D, HAS_MASS>(w, sc.mp, c0, L,
+        scatter_stencil<D, HAS_MASS>(w, PM ? r[REC - 1] : sc.mp, c0, L,
                                      [&](int, int, int, const float *val) {
 #pragma unroll
           for (int c = 0; c < NCH; ++c) acc[oi * NCH + c] += val[c];
@@ -1285,6 +1302,35 @@ __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
           load_vec<D>(A.s.x, A.ld, p, xp);
           return stencil_base<D>(xp, sc, base, f, eb) &&
                  p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
+        });
+  }
+}
+
+// The same with per-particle materials: each record also carries the
+// particle's mass.
+template <int D>
+__global__ __launch_bounds__(256) void k_p2g_sorted_pm(P2GArgs A) {
+  const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
+  if (A.tiles.cnt[tile] == 0) return;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  if constexpr (D == 2) {
+    __shared__ WaveBoxSmem<D, D + 1, true> sm;
+    sorted_cell_scatter_wb<D, D + 1, true, true>(
+        A, tile, sm, A.gm, A.gp,
+        [&](int p, const float *xp, const float *f, float (&w)[D][3],
+            float *c0, float (&L)[D][D], float &mpp, unsigned &eb) {
+          return p2g_particle_m<D>(A, sc, p, xp, f, w, c0, L, mpp, eb);
+        });
+  } else {
+    __shared__ SortedCellSmem<D, D + 1, 2, true, true> sm;
+    sorted_cell_scatter<D, D + 1, true, 2, true, true>(
+        A, tile, sm, A.gm, A.gp,
+        [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+            float (&L)[D][D], float &mpp, unsigned &eb) {
+          float xp[D];
+          load_vec<D>(A.s.x, A.ld, p, xp);
+          return stencil_base<D>(xp, sc, base, f, eb) &&
+                 p2g_particle_m<D>(A, sc, p, xp, f, w, c0, L, mpp, eb);
         });
   }
 }
@@ -2823,6 +2869,10 @@ int launch_adj_scatter_tile(int dim, const AdjScatterArgs &a, int n_tiles,
 }
 
 int launch_p2g_sorted(int dim, const P2GArgs &a, int n_tiles, hipStream_t st) {
+  if (a.mat) {
+    if (dim == 2) MPM_LAUNCH(k_p2g_sorted_pm<2>, n_tiles, 256, st, a);
+    MPM_LAUNCH(k_p2g_sorted_pm<3>, n_tiles, 256, st, a);
+  }
   if (dim == 2) MPM_LAUNCH(k_p2g_sorted<2>, n_tiles, 256, st, a);
   MPM_LAUNCH(k_p2g_sorted<3>, n_tiles, 256, st, a);
 }

@@ -120,8 +120,8 @@ def test_uniform_field_equals_scene_materials_and_switching_off():
     sim.set_materials(_cu(np.full(N, sc.E)), _cu(np.full(N, sc.rho)))
     got = sim.rollout(to_gpu(sc.state), _cu(acts), T, ckpt_k=8, gT=to_gpu(gT))
     sim.sync_errors()
-    # the field scatters with per-particle LDS atomics, the scene path with the
-    # sorted scatter: FP32 summation order only
+    # the field path scatters masses from the records and runs no fused
+    # forward kernel: FP32 summation order only
     for a, r in zip(to_np(got[0]) + to_np(got[1]), to_np(ref[0]) + to_np(ref[1])):
         assert rel_err(a, r) < 1e-5
     sim.set_materials(None, None)
