@@ -361,6 +361,7 @@ int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
   a.G = c->G;
   a.err = c->d_err;
   a.tiles = tile_info(c);
+  a.mat = c->has_mat ? c->mat_sorted : nullptr;  // (binned rollouts only)
   ProfScope ps(c, MPM_K_G2P_P2G);
   return launch_g2p_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
 }
@@ -858,8 +859,7 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   // substep's P2G (state n+1 goes from registers to the scatter)
   // (not with a closed-loop controller: the actuation of substep n+1 needs
   // the component means of state n+1 first)
-  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on &&
-                    !c->has_mat;
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on;
   auto act_of = [&](int n) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };

@@ -139,6 +139,7 @@ struct G2P2GArgs {
   int64_t G;
   unsigned *err;
   TileInfo tiles;
+  const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
 };
 
 struct AdjScatterArgs {

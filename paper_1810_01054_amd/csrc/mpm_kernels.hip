@@ -1370,12 +1370,13 @@ __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
 // new state straight to the scatter's record step (section III, P2G), so
 // state n+1 is not read back from HBM.  Particles whose stencil left the box
 // gather from HBM.
-template <int D>
+// PM: per-particle materials (the records carry each particle's mass).
+template <int D, bool PM>
 __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
   static_assert(D == 3, "the fused pass is built for 3D tiles");
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, B = SC::B;
-  __shared__ SortedCellSmem<D, D + 1, 2, true> sm;
+  __shared__ SortedCellSmem<D, D + 1, 2, true, PM> sm;
   __shared__ float s_v[D * SV];
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
@@ -1391,10 +1392,8 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
     for (int a = 0; a < D; ++a) s_v[a * SV + i] = in ? A.gv[a * A.G + gi] : 0.0f;
   }
   // (the scatter synchronises before its record step reads s_v)
-  sorted_cell_scatter<D, D + 1, true, 2, true>(
-      A, tile, sm, A.gm, A.gp,
-      [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
-          float (&L)[D][D], unsigned &eb) {
+  auto part = [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+                  float (&L)[D][D], float &mpp, unsigned &eb) {
         float x[D], f0[D], F[D * D];
         int b0[D];
         load_vec<D>(A.s.x, A.ld, p, x);
@@ -1478,8 +1477,21 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
         if (!stencil_base<D>(xn, sc, base, f, eb)) return false;
         const int j = A.act_id[p];
         const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
-        return p2g_record<D>(sc, scene_mat(sc), Fn, Cn, vn, s_act, j >= 0, f, w, c0, L, eb);
-      });
+        const Mat m = PM ? particle_mat(A.mat, A.ld, sc, p) : scene_mat(sc);
+        mpp = m.mp;
+        return p2g_record<D>(sc, m, Fn, Cn, vn, s_act, j >= 0, f, w, c0, L, eb);
+      };
+  if constexpr (PM) {
+    sorted_cell_scatter<D, D + 1, true, 2, true, true>(A, tile, sm, A.gm, A.gp, part);
+  } else {
+    sorted_cell_scatter<D, D + 1, true, 2, true>(
+        A, tile, sm, A.gm, A.gp,
+        [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+            float (&L)[D][D], unsigned &eb) {
+          float mpp;
+          return part(p, base, f, w, c0, L, mpp, eb);
+        });
+  }
 }
 
 template <int D>
@@ -2904,7 +2916,8 @@ int launch_grid(int dim, const GridArgs &a, hipStream_t st) {
 
 int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_tiles, hipStream_t st) {
   if (dim != 3) return -1;  // the caller only fuses 3D passes
-  MPM_LAUNCH(k_g2p_p2g_sorted<3>, n_tiles, 256, st, a);
+  if (a.mat) MPM_LAUNCH((k_g2p_p2g_sorted<3, true>), n_tiles, 256, st, a);
+  MPM_LAUNCH((k_g2p_p2g_sorted<3, false>), n_tiles, 256, st, a);
 }
 
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st) {
