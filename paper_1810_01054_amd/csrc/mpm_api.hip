@@ -47,11 +47,12 @@ struct mpm_ctx {
   // captured inner loops of rollouts (forward, reverse)
   struct GraphKey {
     int T = 0, k = 0, memo = 0, grids_all = 0, sorted = 0, nch = 0, nne = 0, ctl = 0, rev = 0;
+    int mat = 0;  // a per-particle material field selects other kernels
     const void *p[8] = {};
     bool operator==(const GraphKey &o) const {
       if (T != o.T || k != o.k || memo != o.memo || grids_all != o.grids_all ||
           sorted != o.sorted || nch != o.nch || nne != o.nne || ctl != o.ctl ||
-          rev != o.rev)
+          rev != o.rev || mat != o.mat)
         return false;
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
@@ -661,6 +662,7 @@ mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
   k.p[7] = c->ctl.on ? c->ctl.Z : nullptr;
   k.ctl = c->ctl.on ? c->ctl.nz : 0;
   k.rev = t.rev ? 2 * t.rev + t.rev_spine : 0;
+  k.mat = c->has_mat;
   return k;
 }
 

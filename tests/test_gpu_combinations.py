@@ -144,3 +144,36 @@ def test_friction_materials_and_binomial_together():
     say("friction_materials_binomial")
     _check(sim, sc, T, -3, acts, gT, ref)
     sim.close()
+
+
+def test_graph_replay_follows_the_material_field():
+    # a rollout captured without a field must not be replayed once a field is
+    # set (other kernels, gradient accumulators), nor the reverse
+    sc = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=44)
+    T = 12
+    E_p, rho_p = S.material_field(sc, 90)
+    acts = oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+    gT = _seed(sc, 91)
+    graph = sim_for(sc, graphs=True)
+    eager = sim_for(sc, graphs=False)
+    say("graph_material_toggle")
+    outs = {}
+    for phase in ("plain", "field", "plain_again"):
+        for name, sim in (("graph", graph), ("eager", eager)):
+            if phase == "field":
+                sim.set_materials(_cu(E_p), _cu(rho_p))
+            elif phase == "plain_again":
+                sim.set_materials(None, None)
+            sT, g0, gact = sim.rollout(to_gpu(sc.state), _cu(acts), T, ckpt_k=4, gT=to_gpu(gT))
+            gm = sim.material_grad() if phase == "field" else None
+            sim.sync_errors()
+            outs[name] = (to_np(sT), to_np(g0), gm)
+        (sa, ga, ma), (sb, gb, mb) = outs["graph"], outs["eager"]
+        assert rel_err(sa[0], sb[0]) < 1e-6, phase
+        for c in range(4):
+            assert rel_err(ga[c], gb[c]) < 1e-5, (phase, c)
+        if ma is not None:
+            assert rel_err(ma[0].cpu().numpy(), mb[0].cpu().numpy()) < 1e-5
+            assert rel_err(ma[1].cpu().numpy(), mb[1].cpu().numpy()) < 1e-5
+    graph.close()
+    eager.close()
