@@ -240,9 +240,10 @@ int mpm_rollout_ctrl_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
  * scene).  E_p, rho_p: DEVICE float [N_tot] in caller order, each nullable
  * (NULL = the scene's E or rho); both NULL switches the field off.  The
  * particle's Lame parameters follow from E_p and its scene's nu, its mass is
- * rho_p V0.  The values are copied; they apply to every later forward and
- * reverse call (set them before a rollout and keep them until its reverse
- * pass).  With a field, the binned P2G's records carry each particle's
+ * rho_p V0.  The values are copied by a kernel queued on the context's
+ * stream (keep E_p, rho_p valid until the stream reaches it); they apply to
+ * every later forward and reverse call (set them before a rollout and keep
+ * them until its reverse pass).  With a field, the binned P2G's records carry each particle's
  * mass, the adjoint gather reads each particle's material, and 3D rollouts
  * do not fuse G2P with the next P2G. */
 int mpm_set_materials(mpm_ctx *ctx, const float *E_p, const float *rho_p);
