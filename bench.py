@@ -307,8 +307,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one MI355X only (one GPU per box); "
-              "multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py: measures the single-GPU path on one MI355X; runs on more "
+              "than one GPU are not supported (the scenes would shard as described "
+              "in the design notes)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
