@@ -113,3 +113,34 @@ def test_friction_scene_arguments_are_checked():
         from paper_1810_01054_amd.sim import Simulator
         with pytest.raises(MPMError):
             Simulator([p], act_id=sc.act_id)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_friction_on_the_high_faces_and_corners(dim):
+    # the contact scene mirrored through the box centre: pressed into the
+    # high faces (inward normal -e_a), into the corner of all of them in 3D
+    base = S.wall_contact(dim, n=24, n_particles=400, seed=29 + dim, friction=0.35)
+    sc = S.wall_contact(dim, n=24, n_particles=400, seed=29 + dim, friction=0.35)
+    sc.x = (np.float32(1.0) - base.x).astype(np.float32)
+    sc.v = (-base.v).astype(np.float32)
+    g = sc.n_grid
+    assert (np.floor(sc.x * g - 0.5) >= g - sc.wall - 2).any(axis=1).all()  # every axis' band
+    T = 20
+    rng = np.random.default_rng(35)
+    acts = rng.uniform(-1.5, 1.5, size=(T, sc.n_act)).astype(np.float32)
+    N, d = sc.n_particles, sc.dim
+    gT = [(rng.normal(size=(d, N)) / N).astype(np.float32),
+          (rng.normal(size=(d, N)) / N).astype(np.float32),
+          np.zeros((d * d, N), np.float32), np.zeros((d * d, N), np.float32)]
+    refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                         acts.astype(np.float64), f64(gT))
+    sim = sim_for(sc)
+    say("friction_high_faces", dim, N)
+    sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
+                               ckpt_k=5, gT=to_gpu(gT))
+    sim.sync_errors()
+    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
+        assert rel_err(a, r) < GRAD_TOL, (c, rel_err(a, r))
+    assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+    sim.close()
