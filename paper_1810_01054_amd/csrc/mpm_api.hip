@@ -132,7 +132,8 @@ struct mpm_ctx {
     int *comp = nullptr;       // component of each particle (tape order) [N]
     float *inv_cnt = nullptr;  // [CTL_MAX_COMP]
     float *W = nullptr, *b = nullptr, *target = nullptr;  // copies
-    float *partial = nullptr;  // [2 d n_comp][ctl_rows(N)]
+    float *partial = nullptr;  // [2 d n_comp][partial_rows] (entry-major)
+    int partial_rows = 0;
     double *sums = nullptr;    // [CTL_MAX_ZS]
     unsigned *done = nullptr;  // reduction counter (zero between launches)
     double *gW = nullptr, *gb = nullptr;  // FP64 accumulators
@@ -328,7 +329,8 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
 
 int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
             State out, const float *gv, const float *gm = nullptr,
-            const float *gp = nullptr, hipStream_t st = nullptr) {
+            const float *gp = nullptr, hipStream_t st = nullptr,
+            bool ctl_sums = false) {
   G2PArgs a;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
@@ -341,6 +343,13 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
   a.gp = gp;
   a.G = c->G;
   a.err = c->d_err;
+  if (ctl_sums) {  // the next substep's controller reads these rows
+    if (c->ctl.partial_rows < n_chunks) return MPM_ERR_ARG;
+    a.ctl_comp = c->ctl.comp;
+    a.ctl_partial = c->ctl.partial;
+    a.ctl_nzs = 2 * c->dim * c->ctl.n_comp;
+    a.ctl_rows = n_chunks;  // rows = chunks, entry stride n_chunks
+  }
   ProfScope ps(c, MPM_K_G2P);
   return launch_g2p(c->dim, a, st ? st : c->stream);
 }
@@ -713,7 +722,7 @@ int fwd_substep(mpm_ctx *c, int n, const State &in, const State &out) {
   return fwd_g2p(c, chunks, nch, cs(in), out, c->gv);
 }
 
-int ctl_forward(mpm_ctx *c, const State &s, int n);
+int ctl_forward(mpm_ctx *c, const State &s, int n, int g2p_rows = 0);
 int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g);
 
 // Binomial tapes: slot 0 = S^0, slots 1..rev = checkpoints, slot rev + 1 =
@@ -802,8 +811,10 @@ struct RevolveRun {
 };
 
 // Controller at substep n: component means of state n -> z^n (tape) ->
-// a^n = tanh(W z^n + b) into the tape's actuation row n.
-int ctl_forward(mpm_ctx *c, const State &s, int n) {
+// a^n = tanh(W z^n + b) into the tape's actuation row n.  g2p_rows > 0: the
+// G2P that produced state n already wrote that many rows of component sums
+// (only the reduction runs).
+int ctl_forward(mpm_ctx *c, const State &s, int n, int g2p_rows) {
   const auto &k = c->ctl;
   CtlArgs a;
   a.dim = c->dim;
@@ -824,6 +835,7 @@ int ctl_forward(mpm_ctx *c, const State &s, int n) {
   a.target = k.target;
   a.act = c->tape.act + (int64_t)n * c->n_act;
   a.z = k.Z + (int64_t)n * k.nz;
+  if (g2p_rows > 0) return launch_ctl_reduce(a, g2p_rows, c->stream) ? MPM_ERR_HIP : MPM_OK;
   return launch_ctl_forward(a, c->stream) ? MPM_ERR_HIP : MPM_OK;
 }
 
@@ -868,7 +880,9 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   for (int n = 0; n < L.T; ++n) {
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
-    if (c->ctl.on) RC(ctl_forward(c, s, n));
+    // the controller's component sums of state n come from the G2P that
+    // produced it (substep 0: their own kernel)
+    if (c->ctl.on) RC(ctl_forward(c, s, n, n > 0 ? nch : 0));
     if (!fuse || n == 0)
       RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp));
     if (c->tape.grids_all) {
@@ -880,7 +894,8 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
     if (fuse && n + 1 < L.T)
       RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1)));
     else
-      RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv));
+      RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv, nullptr, nullptr, nullptr,
+                 c->ctl.on && n + 1 < L.T));
   }
   return MPM_OK;
 }
@@ -1450,12 +1465,24 @@ int ctl_setup(mpm_ctx *c, const mpm_controller *u, int T) {
     RC(dmalloc(&k.W, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
     RC(dmalloc(&k.b, CTL_MAX_ACT, s));
     RC(dmalloc(&k.target, 3, s));
-    RC(dmalloc(&k.partial, (int64_t)ctl_rows((int)c->N) * CTL_MAX_ZS, s));
     RC(dmalloc(&k.sums, CTL_MAX_ZS, s));
     RC(dmalloc(&k.done, 1, s));
     RC(launch_fill_i32((int *)k.done, 1, s));
     RC(dmalloc(&k.gW, (int64_t)CTL_MAX_ACT * CTL_MAX_NZ, s));
     RC(dmalloc(&k.gb, CTL_MAX_ACT, s));
+  }
+  // rows of component sums: one per workgroup of the controller's own sum
+  // kernel, or one per G2P chunk (the G2P of each substep writes them)
+  {
+    int nch = 0;
+    (void)cur_chunks(c, &nch);
+    const int rows = std::max(ctl_rows(N), nch);
+    if (rows > k.partial_rows) {
+      dfree(k.partial, s);
+      k.partial_rows = 0;
+      RC(dmalloc(&k.partial, (int64_t)rows * CTL_MAX_ZS, s));
+      k.partial_rows = rows;
+    }
   }
   k.n_comp = u->n_comp;
   k.nz = d * (1 + 2 * u->n_comp);

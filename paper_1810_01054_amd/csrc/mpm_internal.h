@@ -122,6 +122,11 @@ struct G2PArgs {
   const float *gm, *gp;  // non-null: velocities from these m, p (not gv)
   int64_t G;
   unsigned *err;
+  // non-null: the controller's per-chunk component sums of the new state
+  // into ctl_partial (entry-major, ctl_rows >= n_chunks rows)
+  const int *ctl_comp = nullptr;
+  float *ctl_partial = nullptr;
+  int ctl_nzs = 0, ctl_rows = 0;
 };
 
 // G2P of substep n fused with the binned P2G of substep n+1 (3D rollouts):
@@ -263,7 +268,7 @@ struct CtlArgs {
   const float *inv_cnt;   // [n_comp] 1 / particles of the component
   const float *x, *v;     // state n ([d][ld])
   int ld;
-  float *partial;         // [nzs][ctl_rows(N)] per-workgroup sums
+  float *partial;         // [nzs][rows] per-workgroup sums (entry-major)
   double *sums;           // [nzs]
   unsigned *done;         // workgroups finished (zero between launches)
   const float *W, *b, *target;  // [n_act][nz], [n_act], [d]
@@ -271,6 +276,9 @@ struct CtlArgs {
   float *z;               // out: [nz] state vector of this substep (tape)
 };
 int launch_ctl_forward(const CtlArgs &a, hipStream_t st);
+// The reduction and controller evaluation alone, over n_rows partial rows
+// written by the previous G2P (launch_g2p with ctl_partial).
+int launch_ctl_reduce(const CtlArgs &a, int n_rows, hipStream_t st);
 // Rows of partial sums the forward reduction uses for N particles.
 int ctl_rows(int N);
 struct CtlAdjArgs {

@@ -1785,14 +1785,58 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
 // step 3: G2P gather + F/C/x update
 // ---------------------------------------------------------------------------
 
+// Closed-loop controller sums (section IV, Control): 2 d n_comp <= 96
+// entries (x_a of component c at 2 d c + a, v_a at 2 d c + d + a).
+constexpr int CTL_MAX_NZS = 96;
+
+// Adds this wave's particles to its LDS row of component sums: the lanes of
+// one component at a time are reduced with a reduce-scatter butterfly (the
+// 2d values padded to 8: 10 cross-lane steps), lane group v ending with the
+// total of value v.  c < 0: the lane contributes nothing.  Every lane of the
+// wave must call it.
 template <int D>
+__device__ __forceinline__ void ctl_wave_add(int c, const float *val8, float *row) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  const int vi = (h5 ? 4 : 0) + (h4 ? 2 : 0) + (h3 ? 1 : 0);
+  unsigned long long todo = __ballot(c >= 0);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    const int cc = __shfl(c, src, 64);
+    const bool mine = c == cc;
+    float q[4], u[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float lo = mine ? val8[k] : 0.0f, hi = mine ? val8[k + 4] : 0.0f;
+      q[k] = (h5 ? hi : lo) + __shfl_xor(h5 ? lo : hi, 32, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      u[k] = (h4 ? q[k + 2] : q[k]) + __shfl_xor(h4 ? q[k] : q[k + 2], 16, 64);
+    float w = (h3 ? u[1] : u[0]) + __shfl_xor(h3 ? u[0] : u[1], 8, 64);
+    w += __shfl_xor(w, 4, 64);
+    w += __shfl_xor(w, 2, 64);
+    w += __shfl_xor(w, 1, 64);
+    if ((lane & 7) == 0 && vi < 2 * D) row[2 * D * cc + vi] += w;
+    todo &= ~__ballot(mine);
+  }
+}
+
+// CTL: also the controller's per-workgroup component sums of the new state
+// (row = chunk of the partial array, entry-major), so the controller of the
+// next substep only reduces the rows.
+template <int D, bool CTL>
 __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
   __shared__ float s_v[D * LDS_NODES];
-  const Chunk ch = A.chunks[xcd_block_id()];
+  __shared__ float s_ctl[CTL ? 4 : 1][CTL ? CTL_MAX_NZS : 1];
+  const int chunk = xcd_block_id();
+  const Chunk ch = A.chunks[chunk];
   const DevScene sc = A.scenes[ch.scene];
   const int t = threadIdx.x;
   const bool active = t < ch.count;
   const int p = ch.start + t;
+  if constexpr (CTL)
+    for (int i = t & 63; i < CTL_MAX_NZS; i += 64) s_ctl[t >> 6][i] = 0.0f;
   unsigned eb = 0;
   float xp[D], f[D];
   int base[D];
@@ -1824,7 +1868,9 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
     }
     __syncthreads();
   }
-  if (!active) return;
+  float ctl_val[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // CTL: new x and v of this lane
+  bool ctl_have = false;
+  auto body = [&]() {
   if (!ok) {
     float F[D * D];
     load_mat<D>(A.s.F, A.ld, p, F);
@@ -1929,6 +1975,26 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
   store_mat<D>(A.out.C, A.ld, p, Cn);
   store_mat<D>(A.out.F, A.ld, p, Fn);
   if (eb) atomicOr(A.err, eb);
+  if constexpr (CTL) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      ctl_val[a] = xn[a];
+      ctl_val[D + a] = vn[a];
+    }
+    ctl_have = true;
+  }
+  };  // body
+  if constexpr (!CTL) {
+    if (active) body();
+  } else {
+    if (active) body();
+    const int c = ctl_have ? A.ctl_comp[p] : -1;
+    ctl_wave_add<D>(c, ctl_val, s_ctl[t >> 6]);
+    __syncthreads();
+    for (int i = t; i < A.ctl_nzs; i += CH)
+      A.ctl_partial[(int64_t)i * A.ctl_rows + chunk] =
+          (s_ctl[0][i] + s_ctl[1][i]) + (s_ctl[2][i] + s_ctl[3][i]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2627,7 +2693,6 @@ __global__ __launch_bounds__(256) void k_fill(T *p, int64_t n) {
 // closed-loop controller a = tanh(W z + b) (section IV, Control)
 // ---------------------------------------------------------------------------
 
-constexpr int CTL_MAX_NZS = 96;  // 2 d n_comp <= 96 (n_comp <= 16 in 3D)
 constexpr int CTL_WG = 1024;      // workgroups of the controller kernels at most
 
 // Sums of x and v over each component, one row of partial sums per
@@ -2643,42 +2708,18 @@ __global__ __launch_bounds__(256) void k_ctl_partial(CtlArgs A, int n_rows) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int nzs = 2 * D * A.n_comp;
   for (int i = lane; i < CTL_MAX_NZS; i += 64) s_w[wave][i] = 0.0f;
-  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
-  const int vi = (h5 ? 4 : 0) + (h4 ? 2 : 0) + (h3 ? 1 : 0);
   for (int p0 = blockIdx.x * 256; p0 < A.N; p0 += n_rows * 256) {
     const int p = p0 + t;
     const bool in = p < A.N;
     // loads independent of the component id: one memory round trip
     const int c = in ? A.comp[p] : -1;
-    float val[8];
+    float val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       val[a] = in ? A.x[a * A.ld + p] : 0.0f;
       val[D + a] = in ? A.v[a * A.ld + p] : 0.0f;
     }
-#pragma unroll
-    for (int k = 2 * D; k < 8; ++k) val[k] = 0.0f;
-    unsigned long long todo = __ballot(c >= 0);
-    while (todo) {
-      const int src = __ffsll((long long)todo) - 1;
-      const int cc = __shfl(c, src, 64);
-      const bool mine = c == cc;
-      float q[4], u[2];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float lo = mine ? val[k] : 0.0f, hi = mine ? val[k + 4] : 0.0f;
-        q[k] = (h5 ? hi : lo) + __shfl_xor(h5 ? lo : hi, 32, 64);
-      }
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-        u[k] = (h4 ? q[k + 2] : q[k]) + __shfl_xor(h4 ? q[k] : q[k + 2], 16, 64);
-      float w = (h3 ? u[1] : u[0]) + __shfl_xor(h3 ? u[0] : u[1], 8, 64);
-      w += __shfl_xor(w, 4, 64);
-      w += __shfl_xor(w, 2, 64);
-      w += __shfl_xor(w, 1, 64);
-      if ((lane & 7) == 0 && vi < 2 * D) s_w[wave][2 * D * cc + vi] += w;
-      todo &= ~__ballot(mine);
-    }
+    ctl_wave_add<D>(c, val, s_w[wave]);
   }
   __syncthreads();
   for (int i = t; i < nzs; i += 256)
@@ -2921,8 +2962,13 @@ int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_tiles, hipStream_t 
 }
 
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st) {
-  if (dim == 2) MPM_LAUNCH(k_g2p<2>, a.n_chunks, CH, st, a);
-  MPM_LAUNCH(k_g2p<3>, a.n_chunks, CH, st, a);
+  if (a.ctl_partial) {
+    if (a.ctl_nzs > CTL_MAX_NZS || a.ctl_rows < a.n_chunks) return -1;
+    if (dim == 2) MPM_LAUNCH((k_g2p<2, true>), a.n_chunks, CH, st, a);
+    MPM_LAUNCH((k_g2p<3, true>), a.n_chunks, CH, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_g2p<2, false>), a.n_chunks, CH, st, a);
+  MPM_LAUNCH((k_g2p<3, false>), a.n_chunks, CH, st, a);
 }
 
 int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st) {
@@ -3061,6 +3107,12 @@ int launch_ctl_forward(const CtlArgs &a, hipStream_t st) {
 }
 
 int ctl_rows(int N) { return std::min((N + 255) / 256, 2048); }
+
+int launch_ctl_reduce(const CtlArgs &a, int n_rows, hipStream_t st) {
+  const int nzs = 2 * a.dim * a.n_comp;
+  if (n_rows < 1 || nzs == 0 || nzs > CTL_MAX_NZS || a.n_act > 64) return -1;
+  MPM_LAUNCH(k_ctl_reduce, nzs, 256, st, a, n_rows);
+}
 
 int launch_ctl_adjoint(const CtlAdjArgs &a, hipStream_t st) {
   if (a.N < 1 || a.n_act > 64 || 2 * a.dim * a.n_comp > CTL_MAX_NZS) return -1;
