@@ -412,3 +412,23 @@ def material_field(scene: Scene, seed: int, E_spread: float = 0.5,
     E_p = scene.E * (1.0 + rng.uniform(-E_spread, E_spread, size=N))
     rho_p = scene.rho * (1.0 + rng.uniform(-rho_spread, rho_spread, size=N))
     return E_p.astype(F32), rho_p.astype(F32)
+
+
+def analytic_block(kind: str, seed: int = 61) -> Scene:
+    """The analytic accuracy cases of section IV (Table III), as a 3D block
+    of 5 x 4 x 5 cells (800 particles) on a 32^3 grid sliding along x at
+    0.5: "A1" in free flight (no gravity, lifted clear of the walls); "A2"
+    pressed into a friction-less floor (gravity, v_y = -0.3, friction
+    projection with c = 0).  In both, the centroid's x after T substeps
+    moves by exactly T dt per unit of a uniform initial x-velocity shift."""
+    sc = box_3d(32, (12, 4, 12), (17, 8, 17), seed=seed, name=f"analytic_{kind}")
+    sc.v[0, :] = 0.5
+    if kind == "A1":
+        sc.gravity = (0.0, 0.0, 0.0)
+        sc.x[1, :] += F32(6 / 32)
+    elif kind == "A2":
+        sc.bc, sc.friction = 1, 0.0
+        sc.v[1, :] = -0.3
+    else:
+        raise ValueError(kind)
+    return sc
