@@ -1535,14 +1535,21 @@ __global__ __launch_bounds__(256) void k_adj_scatter_cell(AdjScatterArgs A,
 }
 
 // Sum over the tile boxes covering scene-local node `li` (coordinates g) of
-// channels [c_lo, c_lo + NC) into acc.
+// channels [c_lo, c_lo + NC) into acc.  Tile t's box spans nodes
+// [t B - 1, t B + B + 2], so at most two tiles per axis cover a node (B >= 4):
+// the 2^D candidates are enumerated with fixed trip counts, all tile counts
+// are loaded at once and then all box entries (two dependent memory round
+// trips per node instead of two per covering tile); the adds keep the order
+// of the candidates (axis 0 slowest), the order of the nested tile loops.
 template <int D, int B, int NC>
 __device__ __forceinline__ bool add_tile_boxes(const DevScene &sc, int li,
                                                const int *tile_cnt,
                                                const float *part, int nch,
                                                int c_lo, float *acc) {
+  static_assert(B >= 4, "two tiles per axis cover a node only for B >= 4");
   constexpr int S = TileBox<B>::S;
   constexpr int SV = D == 2 ? S * S : S * S * S;
+  constexpr int K = 1 << D;
   int g[D], tlo[D], thi[D];
   int r = li;
 #pragma unroll
@@ -1552,36 +1559,48 @@ __device__ __forceinline__ bool add_tile_boxes(const DevScene &sc, int li,
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    // tile t's box spans nodes [t B - 1, t B + B + 2]
     thi[a] = min((g[a] + 1) / B, sc.nt - 1);
     tlo[a] = g[a] >= 3 ? (g[a] - 3) / B : 0;
   }
-  bool covered = false;
-  if constexpr (D == 2) {
-    for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-      for (int t1 = tlo[1]; t1 <= thi[1]; ++t1) {
-        const int tile = sc.tile_off + t0 * sc.nt + t1;
-        if (tile_cnt[tile] == 0) continue;
-        covered = true;
-        const int l = (g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1));
-        const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
+  int tile[K], loc[K], cnt[K];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += bx[c * SV];
-      }
-  } else {
-    for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-      for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
-        for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
-          const int tile = sc.tile_off + (t0 * sc.nt + t1) * sc.nt + t2;
-          if (tile_cnt[tile] == 0) continue;
-          covered = true;
-          const int l = ((g[0] - (t0 * B - 1)) * S + (g[1] - (t1 * B - 1))) * S +
-                        (g[2] - (t2 * B - 1));
-          const float *bx = part + ((int64_t)tile * nch + c_lo) * SV + l;
+  for (int k = 0; k < K; ++k) {
+    // a candidate past thi on some axis is clamped to a covering tile, so
+    // its count load is in bounds and none waits behind a branch; its count
+    // is then dropped
+    bool ok = true;
+    int t_lin = 0, l = 0;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[c] += bx[c * SV];
-        }
+    for (int a = 0; a < D; ++a) {
+      const int t = min(tlo[a] + ((k >> (D - 1 - a)) & 1), thi[a]);
+      ok = ok && tlo[a] + ((k >> (D - 1 - a)) & 1) <= thi[a];
+      t_lin = t_lin * sc.nt + t;
+      l = l * S + (g[a] - (t * B - 1));
+    }
+    tile[k] = sc.tile_off + t_lin;
+    loc[k] = l;
+    const int c = tile_cnt[tile[k]];
+    cnt[k] = ok ? c : 0;
   }
+  float val[K][NC];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // an empty candidate reads the first box's entries instead (one cached
+    // line for the whole wave, value dropped below): no branch, and no HBM
+    // traffic for boxes that no kernel wrote
+    const float *bx =
+        part + (cnt[k] != 0 ? ((int64_t)tile[k] * nch + c_lo) * SV + loc[k] : 0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[k][c] = bx[c * SV];
+  }
+  bool covered = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (cnt[k] != 0) {
+      covered = true;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += val[k][c];
+    }
   return covered;
 }
 
