@@ -164,6 +164,18 @@ def test_rollout_scatter_modes(scatter):
     _rollout_case(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=32), 30, ks=[0], scatter=scatter)
 
 
+@pytest.mark.parametrize("case", ["2d_tile16", "3d_tile8"])
+def test_rollout_wide_tiles(case):
+    # the autotuner's wide-tile candidates (16^2 cells in 2D, 8^3 in 3D): the
+    # per-particle LDS-atomic scatters into (tile + 4)^d boxes, and grid nodes
+    # summed over one or two boxes per axis, with ragged last tiles
+    if case == "2d_tile16":
+        _rollout_case(S.config_1b(), 50, ks=[0, 10], tile=16)
+    else:
+        _rollout_case(S.box_3d(32, (5, 3, 9), (21, 12, 18), seed=33), 30, ks=[0, 10],
+                      tile=8)
+
+
 @pytest.mark.parametrize("recompute_grids", [False, True])
 def test_rollout_then_step_then_backward(recompute_grids):
     # the tape survives step calls between a rollout and its reverse pass, for
