@@ -189,6 +189,15 @@ int mpm_rollout(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
 int64_t mpm_revolve_steps(int64_t L, int32_t slots);
 int64_t mpm_revolve_split(int64_t L, int32_t slots);
 
+/* Generation of the context's tape (HOST out): a counter bumped by every
+ * mpm_rollout and mpm_rollout_ctrl (each replaces the tape, also when it
+ * fails) and by mpm_set_materials (the reverse pass reads the material
+ * field).  A caller that defers a reverse pass (an autograd graph) records
+ * the value after its rollout and compares it before mpm_rollout_backward:
+ * a different value means that reverse pass would differentiate another
+ * rollout.  Errors: MPM_ERR_ARG (NULL argument). */
+int mpm_tape_generation(const mpm_ctx *ctx, uint64_t *gen);
+
 /* Reverse pass over the tape of the last mpm_rollout: chain rule across the
  * T substeps from dL/ds^T (`gT`) to dL/ds^0 (`g0`) and dL/ds [T][n_act_tot]
  * (`g_act`, overwritten, nullable).  MPM_ERR_STATE without a tape.  The tape

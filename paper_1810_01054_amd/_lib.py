@@ -55,7 +55,7 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_act_bank_backward", "mpm_sync_errors", "mpm_strerror",
            "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
            "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split",
-           "mpm_set_materials", "mpm_material_grad"]
+           "mpm_set_materials", "mpm_material_grad", "mpm_tape_generation"]
 
 KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
 
@@ -89,6 +89,7 @@ def lib():
     L.mpm_rollout_ctrl_backward.argtypes = [vp, sp, sp, vp, vp, vp]
     L.mpm_set_materials.argtypes = [vp, vp, vp]
     L.mpm_material_grad.argtypes = [vp, vp, vp]
+    L.mpm_tape_generation.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.mpm_revolve_steps.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.mpm_revolve_steps.restype = ctypes.c_int64
     L.mpm_revolve_split.argtypes = [ctypes.c_int64, ctypes.c_int32]

@@ -6,8 +6,16 @@ backward runs ``mpm_rollout_backward`` over the tape of that same rollout.
 ``rollout_ctrl`` is the closed-loop form (actuation from a tanh layer over
 the component means of the state, mpm_rollout_ctrl); ``rollout_materials``
 also differentiates a per-particle material field (mpm_set_materials).
-A context keeps one tape, so a second rollout on the same simulator makes
-the first one's backward raise instead of returning wrong gradients.
+A context keeps one tape, so a second rollout (or a set_materials call) on
+the same simulator makes the first one's backward raise instead of
+returning wrong gradients: each forward records the library's tape
+generation (mpm_tape_generation) and the backward compares it.
+
+Device-side errors (a particle left the grid, det F <= 0, a non-finite
+value) are sticky in the context and reported by the next synchronising
+call.  With ``check_errors=True`` the wrappers synchronise after the
+rollout and after its reverse pass and raise such an error at once (this
+costs the host/device overlap of one synchronisation per call).
 """
 from __future__ import annotations
 
@@ -18,77 +26,82 @@ import torch
 from .sim import Simulator, act_bank_backward, act_bank_forward
 
 
+def _record(ctx, sim: Simulator, T: int, check_errors: bool):
+    if check_errors:
+        sim.sync_errors()
+    ctx.sim, ctx.T, ctx.gen, ctx.check = sim, T, sim.tape_generation(), check_errors
+
+
+def _seed_adjoint(ctx, gx, gv, gC, gF):
+    sim = ctx.sim
+    if sim.tape_generation() != ctx.gen:
+        raise RuntimeError("the simulator ran another rollout (or changed its material "
+                           "field) since this one; its tape is gone (use one Simulator "
+                           "per live graph)")
+    ref = sim.empty_state()
+    return tuple(torch.zeros_like(r) if t is None else t.contiguous()
+                 for t, r in zip((gx, gv, gC, gF), ref))
+
+
 class MPMRolloutFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, x0, v0, C0, F0, act):
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, check_errors: bool,
+                x0, v0, C0, F0, act):
         sT = sim.rollout(tuple(t.contiguous() for t in (x0, v0, C0, F0)),
                          act.contiguous() if act is not None else None, T, ckpt_k)
-        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
-        ctx.sim, ctx.T, ctx.gen = sim, T, sim._tape_gen
+        _record(ctx, sim, T, check_errors)
         ctx.has_act = act is not None
         return sT
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
-        sim = ctx.sim
-        if getattr(sim, "_tape_gen", None) != ctx.gen:
-            raise RuntimeError("the simulator ran another rollout since this one; "
-                               "its tape is gone (use one Simulator per live graph)")
-        ref = sim.empty_state()
-        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
-                  for t, r in zip((gx, gv, gC, gF), ref))
-        g0, g_act = sim.rollout_backward(g, ctx.T)
-        return (None, None, None, *g0, g_act if ctx.has_act else None)
+        g = _seed_adjoint(ctx, gx, gv, gC, gF)
+        g0, g_act = ctx.sim.rollout_backward(g, ctx.T)
+        if ctx.check:
+            ctx.sim.sync_errors()
+        return (None, None, None, None, *g0, g_act if ctx.has_act else None)
 
 
 class MPMRolloutCtrlFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, comp_id, n_comp: int,
-                x0, v0, C0, F0, W, b, target):
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, check_errors: bool, comp_id,
+                n_comp: int, x0, v0, C0, F0, W, b, target):
         sT, act = sim.rollout_ctrl(tuple(t.contiguous() for t in (x0, v0, C0, F0)), T,
                                    comp_id, n_comp, W.contiguous(), b.contiguous(),
                                    target.contiguous(), ckpt_k)
-        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
-        ctx.sim, ctx.T, ctx.gen, ctx.nz = sim, T, sim._tape_gen, W.shape[1]
+        _record(ctx, sim, T, check_errors)
+        ctx.nz = W.shape[1]
         ctx.mark_non_differentiable(act)
         return (*sT, act)
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF, _gact):
-        sim = ctx.sim
-        if getattr(sim, "_tape_gen", None) != ctx.gen:
-            raise RuntimeError("the simulator ran another rollout since this one; "
-                               "its tape is gone (use one Simulator per live graph)")
-        ref = sim.empty_state()
-        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
-                  for t, r in zip((gx, gv, gC, gF), ref))
-        g0, _, g_W, g_b = sim.rollout_ctrl_backward(g, ctx.T, ctx.nz)
-        return (None, None, None, None, None, *g0, g_W, g_b, None)
+        g = _seed_adjoint(ctx, gx, gv, gC, gF)
+        g0, _, g_W, g_b = ctx.sim.rollout_ctrl_backward(g, ctx.T, ctx.nz)
+        if ctx.check:
+            ctx.sim.sync_errors()
+        return (None, None, None, None, None, None, *g0, g_W, g_b, None)
 
 
 class MPMRolloutMatFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, x0, v0, C0, F0, act, E_p, rho_p):
+    def forward(ctx, sim: Simulator, T: int, ckpt_k: int, check_errors: bool,
+                x0, v0, C0, F0, act, E_p, rho_p):
         sim.set_materials(E_p.contiguous(), rho_p.contiguous())
         sT = sim.rollout(tuple(t.contiguous() for t in (x0, v0, C0, F0)),
                          act.contiguous() if act is not None else None, T, ckpt_k)
-        sim._tape_gen = getattr(sim, "_tape_gen", 0) + 1
-        ctx.sim, ctx.T, ctx.gen = sim, T, sim._tape_gen
+        _record(ctx, sim, T, check_errors)
         ctx.has_act = act is not None
         return sT
 
     @staticmethod
     def backward(ctx, gx, gv, gC, gF):
-        sim = ctx.sim
-        if getattr(sim, "_tape_gen", None) != ctx.gen:
-            raise RuntimeError("the simulator ran another rollout since this one; "
-                               "its tape is gone (use one Simulator per live graph)")
-        ref = sim.empty_state()
-        g = tuple(torch.zeros_like(r) if t is None else t.contiguous()
-                  for t, r in zip((gx, gv, gC, gF), ref))
-        g0, g_act = sim.rollout_backward(g, ctx.T)
-        g_E, g_rho = sim.material_grad()
-        return (None, None, None, *g0, g_act if ctx.has_act else None, g_E, g_rho)
+        g = _seed_adjoint(ctx, gx, gv, gC, gF)
+        g0, g_act = ctx.sim.rollout_backward(g, ctx.T)
+        g_E, g_rho = ctx.sim.material_grad()
+        if ctx.check:
+            ctx.sim.sync_errors()
+        return (None, None, None, None, *g0, g_act if ctx.has_act else None, g_E, g_rho)
 
 
 class ActBankFn(torch.autograd.Function):
@@ -107,29 +120,30 @@ class ActBankFn(torch.autograd.Function):
 
 
 def rollout(sim: Simulator, state0, act: Optional[torch.Tensor], T: int,
-            ckpt_k: int = 32):
+            ckpt_k: int = 32, check_errors: bool = False):
     """Differentiable T-substep rollout: returns (xT, vT, CT, FT)."""
     x0, v0, C0, F0 = state0
-    return MPMRolloutFn.apply(sim, T, ckpt_k, x0, v0, C0, F0, act)
+    return MPMRolloutFn.apply(sim, T, ckpt_k, check_errors, x0, v0, C0, F0, act)
 
 
 def rollout_ctrl(sim: Simulator, state0, T: int, comp_id, n_comp: int, W, b, target,
-                 ckpt_k: int = 32):
+                 ckpt_k: int = 32, check_errors: bool = False):
     """Differentiable closed-loop rollout a^n = tanh(W z^n + b): returns
     (xT, vT, CT, FT, act) with gradients to the initial state, W and b
     (act, the controller's output, carries none)."""
     x0, v0, C0, F0 = state0
-    return MPMRolloutCtrlFn.apply(sim, T, ckpt_k, comp_id, n_comp, x0, v0, C0, F0, W, b,
-                                  target)
+    return MPMRolloutCtrlFn.apply(sim, T, ckpt_k, check_errors, comp_id, n_comp,
+                                  x0, v0, C0, F0, W, b, target)
 
 
 def rollout_materials(sim: Simulator, state0, act: Optional[torch.Tensor], T: int,
-                      E_p, rho_p, ckpt_k: int = 32):
+                      E_p, rho_p, ckpt_k: int = 32, check_errors: bool = False):
     """Differentiable rollout over a per-particle material field (E_p,
     rho_p [N]): returns (xT, vT, CT, FT) with gradients to the initial
     state, the actuation, E_p and rho_p (system identification, co-design)."""
     x0, v0, C0, F0 = state0
-    return MPMRolloutMatFn.apply(sim, T, ckpt_k, x0, v0, C0, F0, act, E_p, rho_p)
+    return MPMRolloutMatFn.apply(sim, T, ckpt_k, check_errors, x0, v0, C0, F0, act,
+                                 E_p, rho_p)
 
 
 def act_bank(T: int, dt: float, freq, amp, phase):

@@ -71,6 +71,9 @@ struct mpm_ctx {
   hipEvent_t ev_start = nullptr, ev_recomp = nullptr, ev_adj = nullptr;
   hipStream_t stream = nullptr;
   int poisoned = 0;
+  // bumped by every call that replaces the tape or the material field the
+  // reverse pass reads (mpm_tape_generation)
+  uint64_t tape_gen = 0;
 
   std::vector<DevScene> h_scenes;
   DevScene *d_scenes = nullptr;
@@ -1332,6 +1335,12 @@ int mpm_set_stream(mpm_ctx *c, void *stream) {
   return MPM_OK;
 }
 
+int mpm_tape_generation(const mpm_ctx *c, uint64_t *gen) {
+  if (!c || !gen) return MPM_ERR_ARG;
+  *gen = c->tape_gen;
+  return MPM_OK;
+}
+
 int mpm_info(const mpm_ctx *c, int64_t *n_particles, int32_t *n_act,
              int64_t *n_nodes) {
   if (!c) return MPM_ERR_ARG;
@@ -1403,6 +1412,7 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
 
 int mpm_set_materials(mpm_ctx *c, const float *E_p, const float *rho_p) {
   RC(check_ctx(c));
+  ++c->tape_gen;
   c->gmat_valid = 0;
   if (!E_p && !rho_p) {
     c->has_mat = 0;
@@ -1513,6 +1523,7 @@ int ctl_setup(mpm_ctx *c, const mpm_controller *u, int T) {
 int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
                 const float *act, const mpm_controller *ctl, mpm_state *sT) {
   auto &t = c->tape;
+  ++c->tape_gen;
   t.valid = 0;
   t.rev_spine = 0;
   c->ctl.on = 0;

@@ -262,6 +262,13 @@ class Simulator:
     def sync_errors(self):
         check(self.L.mpm_sync_errors(self.ctx), "device error")
 
+    def tape_generation(self) -> int:
+        """The context's tape generation (mpm_tape_generation): changes with
+        every rollout and every set_materials."""
+        g = ctypes.c_uint64()
+        check(self.L.mpm_tape_generation(self.ctx, ctypes.byref(g)), "mpm_tape_generation")
+        return g.value
+
 
 def act_bank_forward(T: int, dt: float, freq: torch.Tensor, amp: torch.Tensor,
                      phase: torch.Tensor, stream=None) -> torch.Tensor:

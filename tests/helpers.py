@@ -32,3 +32,36 @@ def rel_err(a, b) -> float:
     if nb == 0.0:
         return float(np.linalg.norm(a))
     return float(np.linalg.norm(a - b) / nb)
+
+
+def max_err(a, b, scale=None) -> float:
+    """Largest per-element error max_i |a_i - b_i| / scale.  The scale
+    defaults to the reference's largest magnitude max_i |b_i| (the field's own
+    size), so one wrong element shows at its own size instead of being
+    averaged over the array as in the normwise error; absolute error when the
+    reference is zero."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    if a.shape != b.shape:
+        raise ValueError(f"shape mismatch {a.shape} vs {b.shape}")
+    if a.size == 0:
+        return 0.0
+    if not np.isfinite(a).all():
+        return float("inf")
+    if scale is None:
+        scale = float(np.abs(b).max())
+    if scale == 0.0:
+        return float(np.abs(a - b).max())
+    return float(np.abs(a - b).max() / scale)
+
+
+def err(a, b) -> float:
+    """The larger of the normwise relative error and the per-element error
+    relative to the field's largest magnitude: a parity bound on err holds
+    for the array as a whole and for every element of it."""
+    return max(rel_err(a, b), max_err(a, b))
+
+
+def dx_err(x, ref, dx: float) -> float:
+    """Largest position error of any particle component in grid cells."""
+    return max_err(x, ref, scale=dx)

@@ -9,8 +9,8 @@ import torch
 
 import oracle
 from paper_1810_01054_amd import scenes as S
-from tests.helpers import oscene, f64, rel_err
-from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, concat_state
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, concat_state, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -49,15 +49,15 @@ def _check(sim, sc, T, k, acts, gT, ref, mat=True):
     refT, ref0, ref_act, gE, grho = ref
     sT, g0, gact = sim.rollout(to_gpu(sc.state), _cu(acts), T, ckpt_k=k, gT=to_gpu(gT))
     sim.sync_errors()
-    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
     for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
-        assert rel_err(a, r) < GRAD_TOL, (c, rel_err(a, r))
-    assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+        assert err(a, r) < GRAD_TOL, (c, err(a, r))
+    assert err(gact.cpu().numpy(), ref_act) < GRAD_TOL
     if mat:
         gEg, grhog = sim.material_grad()
         sim.sync_errors()
-        assert rel_err(gEg.cpu().numpy(), gE) < GRAD_TOL
-        assert rel_err(grhog.cpu().numpy(), grho) < GRAD_TOL
+        assert err(gEg.cpu().numpy(), gE) < GRAD_TOL
+        assert err(grhog.cpu().numpy(), grho) < GRAD_TOL
 
 
 @pytest.mark.parametrize("opts", [dict(scatter=1), dict(scatter=2), dict(sort=False)],
@@ -100,11 +100,11 @@ def test_materials_on_a_two_scene_batch():
     for i, sc in enumerate((a, b)):
         refT, ref0, ref_act, gE, grho = _oracle_mat(sc, mats[i][0], mats[i][1], T, acts[i], gTs[i])
         sl = slice(off, off + sc.n_particles)
-        assert rel_err(to_np(sT)[0][:, sl], refT[0]) < POS_TOL
+        check_state([a[:, sl] for a in to_np(sT)], refT, 1.0 / sc.n_grid, label=f"{sc.name}")
         for c in range(4):
-            assert rel_err(to_np(g0)[c][:, sl], ref0[c]) < GRAD_TOL
-        assert rel_err(gEg.cpu().numpy()[sl], gE) < GRAD_TOL
-        assert rel_err(grhog.cpu().numpy()[sl], grho) < GRAD_TOL
+            assert err(to_np(g0)[c][:, sl], ref0[c]) < GRAD_TOL
+        assert err(gEg.cpu().numpy()[sl], gE) < GRAD_TOL
+        assert err(grhog.cpu().numpy()[sl], grho) < GRAD_TOL
         off += sc.n_particles
     sim.close()
 
@@ -123,12 +123,12 @@ def test_controller_without_binning():
                                                  _cu(W), _cu(b), _cu(target), ckpt_k=4,
                                                  gT=to_gpu(gT))
     sim.sync_errors()
-    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
-    assert rel_err(act.cpu().numpy(), racts) < POS_TOL
+    check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
+    assert err(act.cpu().numpy(), racts) < POS_TOL
     for a, r in zip(to_np(g0), r0):
-        assert rel_err(a, r) < GRAD_TOL
-    assert rel_err(gW.cpu().numpy(), rW) < GRAD_TOL
-    assert rel_err(gb.cpu().numpy(), rb) < GRAD_TOL
+        assert err(a, r) < GRAD_TOL
+    assert err(gW.cpu().numpy(), rW) < GRAD_TOL
+    assert err(gb.cpu().numpy(), rb) < GRAD_TOL
     sim.close()
 
 
@@ -169,11 +169,11 @@ def test_graph_replay_follows_the_material_field():
             sim.sync_errors()
             outs[name] = (to_np(sT), to_np(g0), gm)
         (sa, ga, ma), (sb, gb, mb) = outs["graph"], outs["eager"]
-        assert rel_err(sa[0], sb[0]) < 1e-6, phase
+        assert err(sa[0], sb[0]) < 1e-6, phase
         for c in range(4):
-            assert rel_err(ga[c], gb[c]) < 1e-5, (phase, c)
+            assert err(ga[c], gb[c]) < 1e-5, (phase, c)
         if ma is not None:
-            assert rel_err(ma[0].cpu().numpy(), mb[0].cpu().numpy()) < 1e-5
-            assert rel_err(ma[1].cpu().numpy(), mb[1].cpu().numpy()) < 1e-5
+            assert err(ma[0].cpu().numpy(), mb[0].cpu().numpy()) < 1e-5
+            assert err(ma[1].cpu().numpy(), mb[1].cpu().numpy()) < 1e-5
     graph.close()
     eager.close()

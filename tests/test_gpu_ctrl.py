@@ -12,8 +12,8 @@ import torch
 import oracle
 from paper_1810_01054_amd import scenes as S
 from paper_1810_01054_amd._lib import MPMError
-from tests.helpers import oscene, f64, rel_err
-from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -72,13 +72,13 @@ def test_ctrl_rollout_matches_oracle(name, sc, n_comp):
         sT, act, g0, gact, gW, gb = _run(sim, sc, T, k, ctl, gT)
         sim.sync_errors()
         sT = to_np(sT)
-        assert rel_err(sT[0], refT[0]) < POS_TOL, (k, rel_err(sT[0], refT[0]))
-        assert rel_err(act.cpu().numpy(), racts) < POS_TOL
+        check_state(sT, refT, 1.0 / sc.n_grid, label=f"{sc.name} k={k}")
+        assert err(act.cpu().numpy(), racts) < POS_TOL
         g0 = to_np(g0)
         for c in range(4):
-            assert rel_err(g0[c], r0[c]) < GRAD_TOL, (k, c, rel_err(g0[c], r0[c]))
-        assert rel_err(gW.cpu().numpy(), rW) < GRAD_TOL, (k, rel_err(gW.cpu().numpy(), rW))
-        assert rel_err(gb.cpu().numpy(), rb) < GRAD_TOL, (k, rel_err(gb.cpu().numpy(), rb))
+            assert err(g0[c], r0[c]) < GRAD_TOL, (k, c, err(g0[c], r0[c]))
+        assert err(gW.cpu().numpy(), rW) < GRAD_TOL, (k, err(gW.cpu().numpy(), rW))
+        assert err(gb.cpu().numpy(), rb) < GRAD_TOL, (k, err(gb.cpu().numpy(), rb))
     sim.close()
 
 
@@ -95,19 +95,19 @@ def test_ctrl_zero_gain_equals_open_loop_rollout():
     sT, act, g0, gact, gW, gb = _run(sim, sc, T, 8, (comp, nc, W, b, target), gT)
     sim.sync_errors()
     sched = torch.tanh(_cuda(b)).repeat(T, 1).contiguous()
-    assert rel_err(act.cpu().numpy(), sched.cpu().numpy()) < 1e-6
+    assert err(act.cpu().numpy(), sched.cpu().numpy()) < 1e-6
     sT2, g02, gact2 = sim.rollout(to_gpu(sc.state), sched, T, ckpt_k=8, gT=to_gpu(gT))
     sim.sync_errors()
     # the open-loop run fuses G2P with the next P2G (3D), the closed-loop run
     # does not: the two differ by FP32 rounding only
     for a, r in zip(to_np(sT), to_np(sT2)):
-        assert rel_err(a, r) < 1e-6
+        assert err(a, r) < 1e-6
     # with W = 0 the controller adds nothing to the state adjoint
     for a, r in zip(to_np(g0), to_np(g02)):
-        assert rel_err(a, r) < 1e-5
-    assert rel_err(gact.cpu().numpy(), gact2.cpu().numpy()) < 1e-5
+        assert err(a, r) < 1e-5
+    assert err(gact.cpu().numpy(), gact2.cpu().numpy()) < 1e-5
     s = 1.0 - np.tanh(b.astype(np.float64)) ** 2
-    assert rel_err(gb.cpu().numpy(), gact2.cpu().numpy().sum(0) * s) < 1e-5
+    assert err(gb.cpu().numpy(), gact2.cpu().numpy().sum(0) * s) < 1e-5
     sim.close()
 
 
@@ -123,8 +123,8 @@ def test_ctrl_backward_reruns_and_autograd():
     g0b, gactb, gWb, gbb = sim.rollout_ctrl_backward(to_gpu(gT), T, W.shape[1])
     sim.sync_errors()
     for a, r in zip(to_np(g0b), to_np(g0)):
-        assert rel_err(a, r) < 1e-6
-    assert rel_err(gWb.cpu().numpy(), gW.cpu().numpy()) < 1e-6
+        assert err(a, r) < 1e-6
+    assert err(gWb.cpu().numpy(), gW.cpu().numpy()) < 1e-6
     # autograd: L = sum gT . S^T through the torch wrapper
     Wt = _cuda(W).requires_grad_(True)
     bt = _cuda(b).requires_grad_(True)
@@ -135,9 +135,9 @@ def test_ctrl_backward_reruns_and_autograd():
     loss = sum((g * s).sum() for g, s in zip(to_gpu(gT), out[:4]))
     loss.backward()
     sim.sync_errors()
-    assert rel_err(Wt.grad.cpu().numpy(), gW.cpu().numpy()) < 1e-6
-    assert rel_err(bt.grad.cpu().numpy(), gb.cpu().numpy()) < 1e-6
-    assert rel_err(x0[0].grad.cpu().numpy(), to_np(g0)[0]) < 1e-6
+    assert err(Wt.grad.cpu().numpy(), gW.cpu().numpy()) < 1e-6
+    assert err(bt.grad.cpu().numpy(), gb.cpu().numpy()) < 1e-6
+    assert err(x0[0].grad.cpu().numpy(), to_np(g0)[0]) < 1e-6
     # the open-loop tape has no controller
     sim.rollout(to_gpu(sc.state), act, T, ckpt_k=4)
     with pytest.raises(MPMError):
@@ -160,10 +160,10 @@ def test_ctrl_graph_replays_match_eager():
         out = _run(graph, sc, T, 8, ctl, gT)
         graph.sync_errors()
         torch.cuda.synchronize()
-        assert rel_err(to_np(out[0])[0], to_np(ref[0])[0]) < 1e-6
-        assert rel_err(out[1].cpu().numpy(), ref[1].cpu().numpy()) < 1e-6
-        assert rel_err(to_np(out[2])[0], to_np(ref[2])[0]) < 1e-5
-        assert rel_err(out[4].cpu().numpy(), ref[4].cpu().numpy()) < 1e-5
+        assert err(to_np(out[0])[0], to_np(ref[0])[0]) < 1e-6
+        assert err(out[1].cpu().numpy(), ref[1].cpu().numpy()) < 1e-6
+        assert err(to_np(out[2])[0], to_np(ref[2])[0]) < 1e-5
+        assert err(out[4].cpu().numpy(), ref[4].cpu().numpy()) < 1e-5
     eager.close()
     graph.close()
 

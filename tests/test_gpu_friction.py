@@ -11,8 +11,8 @@ import torch
 import oracle
 from paper_1810_01054_amd import scenes as S
 from paper_1810_01054_amd._lib import MPMError
-from tests.helpers import oscene, f64, rel_err
-from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -56,10 +56,10 @@ def test_friction_step_forward_and_backward(name, sc):
     sim.sync_errors()
     om, op = oracle.p2g(os_, f64(sc.state), sc.act_id, act)
     ov = oracle.grid_update(os_, om, op)
-    assert rel_err(v, ov) < STEP_TOL, rel_err(v, ov)
+    assert err(v, ov) < STEP_TOL, err(v, ov)
     ref = oracle.step_fwd(os_, f64(sc.state), sc.act_id, act)
     for a, r in zip(to_np(out), ref):
-        assert rel_err(a, r) < STEP_TOL
+        assert err(a, r) < STEP_TOL
     g1 = tuple(rng.normal(size=a.shape).astype(np.float32) for a in sc.state)
     g_act = torch.zeros(sc.n_act, device="cuda")
     g0 = sim.step_backward(to_gpu(sc.state), torch.tensor(act, device="cuda"), to_gpu(g1),
@@ -67,8 +67,8 @@ def test_friction_step_forward_and_backward(name, sc):
     sim.sync_errors()
     gref, aref = oracle.step_bwd(os_, f64(sc.state), f64(g1), sc.act_id, act)
     for c, (a, r) in enumerate(zip(to_np(g0), gref)):
-        assert rel_err(a, r) < STEP_ADJ_TOL, (c, rel_err(a, r))
-    assert rel_err(g_act.cpu().numpy(), aref) < STEP_ADJ_TOL
+        assert err(a, r) < STEP_ADJ_TOL, (c, err(a, r))
+    assert err(g_act.cpu().numpy(), aref) < STEP_ADJ_TOL
     sim.close()
 
 
@@ -97,10 +97,10 @@ def test_friction_rollout_matches_oracle(name, sc):
         sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
                                    ckpt_k=k, gT=to_gpu(gT))
         sim.sync_errors()
-        assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL, (k, rel_err(to_np(sT)[0], refT[0]))
+        check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
         for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
-            assert rel_err(a, r) < GRAD_TOL, (k, c, rel_err(a, r))
-        assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+            assert err(a, r) < GRAD_TOL, (k, c, err(a, r))
+        assert err(gact.cpu().numpy(), ref_act) < GRAD_TOL
     sim.close()
 
 
@@ -139,8 +139,8 @@ def test_friction_on_the_high_faces_and_corners(dim):
     sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
                                ckpt_k=5, gT=to_gpu(gT))
     sim.sync_errors()
-    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
     for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
-        assert rel_err(a, r) < GRAD_TOL, (c, rel_err(a, r))
-    assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+        assert err(a, r) < GRAD_TOL, (c, err(a, r))
+    assert err(gact.cpu().numpy(), ref_act) < GRAD_TOL
     sim.close()

@@ -11,8 +11,8 @@ import torch
 
 import oracle
 from paper_1810_01054_amd import scenes as S
-from tests.helpers import oscene, f64, rel_err
-from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, gpu_act_bank
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, to_np, sim_for, gpu_act_bank, check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -54,15 +54,15 @@ def test_revolve_rollout_matches_oracle(name, sc, T, slots):
         sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
                                    ckpt_k=-s, gT=to_gpu(gT))
         sim.sync_errors()
-        assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+        check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
         for c, (a, r) in enumerate(zip(to_np(g0), ref0)):
-            assert rel_err(a, r) < GRAD_TOL, (s, c, rel_err(a, r))
-        assert rel_err(gact.cpu().numpy(), ref_act) < GRAD_TOL
+            assert err(a, r) < GRAD_TOL, (s, c, err(a, r))
+        assert err(gact.cpu().numpy(), ref_act) < GRAD_TOL
         # the tape can be reversed again (its checkpoints are re-advanced)
         g0b, gactb = sim.rollout_backward(to_gpu(gT), T)
         sim.sync_errors()
         for a, b in zip(to_np(g0b), to_np(g0)):
-            assert rel_err(a, b) < 1e-5
+            assert err(a, b) < 1e-5
     sim.close()
 
 
@@ -78,9 +78,9 @@ def test_revolve_short_rollouts(T, s):
     sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
                                ckpt_k=-s, gT=to_gpu(gT))
     sim.sync_errors()
-    assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
+    check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
     for a, r in zip(to_np(g0), ref0):
-        assert rel_err(a, r) < GRAD_TOL
+        assert err(a, r) < GRAD_TOL
     sim.close()
 
 
@@ -98,9 +98,9 @@ def test_revolve_c2_300_steps_equals_memo():
         outs.append((to_np(sT), to_np(g0), gact.cpu().numpy()))
     (sa, ga, aa), (sb, gb, ab) = outs
     for c in range(4):
-        assert rel_err(sb[c], sa[c]) < 1e-5
-        assert rel_err(gb[c], ga[c]) < 1e-4, (c, rel_err(gb[c], ga[c]))
-    assert rel_err(ab, aa) < 1e-4
+        assert err(sb[c], sa[c]) < 1e-5
+        assert err(gb[c], ga[c]) < 1e-4, (c, err(gb[c], ga[c]))
+    assert err(ab, aa) < 1e-4
     sim.close()
 
 
@@ -121,10 +121,10 @@ def test_revolve_with_controller_and_graphs():
                 to_gpu(sc.state), T, cu(comp, torch.int32), nc, cu(W), cu(b), cu(target),
                 ckpt_k=-3, gT=to_gpu(gT))
             sim.sync_errors()
-            assert rel_err(to_np(sT)[0], refT[0]) < POS_TOL
-            assert rel_err(act.cpu().numpy(), racts) < POS_TOL
+            check_state(to_np(sT), refT, 1.0 / sc.n_grid, label=f"{sc.name}")
+            assert err(act.cpu().numpy(), racts) < POS_TOL
             for a, r in zip(to_np(g0), r0):
-                assert rel_err(a, r) < GRAD_TOL
-            assert rel_err(gW.cpu().numpy(), rW) < GRAD_TOL
-            assert rel_err(gb.cpu().numpy(), rb) < GRAD_TOL
+                assert err(a, r) < GRAD_TOL
+            assert err(gW.cpu().numpy(), rW) < GRAD_TOL
+            assert err(gb.cpu().numpy(), rb) < GRAD_TOL
         sim.close()

@@ -8,7 +8,7 @@ import torch
 from paper_1810_01054_amd import scenes as S
 from paper_1810_01054_amd.serve import Server, footprint_bytes, summarize
 from tests.gpu_helpers import require_gpu, say
-from tests.helpers import rel_err
+from tests.helpers import err
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,8 @@ def test_mix_equals_alone_and_poisoned_request_fails_alone():
         if i == 3:
             continue
         assert a.error is None and b.error is None, (i, a.error, b.error)
-        assert rel_err(a.xT.cpu().numpy(), b.xT.cpu().numpy()) < 1e-6
-        assert rel_err(a.g_v0.cpu().numpy(), b.g_v0.cpu().numpy()) < 1e-5
+        assert err(a.xT.cpu().numpy(), b.xT.cpu().numpy()) < 1e-6
+        assert err(a.g_v0.cpu().numpy(), b.g_v0.cpu().numpy()) < 1e-5
         # the centroid loss barely depends on actuation over a few dozen
         # substeps (|dL/ds| ~ 1e-16, rounding level): compare absolutely
         assert np.allclose(a.g_act.cpu().numpy(), b.g_act.cpu().numpy(),
