@@ -62,9 +62,12 @@ def seeds(shape_state, seed):
 # (v_i = p_i / m_i with cancellation in p_i), and C' = (4/dx^2) sum N v_i
 # (x_i - x_p) differences node velocities across a cell: each substep's
 # rounding of v and C is ~1e-6 and ~1e-5 of their size, and it is not
-# damped from one substep to the next; F' = (I + dt C') F moves by dt C' per
-# substep, so F keeps near-unit-roundoff accuracy.
-STATE_TOL = {"x": 1e-5, "v": 1e-4, "C": 1e-3, "F": 1e-5}
+# damped from one substep to the next; F' = (I + dt C') F carries dt times
+# C's error into F every substep: over T dt = 0.01 (100 substeps) with |C|
+# up to tens per second in contact and C within 1e-3 of its largest
+# magnitude per element, F's per-element error can reach
+# 0.01 * 1e-3 * 10 = 1e-4 of |F| (normwise it stays near 1e-6).
+STATE_TOL = {"x": 1e-5, "v": 1e-4, "C": 1e-3, "F": 1e-4}
 X_DX_TOL = 1e-3
 
 

@@ -173,7 +173,11 @@ def test_graph_replay_follows_the_material_field():
         for c in range(4):
             assert err(ga[c], gb[c]) < 1e-5, (phase, c)
         if ma is not None:
-            assert err(ma[0].cpu().numpy(), mb[0].cpu().numpy()) < 1e-5
-            assert err(ma[1].cpu().numpy(), mb[1].cpu().numpy()) < 1e-5
+            # dL/dE_p, dL/drho_p are sums over substeps with cancellation, and
+            # the two runs add the scatter's records in different orders (the
+            # rank in a cell comes from an LDS atomic): per element they agree
+            # to the FP32 adjoint bound of a single substep against the oracle
+            assert err(ma[0].cpu().numpy(), mb[0].cpu().numpy()) < 1e-4
+            assert err(ma[1].cpu().numpy(), mb[1].cpu().numpy()) < 1e-4
     graph.close()
     eager.close()
