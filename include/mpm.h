@@ -144,6 +144,35 @@ int mpm_info(const mpm_ctx *ctx, int64_t *n_particles, int32_t *n_act,
 int mpm_step_forward(mpm_ctx *ctx, const mpm_state *s_n, const float *act_n,
                      mpm_state *s_np1);
 
+/* Allocation-free mpm_step_forward, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  One scene, one substep (the same P2G, grid operations
+ * and G2P kernels as mpm_step_forward), no context: nothing is allocated,
+ * freed or synchronised.  The grid, the scene's descriptors and a checked
+ * copy of the actuator ids live in one static device region per GPU (about
+ * 11 MB, held until the process ends) whose limits are
+ * MPM_NOALLOC_MAX_PARTICLES particles and MPM_NOALLOC_MAX_NODES grid nodes;
+ * larger scenes are rejected with MPM_ERR_ARG before any launch.
+ *   scene   HOST descriptor, checked as by mpm_init (dim 2 or 3).
+ *   act_id  DEVICE int32 [N] (nullable = all passive): each particle's
+ *           actuator in [-1, n_act); an id outside that range is taken as
+ *           passive and sets bit 8 of *err.
+ *   s_n, s_np1, act_n  as for mpm_step_forward (DEVICE, ld = N; s_np1 may
+ *           equal s_n; act_n nullable only when n_act = 0).
+ *   err     DEVICE uint32, caller-owned: the kernels OR in 1 (a stencil base
+ *           left the grid), 2 (det F <= 0), 4 (non-finite result), 8 (bad
+ *           actuator id); the caller clears it and reads it after the stream.
+ *   stream  hipStream_t on which the work is queued (asynchronous).
+ * Every call on one GPU shares that GPU's region, which keeps the last
+ * call's grid (the next call clears what must start at zero): calls that
+ * overlap on one GPU (other streams, other host threads) race; calls queued
+ * on one stream are ordered.  Returns MPM_ERR_ARG or MPM_ERR_HIP. */
+#define MPM_NOALLOC_MAX_PARTICLES (1 << 20)
+#define MPM_NOALLOC_MAX_NODES (1 << 18)
+int mpm_step_forward_noalloc(const mpm_scene *scene, const int32_t *act_id,
+                             const mpm_state *s_n, const float *act_n,
+                             mpm_state *s_np1, uint32_t *err, void *stream);
+
 /* Reverse of one substep (supplement (A)-(K)): given state n (`s_n`), its
  * actuation and the adjoint of state n+1 (`g_np1`), writes the adjoint of
  * state n to `g_n` (may equal `g_np1`) and ADDS dL/ds_j^n to `g_act_n`

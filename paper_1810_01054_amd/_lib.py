@@ -55,7 +55,8 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_act_bank_backward", "mpm_sync_errors", "mpm_strerror",
            "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
            "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split",
-           "mpm_set_materials", "mpm_material_grad", "mpm_tape_generation"]
+           "mpm_set_materials", "mpm_material_grad", "mpm_tape_generation",
+           "mpm_step_forward_noalloc"]
 
 KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
 
@@ -82,6 +83,7 @@ def lib():
     L.mpm_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int32), i64p]
     L.mpm_step_forward.argtypes = [vp, sp, vp, sp]
     L.mpm_step_backward.argtypes = [vp, sp, vp, sp, sp, vp]
+    L.mpm_step_forward_noalloc.argtypes = [ctypes.POINTER(Scene), vp, sp, vp, sp, vp, vp]
     L.mpm_rollout.argtypes = [vp, i32, i32, sp, vp, sp, sp, sp, vp]
     L.mpm_rollout_backward.argtypes = [vp, sp, sp, vp]
     L.mpm_rollout_ctrl.argtypes = [vp, i32, i32, sp, ctypes.POINTER(Controller), sp, vp,

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mpm.h"
@@ -162,6 +163,47 @@ struct mpm_ctx {
 namespace {
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_ERR_HIP; }
+
+// Host-side checks of one scene descriptor (mpm_init and the
+// allocation-free step).
+bool scene_valid(const mpm_scene &S, int dim) {
+  if (S.dim != dim || S.n_grid < 3 || S.n_particles < 0 || S.n_act < 0 ||
+      S.n_act > MPM_MAX_ACT || S.wall < 0 || (S.bc != 0 && S.bc != 1))
+    return false;
+  if (S.bc == 1 && !(S.friction >= 0.0f && std::isfinite(S.friction))) return false;
+  if (!(S.dt > 0.0f) || !(S.V0 > 0.0f) || !(S.rho > 0.0f) || !(S.E >= 0.0f) ||
+      !(S.nu > -1.0f && S.nu < 0.5f) || !std::isfinite(S.dt) || !std::isfinite(S.E))
+    return false;
+  return true;
+}
+
+// The kernels' copy of a scene: derived constants (dx = 1/n, D = 4/dx^2,
+// Lame parameters, m_p = rho V0, the stress factor of G_p); offsets zero.
+DevScene dev_scene(const mpm_scene &S, int tile) {
+  DevScene d{};
+  d.n = S.n_grid;
+  d.np = S.n_particles;
+  d.n_act = S.n_act;
+  d.wall = S.wall;
+  d.bc = S.bc;
+  d.nu = S.nu;
+  d.fric = S.bc == 1 ? S.friction : 0.0f;
+  d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
+  d.dt = S.dt;
+  d.dx = 1.0f / (float)S.n_grid;
+  d.inv_dx = (float)S.n_grid;
+  d.Dinv = 4.0f * (float)S.n_grid * (float)S.n_grid;
+  d.mu = S.E / (2.0f * (1.0f + S.nu));
+  d.la = S.E * S.nu / ((1.0f + S.nu) * (1.0f - 2.0f * S.nu));
+  d.mp = S.rho * S.V0;
+  d.V0 = S.V0;
+  d.kG = -d.Dinv * S.dt * S.V0;
+  for (int a = 0; a < 3; ++a) {
+    d.g[a] = S.gravity[a];
+    d.axis[a] = S.act_axis[a];
+  }
+  return d;
+}
 
 template <typename T>
 int dmalloc(T **p, int64_t count, hipStream_t st) {
@@ -1148,15 +1190,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int n_act = 0;
   for (int s = 0; s < n_scenes; ++s) {
     const mpm_scene &S = scenes[s];
-    if (S.dim != dim || S.n_grid < 3 || S.n_particles < 0 || S.n_act < 0 ||
-        S.n_act > MPM_MAX_ACT || S.wall < 0 || (S.bc != 0 && S.bc != 1))
-      return MPM_ERR_ARG;
-    if (S.bc == 1 && !(S.friction >= 0.0f && std::isfinite(S.friction)))
-      return MPM_ERR_ARG;
-    if (!(S.dt > 0.0f) || !(S.V0 > 0.0f) || !(S.rho > 0.0f) || !(S.E >= 0.0f) ||
-        !(S.nu > -1.0f && S.nu < 0.5f) || !std::isfinite(S.dt) ||
-        !std::isfinite(S.E))
-      return MPM_ERR_ARG;
+    if (!scene_valid(S, dim)) return MPM_ERR_ARG;
     const int64_t nn = dim == 2 ? (int64_t)S.n_grid * S.n_grid
                                 : (int64_t)S.n_grid * S.n_grid * S.n_grid;
     const int64_t nt1 = (S.n_grid - 2 + tile - 1) / tile;
@@ -1198,32 +1232,11 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int aoff = 0;
   for (int s = 0; s < n_scenes; ++s) {
     const mpm_scene &S = scenes[s];
-    DevScene d{};
-    d.n = S.n_grid;
-    d.np = S.n_particles;
+    DevScene d = dev_scene(S, tile);
     d.p_off = (int)poff;
     d.g_off = (int)goff;
-    d.n_act = S.n_act;
     d.act_off = aoff;
-    d.wall = S.wall;
-    d.bc = S.bc;
-    d.nu = S.nu;
-    d.fric = S.bc == 1 ? S.friction : 0.0f;
     d.tile_off = (int)toff;
-    d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
-    d.dt = S.dt;
-    d.dx = 1.0f / (float)S.n_grid;
-    d.inv_dx = (float)S.n_grid;
-    d.Dinv = 4.0f * (float)S.n_grid * (float)S.n_grid;
-    d.mu = S.E / (2.0f * (1.0f + S.nu));
-    d.la = S.E * S.nu / ((1.0f + S.nu) * (1.0f - 2.0f * S.nu));
-    d.mp = S.rho * S.V0;
-    d.V0 = S.V0;
-    d.kG = -d.Dinv * S.dt * S.V0;
-    for (int a = 0; a < 3; ++a) {
-      d.g[a] = S.gravity[a];
-      d.axis[a] = S.act_axis[a];
-    }
     c->h_scenes.push_back(d);
     for (int64_t k = 0; k < S.n_particles; k += CH) {
       Chunk ch{s, (int)(poff + k), (int)std::min<int64_t>(CH, S.n_particles - k), 0};
@@ -1368,6 +1381,134 @@ int mpm_step_forward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
   RC(fwd_grid(c, false, c->gm, c->gp, c->gv, 0));
   RC(fwd_g2p(c, c->d_chunks_user, c->n_chunks_user, cs(*s_n), st(*s_np1),
              c->gv));
+  return MPM_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free single substep -----------------------------------------
+// Device memory of mpm_step_forward_noalloc: one static region per GPU (each
+// device holds its own copy, at its own address, until the process ends).
+// Layout: scene descriptor, chunks, node blocks, sanitised actuator ids, grid
+// m, p, v of at most MPM_NOALLOC_MAX_NODES nodes.
+namespace {
+constexpr int64_t NA_SCENE = 0;
+constexpr int64_t NA_CHUNKS = 256;
+constexpr int64_t NA_BLOCKS = NA_CHUNKS + sizeof(Chunk) * (MPM_NOALLOC_MAX_PARTICLES / CH);
+constexpr int64_t NA_ACT = NA_BLOCKS + sizeof(GridBlock) * (MPM_NOALLOC_MAX_NODES / 256);
+constexpr int64_t NA_GRID = NA_ACT + sizeof(int) * MPM_NOALLOC_MAX_PARTICLES;
+constexpr int64_t NA_BYTES = NA_GRID + sizeof(float) * 7 * MPM_NOALLOC_MAX_NODES;
+static_assert(NA_BLOCKS % 256 == 0 && NA_ACT % 256 == 0 && NA_GRID % 256 == 0,
+              "regions keep 256-byte alignment");
+static_assert(sizeof(DevScene) <= 256, "the scene descriptor fits its slot");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+unsigned char *na_ptr[NA_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (looked up once per
+// device; host code never uses the array's name as an address).
+int noalloc_region(unsigned char **out) {
+  int dev = 0;
+  RC(hip_ok(hipGetDevice(&dev)));
+  if (dev < 0 || dev >= NA_MAX_DEVICES) return MPM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(na_mutex);
+  if (!na_ptr[dev]) {
+    void *p = nullptr;
+    RC(hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))));
+    if (!p) return MPM_ERR_HIP;
+    na_ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = na_ptr[dev];
+  return MPM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mpm_step_forward_noalloc(const mpm_scene *scene, const int32_t *act_id,
+                             const mpm_state *s_n, const float *act_n,
+                             mpm_state *s_np1, uint32_t *err, void *stream) {
+  if (!scene || !s_n || !s_np1 || !err) return MPM_ERR_ARG;
+  const int dim = scene->dim;
+  if ((dim != 2 && dim != 3) || !scene_valid(*scene, dim)) return MPM_ERR_ARG;
+  const int64_t n = scene->n_grid;
+  const int64_t nodes = dim == 2 ? n * n : n * n * n;
+  const int64_t N = scene->n_particles;
+  if (nodes > MPM_NOALLOC_MAX_NODES || N > MPM_NOALLOC_MAX_PARTICLES) return MPM_ERR_ARG;
+  if (scene->n_act > 0 && !act_n) return MPM_ERR_ARG;
+  if (N > 0 && (!s_n->x || !s_n->v || !s_n->C || !s_n->F || !s_np1->x || !s_np1->v ||
+                !s_np1->C || !s_np1->F))
+    return MPM_ERR_ARG;
+  unsigned char *base = nullptr;
+  RC(noalloc_region(&base));
+  hipStream_t st = (hipStream_t)stream;
+  DevScene *d_sc = reinterpret_cast<DevScene *>(base + NA_SCENE);
+  Chunk *chunks = reinterpret_cast<Chunk *>(base + NA_CHUNKS);
+  GridBlock *blocks = reinterpret_cast<GridBlock *>(base + NA_BLOCKS);
+  int *ids = reinterpret_cast<int *>(base + NA_ACT);
+  float *gm = reinterpret_cast<float *>(base + NA_GRID);
+  float *gp = gm + MPM_NOALLOC_MAX_NODES;
+  float *gv = gp + 3 * MPM_NOALLOC_MAX_NODES;
+  const int64_t G = MPM_NOALLOC_MAX_NODES;  // plane stride of p and v
+  unsigned *d_err = reinterpret_cast<unsigned *>(err);
+
+  NoAllocArgs na;
+  na.sc = dev_scene(*scene, dim == 2 ? 8 : 4);
+  na.dim = dim;
+  na.N = (int)N;
+  na.nodes = nodes;
+  na.G = G;
+  na.scene = d_sc;
+  na.chunks = chunks;
+  na.blocks = blocks;
+  na.act_id_in = act_id;
+  na.act_id = ids;
+  na.gm = gm;
+  na.gp = gp;
+  na.err = d_err;
+  if (launch_noalloc_setup(na, st)) return MPM_ERR_HIP;
+
+  const CState s{s_n->x, s_n->v, s_n->C, s_n->F};
+  const State o{s_np1->x, s_np1->v, s_np1->C, s_np1->F};
+  P2GArgs a1{};
+  a1.scenes = d_sc;
+  a1.chunks = chunks;
+  a1.n_chunks = (int)((N + CH - 1) / CH);
+  a1.s = s;
+  a1.ld = (int)N;
+  a1.act_id = ids;
+  a1.act = act_n;
+  a1.gm = gm;
+  a1.gp = gp;
+  a1.G = G;
+  a1.err = d_err;
+  if (launch_p2g(dim, a1, st)) return MPM_ERR_HIP;
+  GridArgs a2{};
+  a2.scenes = d_sc;
+  a2.blocks = blocks;
+  a2.n_blocks = (int)((nodes + 255) / 256);
+  a2.gm = gm;
+  a2.gp = gp;
+  a2.gv = gv;
+  a2.G = G;
+  a2.zero_mp = 0;  // the next call clears m and p in its set-up
+  if (launch_grid(dim, a2, st)) return MPM_ERR_HIP;
+  G2PArgs a3{};
+  a3.scenes = d_sc;
+  a3.chunks = chunks;
+  a3.n_chunks = a1.n_chunks;
+  a3.s = s;
+  a3.out = o;
+  a3.ld = (int)N;
+  a3.gv = gv;
+  a3.G = G;
+  a3.err = d_err;
+  if (launch_g2p(dim, a3, st)) return MPM_ERR_HIP;
   return MPM_OK;
 }
 

@@ -17,7 +17,8 @@ constexpr int LDS_NODES = 1024;
 constexpr int LDS_ACT = 64;
 
 // Sticky device error bits (ORed into the context's error word).
-enum : unsigned { EB_DOMAIN = 1u, EB_INVERTED = 2u, EB_NONFINITE = 4u };
+enum : unsigned { EB_DOMAIN = 1u, EB_INVERTED = 2u, EB_NONFINITE = 4u,
+                  EB_ACT_ID = 8u /* allocation-free step: actuator id out of range */ };
 
 // Per-scene constants, precomputed on the host in FP32.
 struct DevScene {
@@ -235,6 +236,21 @@ int launch_mat_field(const DevScene *scenes, const int *pscene, int N,
                      const float *E_p, const float *rho_p, float *mat, hipStream_t st);
 int launch_mat_grad(const DevScene *scenes, const int *pscene, int N, const int *perm,
                     const float *gmat, float *g_E, float *g_rho, hipStream_t st);
+// The allocation-free single substep's set-up (one scene): descriptors,
+// sanitised actuator ids and cleared m, p in the caller's device region.
+struct NoAllocArgs {
+  DevScene sc;
+  int dim, N;
+  int64_t nodes, G;     // the scene's nodes; plane stride of gp
+  DevScene *scene;
+  Chunk *chunks;
+  GridBlock *blocks;
+  const int *act_id_in;  // caller's ids (device, nullable: all passive)
+  int *act_id;           // sanitised copy [N]
+  float *gm, *gp;
+  unsigned *err;
+};
+int launch_noalloc_setup(const NoAllocArgs &a, hipStream_t st);
 int launch_fill_f32(float *p, int64_t n, hipStream_t st);
 int launch_fill_f64(double *p, int64_t n, hipStream_t st);
 int launch_fill_i32(int *p, int64_t n, hipStream_t st);

@@ -3047,6 +3047,42 @@ __global__ __launch_bounds__(256) void k_mat_grad(const DevScene *scenes,
   if (g_rho) g_rho[p] = gmat[2 * N + i] * sc.V0;
 }
 
+// Descriptors and cleared grid of the allocation-free single substep, all
+// from kernel arguments (a captured graph replays them): the scene, its
+// chunks of CH particles and node blocks of 256 nodes, a copy of the
+// actuator ids in which an id outside [-1, n_act) becomes passive and sets
+// EB_ACT_ID, and m = p = 0 on the scene's nodes.
+__global__ __launch_bounds__(256) void k_noalloc_setup(NoAllocArgs a) {
+  const int64_t n = (int64_t)gridDim.x * 256;
+  const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int nch = (a.N + CH - 1) / CH, nb = (int)((a.nodes + 255) / 256);
+  if (t0 == 0) *a.scene = a.sc;
+  for (int64_t i = t0; i < nch; i += n)
+    a.chunks[i] = Chunk{0, (int)(i * CH), (int)min<int64_t>(CH, a.N - i * CH), 0};
+  for (int64_t i = t0; i < nb; i += n)
+    a.blocks[i] = GridBlock{0, (int)(i * 256), (int)min<int64_t>(256, a.nodes - i * 256), 0};
+  unsigned eb = 0;
+  for (int64_t i = t0; i < a.N; i += n) {
+    int j = a.act_id_in ? a.act_id_in[i] : -1;
+    if (j < -1 || j >= a.sc.n_act) {
+      eb |= EB_ACT_ID;
+      j = -1;
+    }
+    a.act_id[i] = j;
+  }
+  if (eb) atomicOr(a.err, eb);
+  for (int64_t i = t0; i < (int64_t)(1 + a.dim) * a.nodes; i += n) {
+    if (i < a.nodes) a.gm[i] = 0.0f;
+    else a.gp[((i - a.nodes) / a.nodes) * a.G + (i - a.nodes) % a.nodes] = 0.0f;
+  }
+}
+
+int launch_noalloc_setup(const NoAllocArgs &a, hipStream_t st) {
+  const int64_t work = std::max<int64_t>(a.N, (1 + a.dim) * a.nodes);
+  const int g = (int)std::min<int64_t>(std::max<int64_t>(blocks_for(work), 1), 2048);
+  MPM_LAUNCH(k_noalloc_setup, g, 256, st, a);
+}
+
 int launch_fill_f32(float *p, int64_t n, hipStream_t st) {
   const int g = (int)std::min<int64_t>(blocks_for(n), 4096);
   MPM_LAUNCH(k_fill<float>, g, 256, st, p, n);

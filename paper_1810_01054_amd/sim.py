@@ -270,6 +270,36 @@ class Simulator:
         return g.value
 
 
+def step_forward_noalloc(scene: dict, s: StateT, act: Optional[torch.Tensor],
+                         out: StateT, err: torch.Tensor,
+                         act_id: Optional[torch.Tensor] = None, stream=None) -> None:
+    """mpm_step_forward_noalloc: one substep of one scene with no context and
+    no allocation (the library's static per-GPU region holds the grid).
+    ``out`` and ``err`` (int32 [1] on the GPU, device error bits OR-ed in)
+    are the caller's; ``act_id`` is an int32 CUDA tensor [N] or None."""
+    L = _lib.lib()
+    d, N = scene["dim"], scene["n_particles"]
+    shapes = [(d, N), (d, N), (d * d, N), (d * d, N)]
+    for st, nm in ((s, "s_n"), (out, "s_np1")):
+        for t, sh, c in zip(st, shapes, "xvCF"):
+            _check_tensor(t, sh, f"{nm}.{c}")
+    if not (err.is_cuda and err.dtype == torch.int32 and err.numel() >= 1):
+        raise ValueError("err must be an int32 CUDA tensor")
+    if act_id is not None and not (act_id.is_cuda and act_id.dtype == torch.int32
+                                   and act_id.is_contiguous() and act_id.numel() == N):
+        raise ValueError(f"act_id must be a contiguous int32 CUDA tensor of {N} entries")
+    n_act = scene.get("n_act", 0)
+    if n_act:
+        _check_tensor(act, (n_act,), "act")
+    sc = scene_struct(scene)
+    a = _lib.State(*[t.data_ptr() for t in s])
+    o = _lib.State(*[t.data_ptr() for t in out])
+    check(L.mpm_step_forward_noalloc(ctypes.byref(sc), _ptr(act_id), ctypes.byref(a),
+                                     _ptr(act) if n_act else None, ctypes.byref(o),
+                                     _ptr(err), _stream_ptr(stream)),
+          "mpm_step_forward_noalloc")
+
+
 def act_bank_forward(T: int, dt: float, freq: torch.Tensor, amp: torch.Tensor,
                      phase: torch.Tensor, stream=None) -> torch.Tensor:
     L = _lib.lib()
