@@ -41,7 +41,10 @@ def kernel_bytes_per_particle(kernel: str, d: int) -> int:
         "g2p": (v + m) + state,                    # x, F in; state out
         "adj_scatter": (v + m) + state,            # x, F, adjoint in
         "adj_gather": state + state + 4 + state,   # S^n, adj in, id; adj out
-        "g2p_p2g": (v + m) + 4 + state,            # x, F, id in; state out
+        # x, F, id in; x, F out (v and C too on checkpoint substeps)
+        "g2p_p2g": (v + m) + 4 + (v + m),
+        # state n, adjoint of n+1, id, x and F of n-1 in; adjoint of n out
+        "adj_fused": state + state + 4 + (v + m) + state,
     }[kernel]
 
 
@@ -257,10 +260,14 @@ def run_batched(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    from paper_1810_01054_amd.autotune import tune
+    from paper_1810_01054_amd.autotune import tune, tune_checkpoint
     N = sum(s.n_particles for s in scs)
-    tuned = tune([s.params() for s in scs], np.concatenate([s.act_id for s in scs]),
-                 state_of(scs), acts_of(scs), use_cache=False)
+    ids = np.concatenate([s.act_id for s in scs])
+    tuned = tune([s.params() for s in scs], ids, state_of(scs), acts_of(scs), use_cache=False)
+    # the checkpoint interval too, unless one was given
+    if args.ckpt_given is None:
+        k = tune_checkpoint([s.params() for s in scs], ids, state_of(scs), acts_of(scs), T,
+                            tuned, use_cache=False)
     batched = [make(scs, **tuned)]
     run(batched, 1)
     wb = run(batched, args.steps)
@@ -296,11 +303,58 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_c2(args):
+    """C2: 2D 256^2, six soft-robot blocks (98,304 particles, 48 actuators
+    with sinusoid banks), T = 1,000 substeps forward + reverse with a
+    checkpoint every 64; loss = centroid x of the final state.  Its blocks
+    travel several cells, so most particles leave their tile box's slack in
+    the second half of the rollout."""
+    import numpy as np
+    import torch
+
+    from paper_1810_01054_amd import scenes as S
+    from paper_1810_01054_amd.sim import Simulator, act_bank_forward
+
+    sc = S.config_2()
+    T = args.T if args.T != 512 else 1000
+    k = args.ckpt_given if args.ckpt_given is not None else 64
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    sim = Simulator([sc.params()], act_id=sc.act_id, fusion=args.fusion)
+    s0 = tuple(t(a) for a in sc.state)
+    act = act_bank_forward(T, sc.dt, t(sc.freq), t(sc.amp), t(sc.phase))
+    N = sc.n_particles
+    gT = [torch.zeros_like(a) for a in s0]
+    gT[0][0].fill_(1.0 / N)
+    gT = tuple(gT)
+    for _ in range(max(args.warmup, 1)):
+        sim.rollout(s0, act, T, k, gT)
+    sim.sync_errors()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sim.rollout(s0, act, T, k, gT)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync_errors()
+    value = N * T * args.steps / wall
+    print(json.dumps({"metric": "particle-substeps/s fwd+bwd, 2D 256^2/98k", "value": round(value, 1),
+                      "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"c2_2d256_98k: 6 blocks, {N} particles, "
+                                             f"T={T} fwd+bwd, checkpoint k={k}",
+                                 "particles": N, "substeps": T, "ckpt_k": k}}), flush=True)
+
+
 def run_serving(args):
     """Poisson arrivals of forward+gradient rollout requests (half 2D, half
-    3D) served by the continuous-admission loop and, on the same trace, by
-    the plain one-at-a-time loop.  The arrival rate is swept at fractions of
-    the plain loop's measured capacity plus one overload point."""
+    3D) served with continuous batching (waiting requests of one dimension
+    share one multi-scene context per lane, each held fixed past its own T)
+    and, on the same trace, by the plain one-at-a-time loop.  The arrival
+    rate is swept at fractions of the plain loop's measured capacity plus one
+    overload point."""
     import torch
 
     from paper_1810_01054_amd import scenes as S
@@ -309,32 +363,36 @@ def run_serving(args):
     n_req = args.requests
     base = S.config_5(n_requests=n_req, rate=1.0, seed=1815)
     warm = S.config_5(n_requests=6, rate=1.0, seed=1816)
-    Server(max_slots=4, ckpt_k=args.ckpt).run([S.Request(0.0, r.scene, r.T) for r in warm])
+    Server(max_batch=args.max_batch, lanes=args.lanes, ckpt_k=args.ckpt).run(
+        [S.Request(0.0, r.scene, r.T) for r in warm])
     burst = [S.Request(0.0, r.scene, r.T) for r in base]
-    cap_res = Server(max_slots=1, ckpt_k=args.ckpt).run(burst, fifo=True)
+    cap_res = Server(ckpt_k=args.ckpt).run(burst, fifo=True)
     cap = summarize(cap_res)["requests_per_s"]
     print(f"c5: plain-loop capacity {cap:.2f} requests/s", file=sys.stderr, flush=True)
     points = []
     for frac in (0.5, 0.8, 0.95, 1.5):
         rate = frac * cap
         reqs = [S.Request(r.arrival / rate, r.scene, r.T) for r in base]
-        mix = summarize(Server(max_slots=args.slots, ckpt_k=args.ckpt).run(reqs))
-        print(f"c5: load {frac} continuous p99 {mix['latency_s']['p99']}", file=sys.stderr,
-              flush=True)
-        fifo = summarize(Server(max_slots=1, ckpt_k=args.ckpt).run(reqs, fifo=True))
-        print(f"c5: load {frac} fifo p99 {fifo['latency_s']['p99']}", file=sys.stderr,
-              flush=True)
-        points.append({"load": frac, "rate_per_s": round(rate, 3), "continuous": mix,
+        mix = summarize(Server(max_batch=args.max_batch, lanes=args.lanes,
+                               ckpt_k=args.ckpt).run(reqs))
+        print(f"c5: load {frac} batched p50 {mix['latency_s']['p50']:.3f} p99 "
+              f"{mix['latency_s']['p99']:.3f} req/s {mix['requests_per_s']:.2f} "
+              f"mean batch {mix['mean_batch']:.2f}", file=sys.stderr, flush=True)
+        fifo = summarize(Server(ckpt_k=args.ckpt).run(reqs, fifo=True))
+        print(f"c5: load {frac} fifo p50 {fifo['latency_s']['p50']:.3f} p99 "
+              f"{fifo['latency_s']['p99']:.3f} req/s {fifo['requests_per_s']:.2f}",
+              file=sys.stderr, flush=True)
+        points.append({"load": frac, "rate_per_s": round(rate, 3), "batched": mix,
                        "fifo": fifo})
-    top = points[2]["continuous"]
+    top = points[2]["batched"]
     out = {"metric": "p99 rollout latency (serving, Poisson mix of 2D/3D fwd+grad requests)",
            "value": top["latency_s"]["p99"], "unit": "s", "n_gpus": 1, "steps": n_req,
            "warmup": len(warm), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{n_req} requests, half 2D (4k-100k particles, 64-256^2) "
                                   f"half 3D (50k-500k, 32-64^3), T 100-500, load 0.95 of "
-                                  f"the plain loop's capacity", "slots": args.slots,
-                      "ckpt_k": args.ckpt},
+                                  f"the plain loop's capacity", "max_batch": args.max_batch,
+                      "lanes": args.lanes, "ckpt_k": args.ckpt},
            "plain_loop_capacity_req_per_s": round(cap, 3),
            "points": points}
     print(json.dumps(out), flush=True)
@@ -346,30 +404,42 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--T", type=int, default=512, help="substeps per rollout")
-    ap.add_argument("--ckpt", type=int, default=32,
-                    help="checkpoint interval (0 = store every state)")
+    ap.add_argument("--ckpt", type=int, default=None,
+                    help="checkpoint interval (0 = store every state; default 32, "
+                         "autotuned for c4)")
     ap.add_argument("--cpu-sample", type=int, default=10,
                     help="substeps of the oracle sample (0 = skip)")
     ap.add_argument("--scatter", type=int, default=0,
                     help="binned scatter mode: 0 default, 1 per-particle LDS atomics, "
                          "2 per-cell in bin order, 3 per-cell after an LDS sort")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c3ctrl", "c4", "c5", "copy"],
-                    help="c3: 3D quadruped (headline); c3ctrl: the same, closed-loop "
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c3ctrl", "c2", "c4", "c5", "copy"],
+                    help="c3: 3D quadruped (headline); c2: 2D 256^2, 98k particles, "
+                         "1,000 substeps; c3ctrl: the same quadruped, closed-loop "
                          "controller; c4: 64 batched 2D scenes; "
                          "c5: serving a Poisson request mix; copy: plain device copy "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--requests", type=int, default=60, help="c5: requests per load point")
-    ap.add_argument("--slots", type=int, default=8, help="c5: concurrent requests")
+    ap.add_argument("--max-batch", type=int, default=16,
+                    help="c5: requests per batch (one multi-scene context)")
+    ap.add_argument("--lanes", type=int, default=2, help="c5: concurrent batches")
     ap.add_argument("--friction", type=float, default=None,
                     help="c3/c3ctrl: walls with the friction projection and this "
                          "coefficient instead of sticky walls")
     ap.add_argument("--materials", action="store_true",
                     help="c3: a per-particle stiffness and density field (E, rho "
                          "x U[0.5, 1.5) / U[0.7, 1.3)) with their gradients")
+    ap.add_argument("--fusion", type=int, default=0,
+                    help="c3: 0 = G2P fused with the next P2G (default), 1 = every "
+                         "kernel separate, 2 = also the reverse gather fused with the "
+                         "previous adjoint scatter")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
+    args.ckpt_given = args.ckpt
+    if args.ckpt is None:
+        args.ckpt = 32
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -406,6 +476,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         return run_batched(args)
+    if args.workload == "c2":
+        return run_c2(args)
     if args.workload == "c5":
         return run_serving(args)
     if args.workload == "copy":
@@ -415,7 +487,8 @@ def main():
         sc.bc, sc.friction = 1, float(np.float32(args.friction))
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
-    sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter)
+    sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter,
+                    fusion=args.fusion)
     t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
     x0, v0, C0, F0 = (t(a) for a in sc.state)
     v0.requires_grad_(True)
@@ -456,10 +529,11 @@ def main():
     dominant = "adj_gather"
     warm_prof = None
     kernel_roof = None
+    realised_pss = None
     for w in range(max(args.warmup, 1)):
         if w == 0 and not args.no_profile:
             sim.profile(["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather",
-                         "g2p_p2g"])
+                         "g2p_p2g", "adj_fused"])
         one_step()
         if w == 0 and not args.no_profile:
             prof = sim.profile_read()
@@ -484,6 +558,13 @@ def main():
             tot = sum(v["_ms"] for v in kernel_roof.values())
             for v in kernel_roof.values():
                 v["share_of_time"] = round(v.pop("_ms") / tot, 4)
+            # the particle-stream bytes the launched kernels move per
+            # particle-substep (from the launch counts of this rollout)
+            realised_pss = sum(
+                n * (kernel_bytes_per_node(kk, d) * sim.G if kk in ("grid", "adj_grid")
+                     else kernel_bytes_per_particle(kk, d) * N)
+                for kk, (n, ms) in prof.items() if n and kk not in ("grid", "adj_grid")
+            ) / (N * T)
     sim.sync_errors()
     torch.cuda.synchronize()
 
@@ -566,11 +647,14 @@ def main():
                              else f"friction projection, c = {args.friction}"),
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
                    "scatter_mode": args.scatter,
+                   "fusion": args.fusion,
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),
-        # the kernels as built move 148 (fused forward) + 144 (recompute G2P)
-        # + 436 (adjoint scatter + gather) algorithmic bytes per particle-substep
-        "pct_hbm_peak_728B_realised": round(728.0 * value / (HBM_PEAK_GBS * 1e9), 4),
+        # the particle-stream bytes the launched kernels move (launch counts
+        # of the profiled warm-up rollout x each kernel's stream bytes)
+        "realised_bytes_per_pss": None if realised_pss is None else round(realised_pss, 1),
+        "pct_hbm_peak_realised": (None if realised_pss is None else
+                                  round(realised_pss * value / (HBM_PEAK_GBS * 1e9), 4)),
         "rollout_latency_ms": {"p50": round(percentile(lat, 0.5), 3),
                                "p99": round(percentile(lat, 0.99), 3)},
         "roofline": roof,

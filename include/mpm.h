@@ -104,7 +104,24 @@ typedef struct mpm_opts {
                           (captured once per tape layout on a library-owned
                           stream, launched on the context's stream); kernel
                           timing (mpm_profile) turns them off; 0 = eager     */
-  int32_t reserved[3]; /* must be 0                                         */
+  int32_t fusion;      /* 3D binned rollouts: 0 = fuse each G2P with the next
+                          substep's P2G (default); 1 = run every kernel
+                          separately; 2 = also fuse each reverse gather with
+                          the previous substep's adjoint scatter (two
+                          workgroups per CU: slower on the measured scenes)  */
+  int32_t deterministic; /* 1: binned rollouts are bitwise reproducible: the
+                          binning ranks a cell's particles by index, the
+                          scatters add a cell's records in a fixed order and
+                          dL/ds is summed per actuator in a fixed order (needs
+                          sort = 1 and the sorted scatter, i.e. the default
+                          tile); particles that drift beyond their tile box's
+                          one cell of slack still add with float atomics, so
+                          a rollout is reproducible while none does; 0 = off */
+  int32_t persistent;  /* 1: the binned rollouts' grid kernels run as
+                          persistent workgroups (eight one-wave workgroups per
+                          CU, each looping over its XCD's share of the node
+                          tiles) instead of one workgroup per node tile    */
+  int32_t reserved[2]; /* must be 0                                         */
 } mpm_opts;
 
 /* Particle state or its adjoint (DEVICE pointers, layout above). */
@@ -273,6 +290,16 @@ int mpm_rollout_ctrl(mpm_ctx *ctx, int T, int ckpt_k, const mpm_state *s0,
 int mpm_rollout_ctrl_backward(mpm_ctx *ctx, const mpm_state *gT, mpm_state *g0,
                               float *g_act, float *g_W, float *g_b);
 
+/* Per-scene horizons (batched requests of different lengths): scene s is
+ * held fixed from substep t_end[s] on, so a rollout of T >= t_end[s]
+ * substeps returns its state after t_end[s] substeps, and the reverse pass
+ * seeded at T returns the gradients of a loss on that state (the substeps
+ * past the horizon are the identity and add nothing to dL/ds).  t_end: HOST
+ * int32 [n_scenes], each >= 0; NULL removes every horizon.  Copied on the
+ * context's stream; invalidates the tape.  Not combined with a closed-loop
+ * controller (mpm_rollout_ctrl returns MPM_ERR_ARG). */
+int mpm_set_horizons(mpm_ctx *ctx, const int32_t *t_end);
+
 /* Per-particle materials (the co-design and system-identification uses of
  * section IV: a stiffness or density field instead of one material per
  * scene).  E_p, rho_p: DEVICE float [N_tot] in caller order, each nullable
@@ -332,7 +359,9 @@ int mpm_sync_errors(mpm_ctx *ctx);
 #define MPM_K_ADJ_GRID 4
 #define MPM_K_ADJ_GATHER 5
 #define MPM_K_G2P_P2G 6 /* G2P of substep n fused with P2G of n+1 (3D rollouts) */
-#define MPM_NUM_KERNELS 7
+#define MPM_K_ADJ_FUSED 7 /* reverse gather of substep n fused with the adjoint
+                             scatter of n-1 (3D rollouts) */
+#define MPM_NUM_KERNELS 8
 int mpm_profile(mpm_ctx *ctx, uint32_t mask);
 int mpm_profile_read(mpm_ctx *ctx, int64_t *count, double *ms);
 

@@ -35,7 +35,9 @@ class Scene(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("sort", ctypes.c_int32),
                 ("scatter", ctypes.c_int32), ("recompute_grids", ctypes.c_int32),
-                ("graphs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("graphs", ctypes.c_int32), ("fusion", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class State(ctypes.Structure):
@@ -56,9 +58,10 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
            "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split",
            "mpm_set_materials", "mpm_material_grad", "mpm_tape_generation",
-           "mpm_step_forward_noalloc"]
+           "mpm_step_forward_noalloc", "mpm_set_horizons"]
 
-KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g"]
+KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g",
+           "adj_fused"]
 
 _lib = None
 
@@ -90,6 +93,7 @@ def lib():
                                    sp, sp, vp, vp, vp]
     L.mpm_rollout_ctrl_backward.argtypes = [vp, sp, sp, vp, vp, vp]
     L.mpm_set_materials.argtypes = [vp, vp, vp]
+    L.mpm_set_horizons.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mpm_material_grad.argtypes = [vp, vp, vp]
     L.mpm_tape_generation.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     L.mpm_revolve_steps.argtypes = [ctypes.c_int64, ctypes.c_int32]

@@ -1,10 +1,14 @@
 """Autotuner for libmpm's launch and tape options.
 
-For a batch of scenes it times short forward + reverse rollouts under each
-candidate configuration (binned scatter mode, tile edge, hipGraph replay,
-checkpoint interval) and keeps the fastest.  Results are cached on disk,
-keyed by GPU architecture, dimension, grid sizes and a particle-count
-bucket, so a configuration is measured once per shape class.
+For a batch of scenes, `tune` times short forward + reverse rollouts under
+each candidate launch configuration (binned scatter mode and tile edge,
+persistent grid kernels, G2P fused with the next P2G or not in 3D, hipGraph
+replay) and keeps the one
+with the smallest median time over the repeats; `tune_checkpoint` then times
+the candidate checkpoint intervals k on a longer probe with those options.
+Results are cached on disk, keyed by GPU architecture, dimension, grid sizes,
+scene count and a particle-count bucket (and, for k, the rollout length), so
+a configuration is measured once per shape class.
 """
 from __future__ import annotations
 
@@ -25,10 +29,15 @@ CACHE_PATH = os.environ.get(
 
 
 def candidates(dim: int) -> List[dict]:
-    """Binned-scatter variants (mode, tile edge) x hipGraph replay."""
-    base = ([{"scatter": 3, "tile": 8}, {"scatter": 1, "tile": 8}, {"scatter": 1, "tile": 16}]
+    """Binned-scatter variants (mode, tile edge; the sorted scatter also with
+    persistent grid kernels and, in 3D, without the fused G2P + P2G kernel)
+    x hipGraph replay."""
+    base = ([{"scatter": 3, "tile": 8}, {"scatter": 3, "tile": 8, "persistent": True},
+             {"scatter": 1, "tile": 8}, {"scatter": 1, "tile": 16}]
             if dim == 2 else
-            [{"scatter": 3, "tile": 4}, {"scatter": 1, "tile": 4}, {"scatter": 1, "tile": 8}])
+            [{"scatter": 3, "tile": 4}, {"scatter": 3, "tile": 4, "persistent": True},
+             {"scatter": 3, "tile": 4, "fusion": 1},
+             {"scatter": 1, "tile": 4}, {"scatter": 1, "tile": 8}])
     return [dict(c, graphs=g) for c in base for g in (False, True)]
 
 
@@ -63,9 +72,23 @@ def best_k(T: int) -> int:
     return max(1, int(round(math.sqrt(max(T, 1)))))
 
 
+def _median_time(sim, state, act, T, k, gT, repeats):
+    sim.rollout(state, act, T, k, gT)          # warm-up / capture
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        sim.rollout(state, act, T, k, gT)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    sim.sync_errors()
+    return float(np.median(ts))
+
+
 def tune(scenes: Sequence[dict], act_id: np.ndarray, state, act: Optional[torch.Tensor],
-         T_probe: int = 16, repeats: int = 2, use_cache: bool = True) -> dict:
-    """Fastest option set (Simulator keyword arguments) for this batch."""
+         T_probe: int = 16, repeats: int = 3, use_cache: bool = True) -> dict:
+    """Fastest option set (Simulator keyword arguments) for this batch: the
+    smallest median time of `repeats` fwd + bwd rollouts of T_probe substeps."""
     key = shape_key(scenes)
     cache = _load() if use_cache else {}
     if key in cache:
@@ -79,14 +102,7 @@ def tune(scenes: Sequence[dict], act_id: np.ndarray, state, act: Optional[torch.
         except Exception:
             continue
         gT = tuple(torch.zeros_like(s) for s in state)
-        sim.rollout(state, act_p, T_probe, 8, gT)          # warm-up / capture
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(repeats):
-            sim.rollout(state, act_p, T_probe, 8, gT)
-        torch.cuda.synchronize()
-        timings.append(((time.perf_counter() - t0) / repeats, opts))
-        sim.sync_errors()
+        timings.append((_median_time(sim, state, act_p, T_probe, 8, gT, repeats), opts))
         sim.close()
     timings.sort(key=lambda t: t[0])
     best = timings[0][1]
@@ -95,3 +111,30 @@ def tune(scenes: Sequence[dict], act_id: np.ndarray, state, act: Optional[torch.
                       "candidates": [o for _, o in timings]}
         _store(cache)
     return dict(best)
+
+
+def tune_checkpoint(scenes: Sequence[dict], act_id: np.ndarray, state,
+                    act: Optional[torch.Tensor], T: int, opts: dict,
+                    ks: Sequence[int] = (8, 16, 32, 64), T_probe: int = 128,
+                    repeats: int = 3, use_cache: bool = True) -> int:
+    """Checkpoint interval for rollouts of T substeps: the candidate k
+    (k <= T) with the smallest median time of fwd + bwd rollouts of
+    min(T, T_probe) substeps under the options `opts`."""
+    key = f"{shape_key(scenes)}/T{T}/k"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return int(cache[key]["k"])
+    Tp = min(T, T_probe)
+    act_p = None if act is None else act[:Tp].contiguous()
+    sim = Simulator(scenes, act_id=act_id, **opts)
+    gT = tuple(torch.zeros_like(s) for s in state)
+    timings = [(_median_time(sim, state, act_p, Tp, k, gT, repeats), k)
+               for k in ks if k <= Tp] or [(0.0, best_k(T))]
+    sim.close()
+    timings.sort()
+    k = int(timings[0][1])
+    if use_cache:
+        cache[key] = {"k": k, "ms": [round(t * 1e3, 3) for t, _ in timings],
+                      "candidates": [kk for _, kk in timings]}
+        _store(cache)
+    return k

@@ -44,6 +44,17 @@ struct mpm_ctx {
   int scatter_mode = 1;  // binned scatters: 1 atomics, 2 per-cell, 3 sorted per-cell
   int keep_grids = 1;    // checkpointed tapes keep every substep's grid
   int use_graphs = 0;    // rollouts replay captured hipGraphs
+  int fuse_forward = 1;  // 3D binned rollouts: G2P fused with the next P2G
+  int fuse_reverse = 0;  // 3D binned reverse: gather fused with the previous scatter
+  int det = 0;           // deterministic sums (binned rollouts)
+  bool horizons = false; // some scene has a horizon (mpm_set_horizons)
+  int persistent = 0;    // persistent node-tile grid kernels
+  int use_nt = 0;        // node-tile grid kernels (sorted scatter, 64-cell tiles)
+  int n_nt = 0;          // node tiles of all scenes
+  int *d_nt_scene = nullptr, *d_nt_dirty = nullptr;
+  int *d_cell_start = nullptr, *d_cell_list = nullptr;  // det binning
+  float *sb_part = nullptr;  // det: per-particle dL/ds of one substep
+  int *d_act_scene = nullptr;  // det: scene of each actuator
 
   // captured inner loops of rollouts (forward, reverse)
   struct GraphKey {
@@ -189,6 +200,8 @@ DevScene dev_scene(const mpm_scene &S, int tile) {
   d.nu = S.nu;
   d.fric = S.bc == 1 ? S.friction : 0.0f;
   d.nt = (int)((S.n_grid - 2 + tile - 1) / tile);
+  d.nnt = S.n_grid / tile + 1;
+  d.t_end = INT32_MAX;
   d.dt = S.dt;
   d.dx = 1.0f / (float)S.n_grid;
   d.inv_dx = (float)S.n_grid;
@@ -319,14 +332,16 @@ TileInfo tile_info(mpm_ctx *c) {
   t.part = c->d_part;
   t.B = c->tile;
   t.list = c->d_tile_list;
+  t.nt_dirty = c->use_nt ? c->d_nt_dirty : nullptr;
   return t;
 }
 
 // `tiles`: particles are binned (rollouts); scatters go through tile boxes.
 int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
             CState s, const int *act_id, const float *act, float *gm,
-            float *gp) {
+            float *gp, int n = 0) {
   P2GArgs a;
+  a.n = n;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
   a.n_chunks = n_chunks;
@@ -342,6 +357,7 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   // per-particle materials: the sorted scatter's records then carry each
   // particle's mass (the per-cell mode falls back to per-tile LDS atomics)
   a.mat = c->has_mat ? (tiles ? c->mat_sorted : c->mat_user) : nullptr;
+  a.det = tiles && c->det;
   ProfScope ps(c, MPM_K_P2G);
   if (tiles && c->scatter_mode == 3)
     return launch_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
@@ -369,14 +385,22 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
   a.out_m = out_m;
   a.out_p = out_p;
   ProfScope ps(c, MPM_K_GRID);
+  if (tiles && c->use_nt) {
+    a.nt_scene = c->d_nt_scene;
+    a.nt_dirty = c->d_nt_dirty;
+    a.n_nt = c->n_nt;
+    a.persist = c->persistent;
+    return launch_grid_nt(c->dim, a, c->stream);
+  }
   return launch_grid(c->dim, a, c->stream);
 }
 
 int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
             State out, const float *gv, const float *gm = nullptr,
             const float *gp = nullptr, hipStream_t st = nullptr,
-            bool ctl_sums = false) {
+            bool ctl_sums = false, int n = 0) {
   G2PArgs a;
+  a.n = n;
   a.scenes = c->d_scenes;
   a.chunks = chunks;
   a.n_chunks = n_chunks;
@@ -402,8 +426,10 @@ int fwd_g2p(mpm_ctx *c, const Chunk *chunks, int n_chunks, CState s,
 // G2P of substep n (state s, grid velocity gv) fused with the binned P2G of
 // substep n+1 (actuation act1) into the tile boxes; writes state n+1.
 int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
-                const int *act_id, const float *act1) {
+                const int *act_id, const float *act1, bool write_vc, int n) {
   G2P2GArgs a;
+  a.n = n;
+  a.write_vc = write_vc ? 1 : 0;
   a.scenes = c->d_scenes;
   a.s = s;
   a.out = out;
@@ -417,18 +443,19 @@ int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
   a.err = c->d_err;
   a.tiles = tile_info(c);
   a.mat = c->has_mat ? c->mat_sorted : nullptr;  // (binned rollouts only)
+  a.det = c->det;
   ProfScope ps(c, MPM_K_G2P_P2G);
   return launch_g2p_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
 }
 
-// ---- the three kernels of one reverse substep ------------------------------
+// ---- the kernels of one reverse substep ------------------------------------
 // gm/gp: forward grid of step n (m, p).
 
-int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
-             CState s, const int *act_id, const float *act,
-             const float *gm, const float *gp, CState g1, State g0,
-             double *gact) {
+// (A)-(C): adjoint of G2P, scattered into the tile boxes / vbar.
+int bwd_scatter(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
+                CState s, CState g1, int n = 0) {
   AdjScatterArgs r1;
+  r1.n = n;
   r1.scenes = c->d_scenes;
   r1.chunks = chunks;
   r1.n_chunks = n_chunks;
@@ -439,19 +466,19 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r1.G = c->G;
   r1.err = c->d_err;
   r1.tiles = tile_info(c);
-  {
-    ProfScope ps(c, MPM_K_ADJ_SCATTER);
-    if (tiles && c->scatter_mode == 3)
-      RC(launch_adj_scatter_sorted(c->dim, r1, c->n_tiles_ne, c->stream));
-    else {
-      r1.tiles.list = nullptr;
-      if (tiles && c->scatter_mode == 2)
-        RC(launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream));
-      else if (tiles) RC(launch_adj_scatter_tile(c->dim, r1, c->n_tiles, c->stream));
-      else RC(launch_adj_scatter(c->dim, r1, c->stream));
-    }
-  }
+  r1.det = tiles && c->det;
+  ProfScope ps(c, MPM_K_ADJ_SCATTER);
+  if (tiles && c->scatter_mode == 3)
+    return launch_adj_scatter_sorted(c->dim, r1, c->n_tiles_ne, c->stream);
+  r1.tiles.list = nullptr;
+  if (tiles && c->scatter_mode == 2)
+    return launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream);
+  if (tiles) return launch_adj_scatter_tile(c->dim, r1, c->n_tiles, c->stream);
+  return launch_adj_scatter(c->dim, r1, c->stream);
+}
 
+// (D)-(E): adjoint of the grid operations (sums the tile boxes).
+int bwd_grid(mpm_ctx *c, bool tiles, const float *gm, const float *gp) {
   AdjGridArgs r2;
   r2.scenes = c->d_scenes;
   r2.blocks = c->d_gblocks;
@@ -466,12 +493,23 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r2.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
   r2.part = tiles ? c->d_part : nullptr;
   r2.B = c->tile;
-  {
-    ProfScope ps(c, MPM_K_ADJ_GRID);
-    RC(launch_adj_grid(c->dim, r2, c->stream));
+  ProfScope ps(c, MPM_K_ADJ_GRID);
+  if (tiles && c->use_nt) {
+    r2.nt_scene = c->d_nt_scene;
+    r2.nt_dirty = c->d_nt_dirty;
+    r2.n_nt = c->n_nt;
+    r2.persist = c->persistent;
+    return launch_adj_grid_nt(c->dim, r2, c->stream);
   }
+  return launch_adj_grid(c->dim, r2, c->stream);
+}
 
+// (F)-(K): adjoint of P2G and of the particle update, gathered.
+int bwd_gather(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
+               CState s, const int *act_id, const float *act, CState g1,
+               State g0, double *gact, int n = 0) {
   AdjGatherArgs r3;
+  r3.n = n;
   r3.scenes = c->d_scenes;
   r3.chunks = chunks;
   r3.n_chunks = n_chunks;
@@ -489,8 +527,68 @@ int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r3.err = c->d_err;
   r3.mat = c->has_mat ? (tiles ? c->mat_sorted : c->mat_user) : nullptr;
   r3.gmat = c->has_mat ? c->gmat : nullptr;
-  ProfScope ps(c, MPM_K_ADJ_GATHER);
-  return launch_adj_gather(c->dim, r3, c->stream);
+  // deterministic mode: per-particle dL/ds, then a fixed-order sum
+  const bool det_s = tiles && c->det && gact != nullptr && c->n_act > 0;
+  if (det_s) {
+    r3.gact = nullptr;
+    r3.sb_part = c->sb_part;
+  }
+  {
+    ProfScope ps(c, MPM_K_ADJ_GATHER);
+    RC(launch_adj_gather(c->dim, r3, c->stream));
+  }
+  if (det_s)
+    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, c->d_tile_start,
+                          act_id, c->sb_part, c->dim, gact, c->stream));
+  return MPM_OK;
+}
+
+int bwd_step(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
+             CState s, const int *act_id, const float *act,
+             const float *gm, const float *gp, CState g1, State g0,
+             double *gact, int n = 0) {
+  RC(bwd_scatter(c, tiles, chunks, n_chunks, s, g1, n));
+  RC(bwd_grid(c, tiles, gm, gp));
+  return bwd_gather(c, tiles, chunks, n_chunks, s, act_id, act, g1, g0, gact, n);
+}
+
+// The gather of reverse substep n fused with the scatter of substep n-1
+// (3D binned rollouts): reads state n, the adjoint of state n+1 and x, F of
+// state n-1; writes the adjoint of state n (g0, not aliasing g1).
+int bwd_gather_scatter(mpm_ctx *c, CState s, CState sp, const int *act_id,
+                       const float *act, CState g1, State g0, double *gact, int n) {
+  AdjFusedArgs a;
+  a.n = n;
+  a.scenes = c->d_scenes;
+  a.s = s;
+  a.g1 = g1;
+  a.g0 = g0;
+  a.sp = sp;
+  a.ld = (int)c->N;
+  a.act_id = act_id;
+  a.act = act;
+  a.pbar = c->pbar;
+  a.mbar = c->mbar;
+  a.gv = c->gv;
+  a.G = c->G;
+  a.gact = gact;
+  a.vbar = c->vbar;
+  a.err = c->d_err;
+  a.tiles = tile_info(c);
+  a.det = c->det;
+  const bool det_s = c->det && gact != nullptr && c->n_act > 0;
+  if (det_s) {
+    a.gact = nullptr;
+    a.sb_part = c->sb_part;
+  }
+  {
+    ProfScope ps(c, MPM_K_ADJ_FUSED);
+    RC(launch_adj_gather_scatter(c->dim, a, c->n_tiles_ne, c->stream));
+  }
+  if (det_s)
+    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, c->d_tile_start,
+                          act_id, c->sb_part, c->dim, gact, c->stream));
+  return MPM_OK;
 }
 
 int ensure_gact(mpm_ctx *c, int64_t n) {
@@ -509,6 +607,8 @@ int bin_particles(mpm_ctx *c, const float *x) {
   hipStream_t s = c->stream;
   RC(launch_fill_i32(c->d_cell_cnt, (int64_t)c->n_tiles * cpt, s));
   RC(launch_fill_i32(c->d_tile_cnt, c->n_tiles, s));
+  // node tiles flagged by particles beyond their box's slack, for this tape
+  if (c->use_nt) RC(launch_fill_i32(c->d_nt_dirty, c->n_nt, s));
   SortArgs a;
   a.scenes = c->d_scenes;
   a.pscene = c->d_pscene;
@@ -526,6 +626,14 @@ int bin_particles(mpm_ctx *c, const float *x) {
   // an invalid particle gets no slot in the permutation: stop here (before
   // any kernel reads the permutation) when counting found one
   RC(read_err(c));  // synchronises
+  if (c->det) {
+    // ranks in a cell by particle index instead of atomic arrival
+    const int64_t ncell = (int64_t)c->n_tiles * cpt;
+    RC(launch_scan_i32(c->d_cell_cnt, c->d_cell_start, (int)ncell, s));
+    RC(launch_cell_fill(c->d_ptile, c->d_pcell, c->d_prank, c->d_cell_start, cpt,
+                        (int)c->N, c->d_cell_list, s));
+    RC(launch_cell_sort(c->d_cell_start, (int)ncell, c->d_cell_list, c->d_prank, s));
+  }
   RC(launch_scan_i32(c->d_tile_cnt, c->d_tile_start, c->n_tiles, s));
   RC(launch_sort_place(c->dim, a, c->d_tile_start, c->d_perm, s));
   RC(launch_chunk_count(c->d_tile_cnt, c->n_tiles, c->d_nch, s));
@@ -762,9 +870,9 @@ int fwd_substep(mpm_ctx *c, int n, const State &in, const State &out) {
   const Chunk *chunks = cur_chunks(c, &nch);
   const bool tiles = c->tape.sorted;
   const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
-  RC(fwd_p2g(c, tiles, chunks, nch, cs(in), cur_act_id(c), act, c->gm, c->gp));
+  RC(fwd_p2g(c, tiles, chunks, nch, cs(in), cur_act_id(c), act, c->gm, c->gp, n));
   RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
-  return fwd_g2p(c, chunks, nch, cs(in), out, c->gv);
+  return fwd_g2p(c, chunks, nch, cs(in), out, c->gv, nullptr, nullptr, nullptr, false, n);
 }
 
 int ctl_forward(mpm_ctx *c, const State &s, int n, int g2p_rows = 0);
@@ -822,11 +930,11 @@ struct RevolveRun {
     const State s = state_at(c, sbuf);
     const float *act = c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
     float *g = slot_grid(c, 0);
-    RC(fwd_p2g(c, tiles, chunks, nch, cs(s), cur_act_id(c), act, c->gm, c->gp));
+    RC(fwd_p2g(c, tiles, chunks, nch, cs(s), cur_act_id(c), act, c->gm, c->gp, n));
     RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
     double *ga = nga ? c->gact + (int64_t)n * c->n_act : nullptr;
     RC(bwd_step(c, tiles, chunks, nch, cs(s), cur_act_id(c), act, g, g + c->G,
-                cs(A1), A0, ga));
+                cs(A1), A0, ga, n));
     if (c->ctl.on) RC(ctl_adjoint(c, n, ga, A0));
     std::swap(A0, A1);
     return MPM_OK;
@@ -918,7 +1026,10 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   // substep's P2G (state n+1 goes from registers to the scatter)
   // (not with a closed-loop controller: the actuation of substep n+1 needs
   // the component means of state n+1 first)
-  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on;
+  // (not in deterministic mode: there G2P is the same kernel as the
+  // reverse pass's recompute)
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on &&
+                    c->fuse_forward && !c->det;
   auto act_of = [&](int n) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };
@@ -929,18 +1040,29 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
     // produced it (substep 0: their own kernel)
     if (c->ctl.on) RC(ctl_forward(c, s, n, n > 0 ? nch : 0));
     if (!fuse || n == 0)
-      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp));
+      RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp, n));
     if (c->tape.grids_all) {
       float *g = slot_grid(c, n);  // keep this substep's grid on the tape
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
     } else {
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
-    if (fuse && n + 1 < L.T)
-      RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1)));
-    else
+    if (fuse && n + 1 < L.T) {
+      // state n+1 is read back only through x and F unless the tape keeps
+      // it (memo, or a checkpoint)
+      RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1),
+                     L.memo || (n + 1) % L.k == 0, n));
+    } else if (c->det && c->tape.grids_all) {
+      // deterministic mode: the velocities are rebuilt from the stored
+      // (m, p) exactly as the reverse pass's recompute does, so a
+      // checkpointed reverse pass sees the forward pass's states bit for bit
+      const float *g = slot_grid(c, n);
+      RC(fwd_g2p(c, chunks, nch, cs(s), o, nullptr, g, g + c->G, nullptr,
+                 c->ctl.on && n + 1 < L.T, n));
+    } else {
       RC(fwd_g2p(c, chunks, nch, cs(s), o, c->gv, nullptr, nullptr, nullptr,
-                 c->ctl.on && n + 1 < L.T));
+                 c->ctl.on && n + 1 < L.T, n));
+    }
   }
   return MPM_OK;
 }
@@ -973,9 +1095,15 @@ int rollout_backward_core(mpm_ctx *c) {
     RevolveRun r{c, A0, A1, nga > 0 ? 1 : 0};
     return t.T > 0 ? r.run(0, t.T, t.rev, 0, t.rev_spine != 0) : MPM_OK;
   }
-  const int nseg = t.memo ? t.T : (t.T + t.k - 1) / t.k;
-  const int seglen = t.memo ? 1 : t.k;
+  // (a memo tape is one segment whose states are all stored)
+  const int nseg = t.memo ? (t.T > 0 ? 1 : 0) : (t.T + t.k - 1) / t.k;
+  const int seglen = t.memo ? t.T : t.k;
   const bool keep = !t.memo && t.grids_all;  // stored grids: G2P-only recompute
+  // 3D binned reverse passes fuse each gather with the previous substep's
+  // scatter (not with a closed-loop controller, whose adjoint adds to the
+  // state adjoint between the two, nor with a per-particle material field)
+  const bool fuse = tiles && c->scatter_mode == 3 && c->dim == 3 && !c->ctl.on &&
+                    !c->has_mat && c->fuse_reverse;
   // state n of segment j (segment states alternate between two banks when
   // the grids are kept, so one segment can be recomputed while the adjoint
   // of the next one runs)
@@ -996,7 +1124,7 @@ int rollout_backward_core(mpm_ctx *c) {
     for (int n = n0; n + 1 < n1; ++n) {
       const float *g = Gr(n0, n);
       RC(fwd_g2p(c, chunks, nch, cs(state_at(c, S(j, n))), state_at(c, S(j, n + 1)),
-                 nullptr, g, g + c->G, st));
+                 nullptr, g, g + c->G, st, false, n));
     }
     return MPM_OK;
   };
@@ -1034,21 +1162,46 @@ int rollout_backward_core(mpm_ctx *c) {
         const State s = state_at(c, S(j, n));
         const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
         float *g = Gr(n0, n);
-        RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp));
+        RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act, c->gm, c->gp, n));
         RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1, g, g + c->G));
         if (n + 1 < n1)
-          RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(j, n + 1)), c->gv));
+          RC(fwd_g2p(c, chunks, nch, cs(s), state_at(c, S(j, n + 1)), c->gv, nullptr,
+                     nullptr, nullptr, false, n));
       }
     }
-    for (int n = n1 - 1; n >= n0; --n) {
-      const State s = state_at(c, S(j, n));
-      const float *act = c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
-      const float *g = Gr(n0, n);
-      RC(bwd_step(c, tiles, chunks, nch, cs(s), ids, act, g, g + c->G, cs(A1),
-                  A0, nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr));
-      // a^n = tanh(W z(S^n) + b): its dependence on state n
-      if (c->ctl.on) RC(ctl_adjoint(c, n, c->gact + (int64_t)n * c->n_act, A0));
+    auto act_of = [&](int n) {
+      return c->n_act ? t.act + (int64_t)n * c->n_act : nullptr;
+    };
+    auto gact_of = [&](int n) {
+      return nga > 0 ? c->gact + (int64_t)n * c->n_act : nullptr;
+    };
+    if (fuse && n1 - n0 >= 2) {
+      // scatter and grid reverse of the segment's last substep, then per
+      // substep the gather fused with the previous substep's scatter, then
+      // the first substep's gather
+      const float *g = Gr(n0, n1 - 1);
+      RC(bwd_scatter(c, tiles, chunks, nch, cs(state_at(c, S(j, n1 - 1))), cs(A1), n1 - 1));
+      RC(bwd_grid(c, tiles, g, g + c->G));
+      for (int n = n1 - 1; n > n0; --n) {
+        RC(bwd_gather_scatter(c, cs(state_at(c, S(j, n))), cs(state_at(c, S(j, n - 1))),
+                              ids, act_of(n), cs(A1), A0, gact_of(n), n));
+        std::swap(A0, A1);
+        const float *gp = Gr(n0, n - 1);
+        RC(bwd_grid(c, tiles, gp, gp + c->G));
+      }
+      RC(bwd_gather(c, tiles, chunks, nch, cs(state_at(c, S(j, n0))), ids, act_of(n0),
+                    cs(A1), A0, gact_of(n0), n0));
       std::swap(A0, A1);
+    } else {
+      for (int n = n1 - 1; n >= n0; --n) {
+        const State s = state_at(c, S(j, n));
+        const float *g = Gr(n0, n);
+        RC(bwd_step(c, tiles, chunks, nch, cs(s), ids, act_of(n), g, g + c->G, cs(A1),
+                    A0, gact_of(n), n));
+        // a^n = tanh(W z(S^n) + b): its dependence on state n
+        if (c->ctl.on) RC(ctl_adjoint(c, n, c->gact + (int64_t)n * c->n_act, A0));
+        std::swap(A0, A1);
+      }
     }
     if (overlap) RC(hip_ok(hipEventRecord(c->ev_adj, c->stream)));
   }
@@ -1145,6 +1298,12 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_tile_flag, c->stream);
   dfree(c->d_tile_pos, c->stream);
   dfree(c->d_tile_list, c->stream);
+  dfree(c->d_nt_scene, c->stream);
+  dfree(c->d_nt_dirty, c->stream);
+  dfree(c->d_cell_start, c->stream);
+  dfree(c->d_cell_list, c->stream);
+  dfree(c->sb_part, c->stream);
+  dfree(c->d_act_scene, c->stream);
   dfree(c->tape.states, c->stream);
   dfree(c->tape.grids, c->stream);
   dfree(c->tape.act, c->stream);
@@ -1172,9 +1331,18 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int scatter = 0;
   int recompute_grids = 0;
   int graphs = 0;
+  int fusion = 0;
+  int det = 0;
+  int persistent = 0;
   if (opts) {
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
       if (opts->reserved[k]) return MPM_ERR_ARG;
+    if (opts->persistent != 0 && opts->persistent != 1) return MPM_ERR_ARG;
+    persistent = opts->persistent;
+    if (opts->fusion < 0 || opts->fusion > 2) return MPM_ERR_ARG;
+    fusion = opts->fusion;
+    if (opts->deterministic != 0 && opts->deterministic != 1) return MPM_ERR_ARG;
+    det = opts->deterministic;
     if (opts->graphs != 0 && opts->graphs != 1) return MPM_ERR_ARG;
     graphs = opts->graphs;
     if (opts->recompute_grids != 0 && opts->recompute_grids != 1) return MPM_ERR_ARG;
@@ -1213,6 +1381,9 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   c->sort = sort;
   c->keep_grids = !recompute_grids;
   c->use_graphs = graphs;
+  c->persistent = persistent;
+  c->fuse_forward = fusion != 1;
+  c->fuse_reverse = fusion == 2;
   {
     const int cells = dim == 2 ? tile * tile : tile * tile * tile;
     if ((scatter == 2 || scatter == 3) && cells != 64) {
@@ -1220,13 +1391,20 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
       return MPM_ERR_ARG;
     }
     c->scatter_mode = scatter == 0 ? (cells == 64 ? 3 : 1) : scatter;
+    // deterministic sums need the binned, sorted scatter
+    if (det && (!sort || c->scatter_mode != 3)) {
+      delete c;
+      return MPM_ERR_ARG;
+    }
+    c->det = det;
   }
   c->stream = (hipStream_t)stream;
   c->n_tiles = (int)n_tiles;
 
   std::vector<Chunk> chunks;
   std::vector<GridBlock> gblocks;
-  std::vector<int> pscene(N), tile_scene;
+  std::vector<int> pscene(N), tile_scene, nt_scene;
+  int64_t ntoff = 0;
   c->h_act_id.assign(N, -1);
   int64_t poff = 0, goff = 0, toff = 0;
   int aoff = 0;
@@ -1237,6 +1415,12 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
     d.g_off = (int)goff;
     d.act_off = aoff;
     d.tile_off = (int)toff;
+    d.nt_off = (int)ntoff;
+    {
+      const int64_t nnts = dim == 2 ? (int64_t)d.nnt * d.nnt : (int64_t)d.nnt * d.nnt * d.nnt;
+      for (int64_t k = 0; k < nnts; ++k) nt_scene.push_back(s);
+      ntoff += nnts;
+    }
     c->h_scenes.push_back(d);
     for (int64_t k = 0; k < S.n_particles; k += CH) {
       Chunk ch{s, (int)(poff + k), (int)std::min<int64_t>(CH, S.n_particles - k), 0};
@@ -1308,6 +1492,18 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   TRY(dmalloc(&c->d_tile_flag, n_tiles, c->stream));
   TRY(dmalloc(&c->d_tile_pos, n_tiles + 1, c->stream));
   TRY(dmalloc(&c->d_tile_list, n_tiles, c->stream));
+  c->n_nt = (int)ntoff;
+  c->use_nt = c->scatter_mode == 3 && c->n_nt > 0;
+  if (c->use_nt) {
+    TRY(dmalloc(&c->d_nt_scene, c->n_nt, c->stream));
+    TRY(dmalloc(&c->d_nt_dirty, c->n_nt, c->stream));
+  }
+  if (c->det) {
+    TRY(dmalloc(&c->d_cell_start, n_tiles * cpt + 1, c->stream));
+    TRY(dmalloc(&c->d_cell_list, std::max<int64_t>(N, 1), c->stream));
+    TRY(dmalloc(&c->sb_part, std::max<int64_t>(N, 1), c->stream));
+    if (n_act > 0) TRY(dmalloc(&c->d_act_scene, n_act, c->stream));
+  }
   {
     const int64_t S = tile + 4;
     TRY(dmalloc(&c->d_part, n_tiles * (dim + 1) * (dim == 2 ? S * S : S * S * S), c->stream));
@@ -1329,6 +1525,18 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   }
   TRY(hip_ok(hipMemcpyAsync(c->d_tile_scene, tile_scene.data(),
                             sizeof(int) * tile_scene.size(), hipMemcpyHostToDevice, s)));
+  if (c->use_nt) {
+    TRY(hip_ok(hipMemcpyAsync(c->d_nt_scene, nt_scene.data(), sizeof(int) * c->n_nt,
+                              hipMemcpyHostToDevice, s)));
+    TRY(launch_fill_i32(c->d_nt_dirty, c->n_nt, s));
+  }
+  std::vector<int> act_scene;
+  if (c->det && n_act > 0) {
+    for (int sc_i = 0; sc_i < n_scenes; ++sc_i)
+      for (int j = 0; j < scenes[sc_i].n_act; ++j) act_scene.push_back(sc_i);
+    TRY(hip_ok(hipMemcpyAsync(c->d_act_scene, act_scene.data(), sizeof(int) * n_act,
+                              hipMemcpyHostToDevice, s)));
+  }
   TRY(launch_fill_f32(c->gm, G, s));
   TRY(launch_fill_f32(c->gp, dim * G, s));
   TRY(launch_fill_f32(c->gv, dim * G, s));
@@ -1551,6 +1759,21 @@ int mpm_step_backward(mpm_ctx *c, const mpm_state *s_n, const float *act_n,
   return MPM_OK;
 }
 
+int mpm_set_horizons(mpm_ctx *c, const int32_t *t_end) {
+  RC(check_ctx(c));
+  if (t_end)
+    for (int s = 0; s < c->n_scenes; ++s)
+      if (t_end[s] < 0) return MPM_ERR_ARG;
+  ++c->tape_gen;
+  c->tape.valid = 0;  // a tape recorded under other horizons is not reversed
+  for (int s = 0; s < c->n_scenes; ++s) c->h_scenes[s].t_end = t_end ? t_end[s] : INT32_MAX;
+  c->horizons = false;
+  for (int s = 0; s < c->n_scenes; ++s) c->horizons = c->horizons || c->h_scenes[s].t_end != INT32_MAX;
+  return hip_ok(hipMemcpyAsync(c->d_scenes, c->h_scenes.data(),
+                               sizeof(DevScene) * c->n_scenes, hipMemcpyHostToDevice,
+                               c->stream));
+}
+
 int mpm_set_materials(mpm_ctx *c, const float *E_p, const float *rho_p) {
   RC(check_ctx(c));
   ++c->tape_gen;
@@ -1746,7 +1969,7 @@ int mpm_rollout_ctrl(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
     return MPM_ERR_ARG;
   if (c->n_scenes != 1 || c->N < 1 || c->n_act < 1 || c->n_act > CTL_MAX_ACT ||
       ctl->n_comp < 1 || 2 * c->dim * ctl->n_comp > CTL_MAX_ZS || !ctl->comp_id ||
-      !ctl->W || !ctl->b || !ctl->target)
+      !ctl->W || !ctl->b || !ctl->target || c->horizons)
     return MPM_ERR_ARG;
   RC(rollout_run(c, T, ckpt_k, s0, nullptr, ctl, sT));
   if (act && T > 0)

@@ -37,6 +37,9 @@ struct DevScene {
   float dt, dx, inv_dx, Dinv;  // Dinv = 4 / dx^2
   float mu, la, mp, V0;        // Lame parameters, particle mass and volume
   float kG;                    // -Dinv * dt * V0 (stress part of G_p)
+  int nnt;      // node tiles per axis (binning; node tile t: nodes tB-1 .. tB+B-2)
+  int nt_off;   // first node tile of the scene
+  int t_end;    // the scene is held fixed from substep t_end on (its horizon)
   float g[3];                  // gravity
   float axis[3];               // actuation axis
 };
@@ -82,6 +85,8 @@ struct TileInfo {
   float *part;       // partial boxes [n_tiles][d+1][S^d]
   int B;             // cells per tile edge
   const int *list;   // non-null: workgroup b handles tile list[b] (non-empty tiles)
+  int *nt_dirty;     // non-null: node tiles that particles beyond their box's slack
+                     // reached with global atomics (set to 1, per rollout)
 };
 
 struct P2GArgs {
@@ -97,6 +102,8 @@ struct P2GArgs {
   unsigned *err;
   TileInfo tiles;     // tile path only
   const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
+  int det = 0;       // deterministic sums (fixed order of a cell's records)
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
 };
 
 struct GridArgs {
@@ -110,6 +117,11 @@ struct GridArgs {
   const float *part;
   int B;
   float *out_m, *out_p;  // non-null: store the summed m and p here (may be gm/gp)
+  // node-tile launch (binned rollouts, 64-cell tiles): one wave per node
+  // tile, nt_scene: scene of each node tile, nt_dirty: see TileInfo
+  const int *nt_scene = nullptr;
+  const int *nt_dirty = nullptr;
+  int n_nt = 0;  int persist = 0;  // persistent launch: a few workgroups loop over the node tiles
 };
 
 struct G2PArgs {
@@ -128,6 +140,7 @@ struct G2PArgs {
   const int *ctl_comp = nullptr;
   float *ctl_partial = nullptr;
   int ctl_nzs = 0, ctl_rows = 0;
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
 };
 
 // G2P of substep n fused with the binned P2G of substep n+1 (3D rollouts):
@@ -136,8 +149,9 @@ struct G2PArgs {
 struct G2P2GArgs {
   const DevScene *scenes;
   CState s;           // state n (x, F read)
-  State out;          // state n+1 (x, v, C, F written); must not alias s
+  State out;          // state n+1 (x, F written; v, C too when write_vc); must not alias s
   int ld;
+  int write_vc;       // state n+1 is kept on the tape: write v and C too
   const float *gv;    // grid velocity of substep n
   const int *act_id;  // scene-local actuator of each particle (-1 passive)
   const float *act;   // [n_act_tot] of substep n+1
@@ -146,6 +160,8 @@ struct G2P2GArgs {
   unsigned *err;
   TileInfo tiles;
   const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
+  int det = 0;       // deterministic sums (fixed order of a cell's records)
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
 };
 
 struct AdjScatterArgs {
@@ -159,6 +175,8 @@ struct AdjScatterArgs {
   int64_t G;
   unsigned *err;
   TileInfo tiles;  // tile path only
+  int det = 0;       // deterministic sums (fixed order of a cell's records)
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
 };
 
 struct AdjGridArgs {
@@ -172,6 +190,9 @@ struct AdjGridArgs {
   const int *tile_cnt;  // non-null: add the tile boxes in `part` to vbar
   const float *part;
   int B;
+  const int *nt_scene = nullptr;  // node-tile launch (see GridArgs)
+  const int *nt_dirty = nullptr;
+  int n_nt = 0;  int persist = 0;  // persistent launch: a few workgroups loop over the node tiles
 };
 
 struct AdjGatherArgs {
@@ -190,6 +211,33 @@ struct AdjGatherArgs {
   unsigned *err;
   const float *mat = nullptr;  // per-particle (mu, la, m_p) [3][ld] or null
   float *gmat = nullptr;       // += dL/dmu, dL/dla, dL/dm_p [3][ld] (with mat)
+  float *sb_part = nullptr;  // non-null: dL/ds of each particle here (not gact)
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
+};
+
+// The reverse of substep n's gather fused with the adjoint scatter of
+// substep n-1 (3D rollouts): reads state n, the adjoint of state n+1, x and
+// F of state n-1 and the adjoint grid of substep n (pbar, mbar, gv); writes
+// the adjoint of state n and scatters substep n-1's adjoint into the tile
+// boxes (and the overflow grid vbar).
+struct AdjFusedArgs {
+  const DevScene *scenes;
+  CState s;          // state n
+  CState g1;         // adjoint of state n+1
+  State g0;          // adjoint of state n (must not alias g1)
+  CState sp;         // state n-1 (x, F read)
+  int ld;
+  const int *act_id;
+  const float *act;  // [n_act_tot] of substep n
+  const float *pbar, *mbar, *gv;  // adjoint grid of substep n
+  int64_t G;
+  double *gact;      // [n_act_tot] accumulated dL/ds^n (nullable)
+  float *vbar;       // overflow adjoint grid of substep n-1
+  unsigned *err;
+  TileInfo tiles;
+  int det = 0;       // deterministic sums (fixed order of a cell's records)
+  float *sb_part = nullptr;  // non-null: dL/ds of each particle here (not gact)
+  int n = 0;         // substep index (scenes past their horizon are held fixed)
 };
 
 struct SortArgs {
@@ -226,11 +274,31 @@ int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_blocks,
 // Tile edges (cells) with compiled kernels for each dimension.
 bool tile_supported(int dim, int B);
 int launch_grid(int dim, const GridArgs &a, hipStream_t st);
+// Node-tile variants of the grid kernels (binned rollouts with 64-cell
+// tiles): every node of node tile t is covered by the boxes of tiles t-1
+// and t per axis only, so a wave takes the 64 nodes of one node tile, reads
+// the candidates' counts once and skips empty boxes (and node tiles with no
+// particle nearby) as a whole.
+int launch_grid_nt(int dim, const GridArgs &a, hipStream_t st);
+int launch_adj_grid_nt(int dim, const AdjGridArgs &a, hipStream_t st);
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st);
 int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_blocks, hipStream_t st);
 int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st);
 int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st);
 int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st);
+int launch_adj_gather_scatter(int dim, const AdjFusedArgs &a, int n_blocks, hipStream_t st);
+// Deterministic mode: per-actuator sums of a substep's per-particle dL/ds
+// (tape order) into gact [n_act]; act_scene: scene of each actuator.
+int launch_sbar_reduce(const DevScene *scenes, const int *act_scene, int n_act,
+                       const int *tile_start, const int *act_id, const float *sb_part,
+                       int dim, double *gact, hipStream_t st);
+// Deterministic ranks at binning: the particles of each cell listed by
+// atomic rank (cell_start: exclusive scan of the cell counts), then each
+// cell's list sorted by particle index, which becomes the rank.
+int launch_cell_fill(const int *ptile, const int *pcell, const int *prank,
+                     const int *cell_start, int cpt, int N, int *list, hipStream_t st);
+int launch_cell_sort(const int *cell_start, int n_cells, int *list, int *prank,
+                     hipStream_t st);
 
 int launch_mat_field(const DevScene *scenes, const int *pscene, int N,
                      const float *E_p, const float *rho_p, float *mat, hipStream_t st);

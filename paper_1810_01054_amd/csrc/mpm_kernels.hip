@@ -21,6 +21,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "mpm_internal.h"
 
 namespace mpm {
@@ -342,6 +344,25 @@ __device__ __forceinline__ int xcd_block_id() {
   return x * q + min(x, r) + k;
 }
 
+// The work items of this workgroup: item xcd_block_id() of a launch with
+// one workgroup per item, or (persistent launch with min(n_items, 8) or more
+// workgroups, fewer than items) every item of its XCD's contiguous share of
+// the items, at a stride of the number of workgroups on that XCD.  No
+// barrier may depend on the count.
+template <typename F>
+__device__ __forceinline__ void for_items(int n_items, bool persistent, F &&f) {
+  if (!persistent) {
+    f(xcd_block_id());
+    return;
+  }
+  constexpr int NX = 8;
+  const int nb = gridDim.x, b = blockIdx.x, x = b % NX, k = b / NX;
+  const int nbx = nb / NX + (x < nb % NX ? 1 : 0);
+  const int q = n_items / NX, r = n_items % NX;
+  const int lo = x * q + min(x, r), hi = lo + q + (x < r ? 1 : 0);
+  for (int i = lo + k; i < hi; i += nbx) f(i);
+}
+
 // ---------------------------------------------------------------------------
 // step 1: P2G scatter
 // ---------------------------------------------------------------------------
@@ -426,6 +447,7 @@ __device__ __forceinline__ bool p2g_particle(const P2GArgs &A,
                                              float (&w)[D][3], float *c0,
                                              float (&Gdx)[D][D],
                                              unsigned &eb) {
+  if (A.n >= sc.t_end) return false;  // past the scene's horizon: held fixed
   float F[D * D], C[D * D], v[D];
   load_mat<D>(A.s.F, A.ld, p, F);
   load_mat<D>(A.s.C, A.ld, p, C);
@@ -444,6 +466,7 @@ __device__ __forceinline__ bool p2g_particle_m(const P2GArgs &A,
                                                float (&w)[D][3], float *c0,
                                                float (&Gdx)[D][D], float &mpp,
                                                unsigned &eb) {
+  if (A.n >= sc.t_end) return false;  // past the scene's horizon: held fixed
   float F[D * D], C[D * D], v[D];
   load_mat<D>(A.s.F, A.ld, p, F);
   load_mat<D>(A.s.C, A.ld, p, C);
@@ -488,15 +511,17 @@ __device__ __forceinline__ void adj_scatter_particle(const AdjScatterArgs &A,
   for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
   // (C): vt + (4/dx^2) Ct (x_i - x_p), x_i - x_p = (o - f) dx
   const float cs = sc.Dinv * sc.dx;
+  // past the scene's horizon the substep is the identity: nothing to add
+  const float on = A.n >= sc.t_end ? 0.0f : 1.0f;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     float s = vt[a];
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-      Cdx[a][b] = cs * Ct[a * D + b];
+      Cdx[a][b] = on * (cs * Ct[a * D + b]);
       s -= Cdx[a][b] * f[b];
     }
-    c0[a] = s;
+    c0[a] = on * s;
   }
 }
 
@@ -815,9 +840,12 @@ struct SortedCell {
 };
 
 // PM: records carry the particle's mass (per-particle materials).
-template <int D, int NCH, int PER, bool V4, bool PM = false>
+// DET: deterministic ranks; mask holds, per box cell, one bit per particle
+// of the batch (PER * 256 bits).
+template <int D, int NCH, int PER, bool V4, bool PM = false, bool DET = false>
 struct SortedCellSmem {
   static constexpr int SV = SortedCell<D>::SV;
+  static constexpr int MW = PER * 8;  // mask words per cell
   float box[V4 ? 4 * SV : NCH * SV];
   float rec[(SortedCell<D>::REC + (PM ? 1 : 0)) * PER * 256];  // field-major, swizzled slots
   int cnt[256];
@@ -825,7 +853,32 @@ struct SortedCellSmem {
   short order[256];  // the tile's own cells, then the occupied ring cells
   int wsum[4];
   int nring;
+  unsigned mask[DET ? SortedCell<D>::NBC * MW : 1];
 };
+
+// Deterministic ranks in a cell (DET scatters): each particle of a batch
+// sets its bit (batch index jl) in its cell's mask; the count of a cell is
+// its number of set bits and a particle's rank the number of set bits below
+// its own, so a cell's records are ordered by batch index whatever order the
+// threads ran in.
+template <int MW>
+__device__ __forceinline__ void det_mark(unsigned *mask, int lc, int jl) {
+  atomicOr(&mask[lc * MW + (jl >> 5)], 1u << (jl & 31));
+}
+template <int MW>
+__device__ __forceinline__ int det_count(const unsigned *mask, int c) {
+  int n = 0;
+#pragma unroll
+  for (int w = 0; w < MW; ++w) n += __popc(mask[c * MW + w]);
+  return n;
+}
+template <int MW>
+__device__ __forceinline__ int det_rank(const unsigned *mask, int lc, int jl) {
+  const unsigned *m = mask + lc * MW;
+  int r = 0;
+  for (int w = 0; w < (jl >> 5); ++w) r += __popc(m[w]);
+  return r + __popc(m[jl >> 5] & ((1u << (jl & 31)) - 1u));
+}
 
 // Exclusive scan of cnt[0..256) into off (256 threads).
 __device__ __forceinline__ void block_scan_256(const int *cnt, int *off,
@@ -944,11 +997,41 @@ __device__ __forceinline__ void offsets_flush(float *box, int lcell,
 
 // PM: the part callback also returns the particle's mass, which the
 // records carry (per-particle materials); otherwise the scene's mass.
+// With a `cell(p, base, eb)` callback (split mode) the ranks come first from
+// the particles' stencil bases alone, and part() runs after the cell scan
+// and writes each record straight to its sorted slot, so no record is held
+// in registers across the batch (part() is then called for every particle
+// of the tile, also when it has no record).
+// Node tiles reached by a particle that adds to the grid with global atomics
+// (stencil base `base`, nodes base .. base+2 per axis): flagged so that the
+// node-tile grid kernels also visit them.
+template <int D>
+__device__ __forceinline__ void mark_dirty(const TileInfo &T, const DevScene &sc,
+                                           const int *base) {
+  if (!T.nt_dirty) return;
+  int lo[D], hi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    lo[a] = (base[a] + 1) / T.B;
+    hi[a] = (base[a] + 3) / T.B;
+  }
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k) {
+    int idx = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) idx = idx * sc.nnt + (((k >> (D - 1 - a)) & 1) ? hi[a] : lo[a]);
+    T.nt_dirty[sc.nt_off + idx] = 1;
+  }
+}
+
+struct NoCell {};
 template <int D, int NCH, bool HAS_MASS, int PER, bool V4, bool PM = false,
-          typename Args, typename Part>
+          bool DET = false, typename Args, typename Part, typename Cell = NoCell>
 __device__ __forceinline__ void sorted_cell_scatter(
-    const Args &A, int tile, SortedCellSmem<D, NCH, PER, V4, PM> &sm, float *gm,
-    float *gp, Part &&part) {
+    const Args &A, int tile, SortedCellSmem<D, NCH, PER, V4, PM, DET> &sm, float *gm,
+    float *gp, Part &&part, Cell &&cell = Cell{}) {
+  constexpr int MW = SortedCellSmem<D, NCH, PER, V4, PM, DET>::MW;
+  constexpr bool SPLIT = !std::is_same<std::decay_t<Cell>, NoCell>::value;
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, NBC = SC::NBC,
                 NIN = SC::NIN, REC = SC::REC, B = SC::B, NQ = SC::NQ;
@@ -964,6 +1047,8 @@ __device__ __forceinline__ void sorted_cell_scatter(
   const int start = A.tiles.start[tile];
   for (int i = t; i < BOXF; i += 256) sm.box[i] = 0.0f;
   sm.cnt[t] = 0;
+  if constexpr (DET)
+    for (int i = t; i < NBC * MW; i += 256) sm.mask[i] = 0u;
   // is box cell t one of the tile's own cells (1..B on every axis)?
   bool own = t < NBC;
   {
@@ -989,9 +1074,32 @@ __device__ __forceinline__ void sorted_cell_scatter(
   for (int b0 = 0; b0 < cnt; b0 += PER * 256) {
     // 1. records, cells and ranks of up to PER particles per thread
     int lc[PER], rank[PER];
-    float rec[PER][RECP];
+    float rec[SPLIT ? 1 : PER][RECP];
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int h = 0; h < PER; ++h) {
+      for (int h = 0; h < PER; ++h) {
+        lc[h] = -1;
+        rank[h] = 0;
+        const int j = b0 + h * 256 + t;
+        int base[D];
+        if (j < cnt && cell(start + j, base, eb)) {
+          int l[D];
+          bool inbox = true;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            l[a] = base[a] - org[a];
+            inbox = inbox && l[a] >= 0 && l[a] < BC;
+          }
+          if (inbox) {
+            lc[h] = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
+            if constexpr (DET) det_mark<MW>(sm.mask, lc[h], h * 256 + t);
+            else rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < (SPLIT ? 0 : PER); ++h) {
       lc[h] = -1;
       rank[h] = 0;
       const int j = b0 + h * 256 + t;
@@ -1021,7 +1129,8 @@ __device__ __forceinline__ void sorted_cell_scatter(
           for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
         }
         if constexpr (PM) rec[h][REC] = mpp;
-        rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
+        if constexpr (DET) det_mark<MW>(sm.mask, lc[h], h * 256 + t);
+        else rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
       } else {
         const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
         scatter_stencil<D, HAS_MASS>(w, mpp, c0, L,
@@ -1029,9 +1138,17 @@ __device__ __forceinline__ void sorted_cell_scatter(
           add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
                                           stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
         });
+        mark_dirty<D>(A.tiles, sc, base);
       }
     }
     __syncthreads();
+    if constexpr (DET) {
+      if (t < NBC) sm.cnt[t] = det_count<MW>(sm.mask, t);
+#pragma unroll
+      for (int h = 0; h < PER; ++h)
+        if (lc[h] >= 0) rank[h] = det_rank<MW>(sm.mask, lc[h], h * 256 + t);
+      __syncthreads();
+    }
     // 2. cell ranges; records to their sorted slots; the occupied ring
     //    cells (particles that drifted out of the tile) after the own cells
     block_scan_256(sm.cnt, sm.off, sm.wsum);
@@ -1046,12 +1163,47 @@ __device__ __forceinline__ void sorted_cell_scatter(
       if (ring) sm.order[NIN + before] = (short)t;
       if (t == 0) sm.nring = sm.wsum[0] + sm.wsum[1] + sm.wsum[2] + sm.wsum[3];
     }
+    if constexpr (SPLIT) {
+      // records after the scan: each goes straight to its sorted slot, or
+      // to the grid when its particle is outside the box's slack
+#pragma unroll 1
+      for (int h = 0; h < PER; ++h) {
+        const int j = b0 + h * 256 + t;
+        if (j >= cnt) continue;
+        int base[D];
+        float f[D], w[D][3], c0[D], L[D][D], mpp = sc.mp;
+        bool got;
+        if constexpr (PM) got = part(start + j, base, f, w, c0, L, mpp, eb);
+        else got = part(start + j, base, f, w, c0, L, eb);
+        if (!got) continue;
+        if (lc[h] >= 0) {
+          const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
 #pragma unroll
-    for (int h = 0; h < PER; ++h) {
-      if (lc[h] < 0) continue;
-      const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
+          for (int a = 0; a < D; ++a) {
+            sm.rec[a * NR + ps] = f[a];
+            sm.rec[(D + a) * NR + ps] = c0[a];
 #pragma unroll
-      for (int k = 0; k < RECP; ++k) sm.rec[k * NR + ps] = rec[h][k];
+            for (int b = 0; b < D; ++b) sm.rec[(2 * D + a * D + b) * NR + ps] = L[a][b];
+          }
+          if constexpr (PM) sm.rec[REC * NR + ps] = mpp;
+        } else {
+          const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+          scatter_stencil<D, HAS_MASS>(w, mpp, c0, L,
+                                       [&](int o0, int o1, int o2, const float *val) {
+            add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
+                                            stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
+          });
+          mark_dirty<D>(A.tiles, sc, base);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < PER; ++h) {
+        if (lc[h] < 0) continue;
+        const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
+#pragma unroll
+        for (int k = 0; k < RECP; ++k) sm.rec[k * NR + ps] = rec[h][k];
+      }
     }
     __syncthreads();
     // 3. per-cell sums of this wave's offsets, then the waves' read-add-write
@@ -1095,6 +1247,8 @@ __device__ __forceinline__ void sorted_cell_scatter(
       }
     }
     sm.cnt[t] = 0;
+    if constexpr (DET)
+      for (int i = t; i < NBC * MW; i += 256) sm.mask[i] = 0u;
     __syncthreads();
   }
   if (eb) atomicOr(A.err, eb);
@@ -1120,19 +1274,21 @@ __device__ __forceinline__ void sorted_cell_scatter(
 // keep two waves busy), and each wave adds its lanes' sums into its own LDS
 // box (read-add-write, the four chains run in parallel); the four boxes are
 // summed at the end.  On the 64-scene 2D batch this beats the offset split.
-template <int D, int NCH, bool PM = false>
+template <int D, int NCH, bool PM = false, bool DET = false>
 struct WaveBoxSmem {
+  static constexpr int MW = 16;  // mask words per cell (batches of 512)
   float box[4][NCH * SortedCell<D>::SV];
   float rec[512 * (SortedCell<D>::REC + (PM ? 1 : 0))];
   int cnt[256];
   int off[256];
   int wsum[4];
+  unsigned mask[DET ? SortedCell<D>::NBC * MW : 1];
 };
 
-template <int D, int NCH, bool HAS_MASS, bool PM = false, typename Args,
-          typename Part>
+template <int D, int NCH, bool HAS_MASS, bool PM = false, bool DET = false,
+          typename Args, typename Part>
 __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
-                                                       WaveBoxSmem<D, NCH, PM> &sm,
+                                                       WaveBoxSmem<D, NCH, PM, DET> &sm,
                                                     float *gm, float *gp,
                                                     Part &&part) {
   using SC = SortedCell<D>;
@@ -1147,9 +1303,12 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
   tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
   const int cnt = A.tiles.cnt[tile];
   const int start = A.tiles.start[tile];
+  constexpr int MW = WaveBoxSmem<D, NCH, PM, DET>::MW;
   float *mybox = sm.box[wave];
   for (int i = t & 63; i < NCH * SV; i += 64) mybox[i] = 0.0f;
   sm.cnt[t] = 0;
+  if constexpr (DET)
+    for (int i = t; i < NBC * MW; i += 256) sm.mask[i] = 0u;
   int cc[D];  // this thread's box cell in phase 3 (t < NBC)
   {
     int l = t;
@@ -1200,7 +1359,8 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
           for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
         }
         if constexpr (PM) rec[h][REC - 1] = mpp;
-        rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
+        if constexpr (DET) det_mark<MW>(sm.mask, lc[h], h * 256 + t);
+        else rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
       } else {
         const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
         scatter_stencil<D, HAS_MASS>(w, mpp, c0, L,
@@ -1208,9 +1368,17 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
           add_global<D, HAS_MASS ? 1 : 0>(gm, gp, A.G,
                                           stencil_gindex<D>(gbase, sc.n, o0, o1, o2), val);
         });
+        mark_dirty<D>(A.tiles, sc, base);
       }
     }
     __syncthreads();
+    if constexpr (DET) {
+      if (t < NBC) sm.cnt[t] = det_count<MW>(sm.mask, t);
+#pragma unroll
+      for (int h = 0; h < PER; ++h)
+        if (lc[h] >= 0) rank[h] = det_rank<MW>(sm.mask, lc[h], h * 256 + t);
+      __syncthreads();
+    }
     // 2. cell ranges; records to their sorted slots
     block_scan_256(sm.cnt, sm.off, sm.wsum);
     __syncthreads();
@@ -1246,6 +1414,8 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
     }
     __syncthreads();
     sm.cnt[t] = 0;
+    if constexpr (DET)
+      for (int i = t; i < NBC * MW; i += 256) sm.mask[i] = 0u;
     __syncthreads();
   }
   if (eb) atomicOr(A.err, eb);
@@ -1279,13 +1449,13 @@ __device__ __forceinline__ void sorted_cell_scatter_wb(const Args &A, int tile,
 // and one set of read-add-write chains per tile); P2G keeps its four
 // channels node-major, the adjoint scatter's three channels are planes.
 // 2D: the per-wave-box variant above.
-template <int D>
+template <int D, bool DET>
 __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
   if constexpr (D == 2) {
-    __shared__ WaveBoxSmem<D, D + 1> sm;
+    __shared__ WaveBoxSmem<D, D + 1, false, DET> sm;
     sorted_cell_scatter_wb<D, D + 1, true>(
         A, tile, sm, A.gm, A.gp,
         [&](int p, const float *xp, const float *f, float (&w)[D][3],
@@ -1293,7 +1463,7 @@ __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
           return p2g_particle<D>(A, sc, p, xp, f, w, c0, L, eb);
         });
   } else {
-    __shared__ SortedCellSmem<D, D + 1, 2, true> sm;
+    __shared__ SortedCellSmem<D, D + 1, 2, true, false, DET> sm;
     sorted_cell_scatter<D, D + 1, true, 2, true>(
         A, tile, sm, A.gm, A.gp,
         [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
@@ -1308,13 +1478,13 @@ __global__ __launch_bounds__(256) void k_p2g_sorted(P2GArgs A) {
 
 // The same with per-particle materials: each record also carries the
 // particle's mass.
-template <int D>
+template <int D, bool DET>
 __global__ __launch_bounds__(256) void k_p2g_sorted_pm(P2GArgs A) {
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
   if constexpr (D == 2) {
-    __shared__ WaveBoxSmem<D, D + 1, true> sm;
+    __shared__ WaveBoxSmem<D, D + 1, true, DET> sm;
     sorted_cell_scatter_wb<D, D + 1, true, true>(
         A, tile, sm, A.gm, A.gp,
         [&](int p, const float *xp, const float *f, float (&w)[D][3],
@@ -1322,7 +1492,7 @@ __global__ __launch_bounds__(256) void k_p2g_sorted_pm(P2GArgs A) {
           return p2g_particle_m<D>(A, sc, p, xp, f, w, c0, L, mpp, eb);
         });
   } else {
-    __shared__ SortedCellSmem<D, D + 1, 2, true, true> sm;
+    __shared__ SortedCellSmem<D, D + 1, 2, true, true, DET> sm;
     sorted_cell_scatter<D, D + 1, true, 2, true, true>(
         A, tile, sm, A.gm, A.gp,
         [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
@@ -1335,13 +1505,13 @@ __global__ __launch_bounds__(256) void k_p2g_sorted_pm(P2GArgs A) {
   }
 }
 
-template <int D>
+template <int D, bool DET>
 __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
   if constexpr (D == 2) {
-    __shared__ WaveBoxSmem<D, D> sm;
+    __shared__ WaveBoxSmem<D, D, false, DET> sm;
     sorted_cell_scatter_wb<D, D, false>(
         A, tile, sm, nullptr, A.vbar,
         [&](int p, const float *, const float *f, float (&w)[D][3], float *c0,
@@ -1350,7 +1520,7 @@ __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
           return true;
         });
   } else {
-    __shared__ SortedCellSmem<D, D, 2, false> sm;
+    __shared__ SortedCellSmem<D, D, 2, false, false, DET> sm;
     sorted_cell_scatter<D, D, false, 2, false>(
         A, tile, sm, nullptr, A.vbar,
         [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
@@ -1366,17 +1536,18 @@ __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
 
 // G2P of substep n and the sorted P2G of substep n+1 in one pass over a
 // tile (3D): the tile's box of grid velocities is staged in LDS, each thread
-// gathers its particles (section III, G2P), writes state n+1, and hands the
-// new state straight to the scatter's record step (section III, P2G), so
-// state n+1 is not read back from HBM.  Particles whose stencil left the box
+// gathers its particles (section III, G2P), writes state n+1 (x and F only,
+// unless the tape keeps state n+1), and hands the new state straight to the
+// scatter's record step (section III, P2G), so state n+1 is not read back
+// from HBM.  Particles whose stencil left the box
 // gather from HBM.
 // PM: per-particle materials (the records carry each particle's mass).
-template <int D, bool PM>
+template <int D, bool PM, bool DET>
 __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
   static_assert(D == 3, "the fused pass is built for 3D tiles");
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, B = SC::B;
-  __shared__ SortedCellSmem<D, D + 1, 2, true, PM> sm;
+  __shared__ SortedCellSmem<D, D + 1, 2, true, PM, DET> sm;
   __shared__ float s_v[D * SV];
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
@@ -1392,10 +1563,26 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
     for (int a = 0; a < D; ++a) s_v[a * SV + i] = in ? A.gv[a * A.G + gi] : 0.0f;
   }
   // (the scatter synchronises before its record step reads s_v)
+  // past the scene's horizon (substep n >= t_end) state n is carried over
+  // unchanged; state n+1 is kept whole once the horizon is reached
+  const bool frozen = A.n >= sc.t_end;
+  const bool write_vc = A.write_vc || A.n + 1 >= sc.t_end;
   auto part = [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
                   float (&L)[D][D], float &mpp, unsigned &eb) {
         float x[D], f0[D], F[D * D];
         int b0[D];
+        if (frozen) {
+          float a[D * D];
+          load_vec<D>(A.s.x, A.ld, p, a);
+          store_vec<D>(A.out.x, A.ld, p, a);
+          load_vec<D>(A.s.v, A.ld, p, a);
+          store_vec<D>(A.out.v, A.ld, p, a);
+          load_mat<D>(A.s.C, A.ld, p, a);
+          store_mat<D>(A.out.C, A.ld, p, a);
+          load_mat<D>(A.s.F, A.ld, p, a);
+          store_mat<D>(A.out.F, A.ld, p, a);
+          return false;
+        }
         load_vec<D>(A.s.x, A.ld, p, x);
         if (!stencil_base<D>(x, sc, b0, f0, eb)) {
           // keep state n+1 defined (the rollout reports the error)
@@ -1469,11 +1656,16 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
         if (!(finite_all(xn, D) && finite_all(vn, D) && finite_all(Cn, D * D) &&
               finite_all(Fn, D * D)))
           eb |= EB_NONFINITE;
+        // the next substep's G2P reads only x and F; v and C are written
+        // where the tape keeps state n+1
         store_vec<D>(A.out.x, A.ld, p, xn);
-        store_vec<D>(A.out.v, A.ld, p, vn);
-        store_mat<D>(A.out.C, A.ld, p, Cn);
         store_mat<D>(A.out.F, A.ld, p, Fn);
-        // the record of state n+1 for the scatter
+        if (write_vc) {
+          store_vec<D>(A.out.v, A.ld, p, vn);
+          store_mat<D>(A.out.C, A.ld, p, Cn);
+        }
+        // the record of state n+1 for the scatter (none past the horizon)
+        if (A.n + 1 >= sc.t_end) return false;
         if (!stencil_base<D>(xn, sc, base, f, eb)) return false;
         const int j = A.act_id[p];
         const float s_act = j >= 0 ? A.act[sc.act_off + j] : 0.0f;
@@ -1758,8 +1950,10 @@ __device__ __forceinline__ void node_velocity(const DevScene &sc, int li,
   const bool wall = is_wall<D>(li, sc.n, sc.wall);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
+    // explicit roundings (no contraction into an FMA): the grid kernel and
+    // the G2P that rebuilds velocities from stored (m, p) get the same bits
     float va = 0.0f;
-    if (m > 0.0f) va = p[a] / m + sc.dt * sc.g[a];
+    if (m > 0.0f) va = __fadd_rn(p[a] / m, __fmul_rn(sc.dt, sc.g[a]));
     v[a] = va;
   }
   if (wall) wall_bc<D>(sc, li, v);
@@ -1798,6 +1992,128 @@ __global__ __launch_bounds__(256) void k_grid(GridArgs A) {
 #pragma unroll
     for (int a = 0; a < D; ++a) A.out_p[a * A.G + gi] = mp[1 + a];
   }
+}
+
+// A node tile of a binned scene (64-cell tiles: B = 4 in 3D, 8 in 2D): node
+// tile t holds nodes tB-1 .. tB+B-2 per axis, lane (l0, l1[, l2]) the node
+// t B - 1 + l, and the boxes of tiles t-1 and t per axis are the only ones
+// that can cover its nodes (box u spans nodes uB-1 .. uB+B+2: the tile's
+// cells, the 2-node stencil reach and one cell of slack per side).  Box t
+// covers the whole node tile; box t-1 reaches only nodes up to tB+2, which
+// is all of them for B = 4 but half of them for B = 8.
+template <int D, int B>
+struct NodeTile {
+  static constexpr int K = 1 << D;
+  int li;          // scene-local node index of this lane
+  bool valid;      // the node lies in the grid
+  int tile[K];     // global tile of candidate k (axis 0 slowest)
+  int loc[K];      // this node's index in candidate k's box
+  bool nz[K];      // candidate k exists and holds particles (uniform)
+  bool cov[K];     // candidate k's box covers this lane's node
+  bool any;
+};
+
+template <int D, int B>
+__device__ __forceinline__ NodeTile<D, B> node_tile(const DevScene &sc, int lt,
+                                                    const int *tile_cnt) {
+  constexpr int S = TileBox<B>::S;
+  NodeTile<D, B> r;
+  int t[D], g[D];
+  {
+    int l = lt, ll = (int)threadIdx.x;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+      t[a] = l % sc.nnt;
+      l /= sc.nnt;
+      g[a] = t[a] * B - 1 + ll % B;
+      ll /= B;
+    }
+  }
+  r.valid = true;
+  r.li = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    r.valid = r.valid && g[a] >= 0 && g[a] < sc.n;
+    r.li = r.li * sc.n + g[a];
+  }
+  r.any = false;
+#pragma unroll
+  for (int k = 0; k < NodeTile<D, B>::K; ++k) {
+    bool ok = true, cov = true;
+    int tl = 0, lc = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int u = t[a] - 1 + ((k >> (D - 1 - a)) & 1);
+      const int l = g[a] - (u * B - 1);
+      ok = ok && u >= 0 && u < sc.nt;
+      cov = cov && l >= 0 && l < S;
+      tl = tl * sc.nt + (u >= 0 && u < sc.nt ? u : 0);
+      lc = lc * S + l;
+    }
+    r.tile[k] = sc.tile_off + tl;
+    r.loc[k] = lc;
+    r.nz[k] = ok && tile_cnt[r.tile[k]] != 0;
+    r.cov[k] = cov;
+    r.any = r.any || r.nz[k];
+  }
+  return r;
+}
+
+// Grid operations over node tiles (see k_grid): direct adds (only where a
+// particle beyond its box's slack flagged the node tile) then the candidate
+// boxes in the nested-loop order.
+template <int D>
+__device__ __forceinline__ void grid_nt_item(const GridArgs &A, int ntg) {
+  constexpr int B = D == 2 ? 8 : 4;
+  constexpr int S = TileBox<B>::S, SV = D == 2 ? S * S : S * S * S;
+  const DevScene sc = A.scenes[A.nt_scene[ntg]];
+  const NodeTile<D, B> nt = node_tile<D, B>(sc, ntg - sc.nt_off, A.tile_cnt);
+  const bool dirty = A.nt_dirty[ntg] != 0;
+  if ((!nt.any && !dirty) || !nt.valid) return;
+  const int64_t gi = sc.g_off + nt.li;
+  float mp[D + 1];
+#pragma unroll
+  for (int c = 0; c <= D; ++c) mp[c] = 0.0f;
+  if (dirty) {
+    mp[0] = A.gm[gi];
+#pragma unroll
+    for (int a = 0; a < D; ++a) mp[1 + a] = A.gp[a * A.G + gi];
+  }
+  const bool direct = mp[0] != 0.0f;
+  float val[NodeTile<D, B>::K][D + 1];
+#pragma unroll
+  for (int k = 0; k < NodeTile<D, B>::K; ++k)
+    if (nt.nz[k] && nt.cov[k]) {
+      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + nt.loc[k];
+#pragma unroll
+      for (int c = 0; c <= D; ++c) val[k][c] = bx[c * SV];
+    }
+#pragma unroll
+  for (int k = 0; k < NodeTile<D, B>::K; ++k)
+    if (nt.nz[k] && nt.cov[k]) {
+#pragma unroll
+      for (int c = 0; c <= D; ++c) mp[c] += val[k][c];
+    }
+  float v[D];
+  node_velocity<D>(sc, nt.li, mp[0], mp + 1, v);
+#pragma unroll
+  for (int a = 0; a < D; ++a) A.gv[a * A.G + gi] = v[a];
+  if (A.zero_mp && direct) {
+    A.gm[gi] = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.gp[a * A.G + gi] = 0.0f;
+  }
+  if (A.out_m) {
+    A.out_m[gi] = mp[0];
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.out_p[a * A.G + gi] = mp[1 + a];
+  }
+}
+
+// P: persistent launch (a few workgroups per CU loop over the node tiles).
+template <int D, bool P>
+__global__ __launch_bounds__(64) void k_grid_nt(GridArgs A) {
+  for_items(A.n_nt, P, [&](int ntg) { grid_nt_item<D>(A, ntg); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1854,6 +2170,21 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
   const int t = threadIdx.x;
   const bool active = t < ch.count;
   const int p = ch.start + t;
+  if (A.n >= sc.t_end) {
+    // past the scene's horizon: the state is carried over unchanged
+    if (active) {
+      float a[D * D];
+      load_vec<D>(A.s.x, A.ld, p, a);
+      store_vec<D>(A.out.x, A.ld, p, a);
+      load_vec<D>(A.s.v, A.ld, p, a);
+      store_vec<D>(A.out.v, A.ld, p, a);
+      load_mat<D>(A.s.C, A.ld, p, a);
+      store_mat<D>(A.out.C, A.ld, p, a);
+      load_mat<D>(A.s.F, A.ld, p, a);
+      store_mat<D>(A.out.F, A.ld, p, a);
+    }
+    return;
+  }
   if constexpr (CTL)
     for (int i = t & 63; i < CTL_MAX_NZS; i += 64) s_ctl[t >> 6][i] = 0.0f;
   unsigned eb = 0;
@@ -2196,6 +2527,84 @@ __global__ __launch_bounds__(256) void k_adj_grid(AdjGridArgs A) {
   }
 }
 
+// Adjoint grid operations over node tiles (see k_adj_grid and k_grid_nt).
+template <int D>
+__device__ __forceinline__ void adj_grid_nt_item(const AdjGridArgs &A, int ntg) {
+  constexpr int B = D == 2 ? 8 : 4;
+  constexpr int S = TileBox<B>::S, SV = D == 2 ? S * S : S * S * S;
+  const DevScene sc = A.scenes[A.nt_scene[ntg]];
+  const NodeTile<D, B> nt = node_tile<D, B>(sc, ntg - sc.nt_off, A.tile_cnt);
+  const bool dirty = A.nt_dirty[ntg] != 0;
+  if ((!nt.any && !dirty) || !nt.valid) return;
+  const int li = nt.li;
+  const int64_t gi = sc.g_off + li;
+  float vb[D];
+  bool nz = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) vb[a] = 0.0f;
+  if (dirty) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      vb[a] = A.vbar[a * A.G + gi];
+      nz = nz || vb[a] != 0.0f;
+    }
+  }
+  const float m = A.gm[gi];
+  float val[NodeTile<D, B>::K][D];
+#pragma unroll
+  for (int k = 0; k < NodeTile<D, B>::K; ++k)
+    if (nt.nz[k] && nt.cov[k]) {
+      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + nt.loc[k];
+#pragma unroll
+      for (int c = 0; c < D; ++c) val[k][c] = bx[c * SV];
+    }
+#pragma unroll
+  for (int k = 0; k < NodeTile<D, B>::K; ++k)
+    if (nt.nz[k] && nt.cov[k]) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) vb[c] += val[k][c];
+    }
+  const bool wall = is_wall<D>(li, sc.n, sc.wall);
+  float pb[D], v[D];
+  float mb = 0.0f;
+  if (m > 0.0f) {
+    const float im = 1.0f / m;
+    float vhat[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      vhat[a] = A.gp[a * A.G + gi] / m;  // before gravity (E)
+      v[a] = vhat[a] + sc.dt * sc.g[a];
+    }
+    // wall nodes: v after the condition, dL/dv before it (sticky: 0; (L))
+    if (wall) wall_bc_bwd<D>(sc, li, v, vb);
+    float dot = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      pb[a] = vb[a] * im;                // (D)
+      dot += vhat[a] * vb[a];
+    }
+    mb = -dot * im;                      // (E)
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = pb[a] = 0.0f;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    A.pbar[a * A.G + gi] = pb[a];
+    A.gv[a * A.G + gi] = v[a];
+  }
+  A.mbar[gi] = mb;
+  if (nz) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.vbar[a * A.G + gi] = 0.0f;
+  }
+}
+
+template <int D, bool P>
+__global__ __launch_bounds__(64) void k_adj_grid_nt(AdjGridArgs A) {
+  for_items(A.n_nt, P, [&](int ntg) { adj_grid_nt_item<D>(A, ntg); });
+}
+
 // ---------------------------------------------------------------------------
 // reverse R3: adjoint of P2G and of the particle update, a grid -> particle
 // gather (supplement F-K)
@@ -2208,9 +2617,8 @@ struct __align__(16) AdjNode {
   float4 b;  // v0, v1, v2 (or 0), unused
 };
 
-template <int D>
-__device__ __forceinline__ AdjNode adj_node_global(const AdjGatherArgs &A,
-                                                   int64_t gi) {
+template <int D, typename Args>
+__device__ __forceinline__ AdjNode adj_node_global(const Args &A, int64_t gi) {
   AdjNode r;
   r.a.x = A.pbar[gi];
   r.a.y = A.pbar[A.G + gi];
@@ -2221,6 +2629,236 @@ __device__ __forceinline__ AdjNode adj_node_global(const AdjGatherArgs &A,
   r.b.z = D == 3 ? A.gv[2 * A.G + gi] : 0.0f;
   r.b.w = 0.0f;
   return r;
+}
+
+// One particle's reverse of substep n once the scatter and grid reverses are
+// done (supplement (F)-(K)).  In: the stencil fraction f of x^n, state n
+// (v, C, F), the adjoint of state n+1 (gx1, gv1, gC1, gF1) and the
+// particle's actuation; node(o0, o1, o2, nd) fetches the record (dL/dp_i,
+// dL/dm_i, v_i) of stencil node base + o.  F^n and dL/dF^{n+1} are used
+// again after the stencil loop; unpark(F, gF1) brings them back there (from
+// LDS or a second read) so that they need not stay in registers across it.
+// Out: xvc(ok, xb, vb, Cb) as soon as the x, v, C adjoints of state n are
+// final, then fout(ok, Fb) with the F adjoint; sb_act += (K) for an actuated
+// particle.  PM: pm_mass(ok, Nmb, Spb, Gb) and pm_stress(ok, Ptb, F, S,
+// inner) hand over what the per-particle material gradients need.  ok is
+// false (and eb set) when F^n is inverted; it is also returned.
+template <int D, bool PM, typename Node, typename Unpark, typename XVC, typename FOut,
+          typename PmMass, typename PmStress>
+__device__ __forceinline__ bool adj_gather_particle(
+    const DevScene &sc, const Mat &m, const float *f, const float *v, const float *C,
+    const float *F0, const float *gx1, const float *gv1, const float *gC1,
+    const float *gF10, float s_act, bool has_act, Node &&node, Unpark &&unpark,
+    XVC &&xvc, FOut &&fout, PmMass &&pm_mass, PmStress &&pm_stress, unsigned &eb,
+    float &sb_act) {
+  // --- quantities live across the stencil loop ---------------------------
+  float w[D][3], dw[D][3];
+  // vt + (4/dx^2) Ct (x_i - x_p) = cV + CdxD o  (v-term and C-term of (J))
+  float cV[D], CdxD[D][D];
+  float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
+  bool ok;
+  {
+    Stress<D> S;
+    ok = stress<D>(sc, m, F0, s_act, has_act, S, eb);
+    float G[D * D];
+    affine_G<D>(sc, m, S.Pt, F0, C, G);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float s1 = gv1[a] + sc.dt * gx1[a];  // (A) vt
+      float s2 = m.mp * v[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        float ct = 0.0f;  // (B) Ct = gC1 + dt gF1 F^T
+#pragma unroll
+        for (int g = 0; g < D; ++g) ct += gF10[a * D + g] * F0[b * D + g];
+        CdxD[a][b] = (gC1[a * D + b] + sc.dt * ct) * (sc.dx * sc.Dinv);
+        Gdx[a][b] = G[a * D + b] * sc.dx;
+        s1 -= CdxD[a][b] * f[b];
+        s2 -= Gdx[a][b] * f[b];
+      }
+      cV[a] = s1;
+      cq[a] = s2;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    bspline_w(f[a], w[a]);
+    bspline_dw(f[a], sc.inv_dx, dw[a]);
+  }
+  // Go = sum N p_i o^T (dL/dG = (Go - Spb f^T) dx after the loop);
+  // Co = sum N v_i o^T gives C^{n+1} = (4/dx^2) dx (Co - Sv f^T), the G2P
+  // of this substep, from the same node velocities
+  float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {}, Co[D * D] = {};
+#pragma unroll
+  for (int a = 0; a < D; ++a) xb[a] = gx1[a];  // (J) direct term dL/dx^{n+1}
+  float Nmb = 0.0f;  // PM: sum N dL/dm_i
+  auto add_node = [&](const AdjNode &nd, float N, const float *gN, const float *o) {
+    const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
+    const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
+    float s_all = m.mp * nd.a.w;  // (J) m-term
+    if constexpr (PM) Nmb += N * nd.a.w;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float cv = cV[a], q = cq[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        cv += CdxD[a][b] * o[b];
+        q += Gdx[a][b] * o[b];
+      }
+      // (J) v-term and C-term (N parts), p-term (N part)
+      s_all += vi[a] * cv + pb[a] * q;
+      const float Npb = N * pb[a], Nv = N * vi[a];
+      Spb[a] += Npb;  // (F), and the delta part of the (J) p-term
+      Sv[a] += Nv;    // delta part of the (J) C-term
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        Gb[a * D + b] += Npb * o[b];
+        Co[a * D + b] += Nv * o[b];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
+  };
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll
+      for (int o1 = 0; o1 < 3; ++o1) {
+        const float N = w[0][o0] * w[1][o1];
+        const float gN[2] = {dw[0][o0] * w[1][o1], w[0][o0] * dw[1][o1]};
+        const float o[2] = {(float)o0, (float)o1};
+        AdjNode nd;
+        node(o0, o1, 0, nd);
+        add_node(nd, N, gN, o);
+      }
+  } else {
+    // rows of the stencil are not unrolled: one row of node records in
+    // flight instead of all 27 keeps the register count near the bound
+#pragma unroll 1
+    for (int o0 = 0; o0 < 3; ++o0)
+#pragma unroll 1
+      for (int o1 = 0; o1 < 3; ++o1) {
+        const float w01 = w[0][o0] * w[1][o1];
+        const float d01 = dw[0][o0] * w[1][o1];
+        const float w0d1 = w[0][o0] * dw[1][o1];
+#pragma unroll
+        for (int o2 = 0; o2 < 3; ++o2) {
+          const float N = w01 * w[2][o2];
+          const float gN[3] = {d01 * w[2][o2], w0d1 * w[2][o2], w01 * dw[2][o2]};
+          const float o[3] = {(float)o0, (float)o1, (float)o2};
+          AdjNode nd;
+          node(o0, o1, o2, nd);
+          add_node(nd, N, gN, o);
+        }
+      }
+  }
+  // (J) delta parts: -sum N [ (4/dx^2) Ct^T v_i + G^T p_i ],
+  // with Ct = Cdx / dx and G = Gdx / dx
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) s += CdxD[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
+    xb[c] -= s * sc.inv_dx;
+  }
+  float C1[D * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      Gb[a * D + b] -= Spb[a] * f[b];
+      C1[a * D + b] = (sc.Dinv * sc.dx) * (Co[a * D + b] - Sv[a] * f[b]);
+    }
+  // --- after the loop: F^n and dL/dF^{n+1} back, the stress again ----------
+  // (the compiler barrier keeps the pre-loop copies from staying live across
+  // the stencil loop)
+  asm volatile("" ::: "memory");
+  float F[D * D], gF1[D * D];
+  unpark(F, gF1);
+  Stress<D> S;
+  unsigned eb2 = 0;
+  stress<D>(sc, m, F, s_act, has_act, S, eb2);
+  float vb[D], Cb[D * D], Ptb[D * D], Fb[D * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) vb[a] = m.mp * Spb[a];  // (F)
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    Gb[k] *= sc.dx;        // dL/dG = sum N p_i (x_i - x_p)^T
+    Cb[k] = m.mp * Gb[k];  // (I)
+  }
+  if constexpr (PM) pm_mass(ok, Nmb, Spb, Gb);
+  if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D)))
+    eb |= EB_NONFINITE;
+  // x, v and C adjoints are final
+  xvc(ok, xb, vb, Cb);
+  // (G) dL/dP_t = kG dL/dG F
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += Gb[a * D + g] * F[g * D + b];
+      Ptb[a * D + b] = sc.kG * s;
+    }
+  // (H) update term (I + dt C^{n+1})^T dL/dF^{n+1}
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = gF1[a * D + b];
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += sc.dt * C1[g * D + a] * gF1[g * D + b];
+      Fb[a * D + b] = s;
+    }
+  // (H) G-term kG dL/dG^T P_t and actuation term dL/dP_t sigma^T
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += Gb[g * D + a] * S.Pt[g * D + b];
+      Fb[a * D + b] += sc.kG * s + Ptb[a * D + b] * S.sigma[b];
+    }
+  // (H) elastic term: mu Ptb + (mu - la lnJ) F^-T Ptb^T F^-T
+  //                  + la <Ptb, F^-T> F^-T
+  float inner = 0.0f, T1[D * D];
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) inner += Ptb[k] * S.FiT[k];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;  // (F^-T Ptb^T)_ab
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += S.FiT[a * D + g] * Ptb[b * D + g];
+      T1[a * D + b] = s;
+    }
+  const float cmu = m.mu - m.la * S.lnJ;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      float s = 0.0f;
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += T1[a * D + g] * S.FiT[g * D + b];
+      Fb[a * D + b] += m.mu * Ptb[a * D + b] + cmu * s + m.la * inner * S.FiT[a * D + b];
+    }
+  if constexpr (PM) pm_stress(ok, Ptb, F, S, inner);
+  // (K) dL/dsigma_aa = (F^T dL/dP_t)_aa;  s-bar = sum_a axis_a sigma-bar_aa
+  if (has_act) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float s = 0.0f;
+#pragma unroll
+      for (int g = 0; g < D; ++g) s += F[g * D + a] * Ptb[g * D + a];
+      sb_act += sc.axis[a] * s;
+    }
+  }
+  if (!finite_all(Fb, D * D)) eb |= EB_NONFINITE;
+  fout(ok, Fb);
+  return ok;
 }
 
 // Launched for three waves per SIMD (at most 168 VGPRs): with F and dL/dF
@@ -2238,6 +2876,23 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   const int t = threadIdx.x;
   const bool active = t < ch.count;
   const int p = ch.start + t;
+  if (A.n >= sc.t_end) {
+    // past the scene's horizon the substep is the identity: the adjoint is
+    // carried over and adds nothing to dL/ds or the material gradients
+    if (active) {
+      float a[D * D];
+      load_vec<D>(A.g1.x, A.ld, p, a);
+      store_vec<D>(A.g0.x, A.ld, p, a);
+      load_vec<D>(A.g1.v, A.ld, p, a);
+      store_vec<D>(A.g0.v, A.ld, p, a);
+      load_mat<D>(A.g1.C, A.ld, p, a);
+      store_mat<D>(A.g0.C, A.ld, p, a);
+      load_mat<D>(A.g1.F, A.ld, p, a);
+      store_mat<D>(A.g0.F, A.ld, p, a);
+      if (A.sb_part) A.sb_part[p] = 0.0f;
+    }
+    return;
+  }
   unsigned eb = 0;
   float xp[D], f[D];
   int base[D];
@@ -2274,260 +2929,73 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   if (!ok) j_act = -1;
   if (ok) {
     const float s_act = j_act >= 0 ? A.act[sc.act_off + j_act] : 0.0f;
-    // --- quantities live across the stencil loop -------------------------
-    float w[D][3], dw[D][3];
-    // vt + (4/dx^2) Ct (x_i - x_p) = cV + CdxD o  (v-term and C-term of (J))
-    float cV[D], CdxD[D][D];
-    float cq[D], Gdx[D][D];  // m v + G (x_i - x_p) = cq + Gdx o
-    {
-      Stress<D> S;
-      ok = stress<D>(sc, m, F, s_act, j_act >= 0, S, eb);
-      float G[D * D];
-      affine_G<D>(sc, m, S.Pt, F, C, G);
-      if constexpr (D == 3) {
-#pragma unroll
-        for (int q = 0; q < D * D; ++q) {
-          s_keep[q * CH + t] = F[q];
-          s_keep[(D * D + q) * CH + t] = gF1[q];
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        float s1 = gv1[a] + sc.dt * gx1[a];  // (A) vt
-        float s2 = m.mp * v[a];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          float ct = 0.0f;  // (B) Ct = gC1 + dt gF1 F^T
-#pragma unroll
-          for (int g = 0; g < D; ++g) ct += gF1[a * D + g] * F[b * D + g];
-          CdxD[a][b] = (gC1[a * D + b] + sc.dt * ct) * (sc.dx * sc.Dinv);
-          Gdx[a][b] = G[a * D + b] * sc.dx;
-          s1 -= CdxD[a][b] * f[b];
-          s2 -= Gdx[a][b] * f[b];
-        }
-        cV[a] = s1;
-        cq[a] = s2;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      bspline_w(f[a], w[a]);
-      bspline_dw(f[a], sc.inv_dx, dw[a]);
-    }
-    // Go = sum N p_i o^T (dL/dG = (Go - Spb f^T) dx after the loop);
-    // Co = sum N v_i o^T gives C^{n+1} = (4/dx^2) dx (Co - Sv f^T), the G2P
-    // of this substep, from the same staged velocities
-    float xb[D], Spb[D] = {}, Sv[D] = {}, Gb[D * D] = {}, Co[D * D] = {};
-    load_vec<D>(A.g1.x, A.ld, p, xb);  // (J) direct term dL/dx^{n+1}
-    const int lbase = box.lds ? box_index<D>(box, base) : 0;
-    const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-
-    float Nmb = 0.0f;  // PM: sum N dL/dm_i
-    auto node = [&](const AdjNode &nd, float N, const float *gN, const float *o) {
-      const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
-      const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
-      float s_all = m.mp * nd.a.w;  // (J) m-term
-      if constexpr (PM) Nmb += N * nd.a.w;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        float cv = cV[a], q = cq[a];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          cv += CdxD[a][b] * o[b];
-          q += Gdx[a][b] * o[b];
-        }
-        // (J) v-term and C-term (N parts), p-term (N part)
-        s_all += vi[a] * cv + pb[a] * q;
-        const float Npb = N * pb[a], Nv = N * vi[a];
-        Spb[a] += Npb;  // (F), and the delta part of the (J) p-term
-        Sv[a] += Nv;    // delta part of the (J) C-term
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-          Gb[a * D + b] += Npb * o[b];
-          Co[a * D + b] += Nv * o[b];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < D; ++c) xb[c] += gN[c] * s_all;
-    };
-
-    if constexpr (D == 2) {
-#pragma unroll
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float N = w[0][o0] * w[1][o1];
-          const float gN[2] = {dw[0][o0] * w[1][o1], w[0][o0] * dw[1][o1]};
-          const float o[2] = {(float)o0, (float)o1};
-          const AdjNode nd = box.lds ? s_n[lbase + o0 * box.e[1] + o1]
-                                     : adj_node_global<D>(A, gbase + o0 * sc.n + o1);
-          node(nd, N, gN, o);
-        }
-    } else {
-      // rows of the stencil are not unrolled: one row of LDS records in
-      // flight instead of all 27 keeps the register count near the bound
-#pragma unroll 1
-      for (int o0 = 0; o0 < 3; ++o0)
-#pragma unroll 1
-        for (int o1 = 0; o1 < 3; ++o1) {
-          const float w01 = w[0][o0] * w[1][o1];
-          const float d01 = dw[0][o0] * w[1][o1];
-          const float w0d1 = w[0][o0] * dw[1][o1];
-#pragma unroll
-          for (int o2 = 0; o2 < 3; ++o2) {
-            const float N = w01 * w[2][o2];
-            const float gN[3] = {d01 * w[2][o2], w0d1 * w[2][o2], w01 * dw[2][o2]};
-            const float o[3] = {(float)o0, (float)o1, (float)o2};
-            const AdjNode nd =
-                box.lds ? s_n[lbase + (o0 * box.e[1] + o1) * box.e[2] + o2]
-                        : adj_node_global<D>(A, gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
-            node(nd, N, gN, o);
-          }
-        }
-    }
-    // (J) delta parts: -sum N [ (4/dx^2) Ct^T v_i + G^T p_i ],
-    // with Ct = Cdx / dx and G = Gdx / dx
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      float s = 0.0f;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-        s += CdxD[a][c] * Sv[a] + Gdx[a][c] * Spb[a];
-      xb[c] -= s * sc.inv_dx;
-    }
-    float C1[D * D];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        Gb[a * D + b] -= Spb[a] * f[b];
-        C1[a * D + b] = (sc.Dinv * sc.dx) * (Co[a * D + b] - Sv[a] * f[b]);
-      }
-    // --- after the loop: reload F and dL/dF^{n+1}, recompute the stress ----
-    // (the compiler barrier keeps the pre-loop copies from staying live
-    // across the stencil loop; in 3D they come back from the thread's LDS
-    // slots instead of a second HBM read)
-    asm volatile("" ::: "memory");
-    float F[D * D], gF1[D * D];
     if constexpr (D == 3) {
 #pragma unroll
       for (int q = 0; q < D * D; ++q) {
-        F[q] = s_keep[q * CH + t];
-        gF1[q] = s_keep[(D * D + q) * CH + t];
-      }
-    } else {
-      load_mat<D>(A.s.F, A.ld, p, F);
-      load_mat<D>(A.g1.F, A.ld, p, gF1);
-    }
-    Stress<D> S;
-    unsigned eb2 = 0;
-    stress<D>(sc, m, F, s_act, j_act >= 0, S, eb2);
-    float vb[D], Cb[D * D], Ptb[D * D], Fb[D * D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) vb[a] = m.mp * Spb[a];  // (F)
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) {
-      Gb[k] *= sc.dx;        // dL/dG = sum N p_i (x_i - x_p)^T
-      Cb[k] = m.mp * Gb[k];  // (I)
-    }
-    if constexpr (PM) {
-      // dL/dm_p = sum N [dL/dm_i + dL/dp_i . (v_p + C_p (x_i - x_p))]
-      if (A.gmat && ok) {
-        float vv[D], CC[D * D];
-        load_vec<D>(A.s.v, A.ld, p, vv);
-        load_mat<D>(A.s.C, A.ld, p, CC);
-        float mbp = Nmb;
-#pragma unroll
-        for (int a = 0; a < D; ++a) mbp += vv[a] * Spb[a];
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) mbp += CC[k] * Gb[k];
-        A.gmat[2 * (int64_t)A.ld + p] += mbp;
+        s_keep[q * CH + t] = F[q];
+        s_keep[(D * D + q) * CH + t] = gF1[q];
       }
     }
-    // x, v and C adjoints are final: store them now (frees their registers)
-    if (!(finite_all(xb, D) && finite_all(vb, D) && finite_all(Cb, D * D)))
-      eb |= EB_NONFINITE;
-    if (ok) {
-      store_vec<D>(A.g0.x, A.ld, p, xb);
-      store_vec<D>(A.g0.v, A.ld, p, vb);
-      store_mat<D>(A.g0.C, A.ld, p, Cb);
-    }
-    // (G) dL/dP_t = kG dL/dG F
+    const int lbase = box.lds ? box_index<D>(box, base) : 0;
+    const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
+    ok = adj_gather_particle<D, PM>(
+        sc, m, f, v, C, F, gx1, gv1, gC1, gF1, s_act, j_act >= 0,
+        [&](int o0, int o1, int o2, AdjNode &nd) {
+          if constexpr (D == 2) {
+            nd = box.lds ? s_n[lbase + o0 * box.e[1] + o1]
+                         : adj_node_global<D>(A, gbase + o0 * sc.n + o1);
+          } else {
+            nd = box.lds ? s_n[lbase + (o0 * box.e[1] + o1) * box.e[2] + o2]
+                         : adj_node_global<D>(A, gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
+          }
+        },
+        [&](float *Fr, float *gFr) {
+          if constexpr (D == 3) {
 #pragma unroll
-    for (int a = 0; a < D; ++a)
+            for (int q = 0; q < D * D; ++q) {
+              Fr[q] = s_keep[q * CH + t];
+              gFr[q] = s_keep[(D * D + q) * CH + t];
+            }
+          } else {
+            load_mat<D>(A.s.F, A.ld, p, Fr);
+            load_mat<D>(A.g1.F, A.ld, p, gFr);
+          }
+        },
+        [&](bool okp, const float *xb, const float *vb, const float *Cb) {
+          if (okp) {
+            store_vec<D>(A.g0.x, A.ld, p, xb);
+            store_vec<D>(A.g0.v, A.ld, p, vb);
+            store_mat<D>(A.g0.C, A.ld, p, Cb);
+          }
+        },
+        [&](bool okp, const float *Fb) {
+          if (okp) store_mat<D>(A.g0.F, A.ld, p, Fb);
+        },
+        [&](bool okp, float Nmb, const float *Spb, const float *Gb) {
+          // dL/dm_p = sum N [dL/dm_i + dL/dp_i . (v_p + C_p (x_i - x_p))]
+          if (A.gmat && okp) {
+            float vv[D], CC[D * D];
+            load_vec<D>(A.s.v, A.ld, p, vv);
+            load_mat<D>(A.s.C, A.ld, p, CC);
+            float mbp = Nmb;
 #pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = 0.0f;
+            for (int a = 0; a < D; ++a) mbp += vv[a] * Spb[a];
 #pragma unroll
-        for (int g = 0; g < D; ++g) s += Gb[a * D + g] * F[g * D + b];
-        Ptb[a * D + b] = sc.kG * s;
-      }
-    // (H) update term (I + dt C^{n+1})^T dL/dF^{n+1}
+            for (int k = 0; k < D * D; ++k) mbp += CC[k] * Gb[k];
+            A.gmat[2 * (int64_t)A.ld + p] += mbp;
+          }
+        },
+        [&](bool okp, const float *Ptb, const float *Fr, const Stress<D> &S, float inner) {
+          // dL/dmu_p = <dL/dP, F - F^-T>, dL/dla_p = ln J <dL/dP, F^-T>
+          if (A.gmat && okp) {
+            float mub = 0.0f;
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = gF1[a * D + b];
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += sc.dt * C1[g * D + a] * gF1[g * D + b];
-        Fb[a * D + b] = s;
-      }
-    // (H) G-term kG dL/dG^T P_t and actuation term dL/dP_t sigma^T
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = 0.0f;
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += Gb[g * D + a] * S.Pt[g * D + b];
-        Fb[a * D + b] += sc.kG * s + Ptb[a * D + b] * S.sigma[b];
-      }
-    // (H) elastic term: mu Ptb + (mu - la lnJ) F^-T Ptb^T F^-T
-    //                  + la <Ptb, F^-T> F^-T
-    float inner = 0.0f, T1[D * D];
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) inner += Ptb[k] * S.FiT[k];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = 0.0f;  // (F^-T Ptb^T)_ab
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += S.FiT[a * D + g] * Ptb[b * D + g];
-        T1[a * D + b] = s;
-      }
-    const float cmu = m.mu - m.la * S.lnJ;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        float s = 0.0f;
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += T1[a * D + g] * S.FiT[g * D + b];
-        Fb[a * D + b] += m.mu * Ptb[a * D + b] + cmu * s + m.la * inner * S.FiT[a * D + b];
-      }
-    if constexpr (PM) {
-      // dL/dmu_p = <dL/dP, F - F^-T>, dL/dla_p = ln J <dL/dP, F^-T>
-      if (A.gmat && ok) {
-        float mub = 0.0f;
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) mub += Ptb[k] * (F[k] - S.FiT[k]);
-        A.gmat[p] += mub;
-        A.gmat[(int64_t)A.ld + p] += S.lnJ * inner;
-      }
-    }
-    // (K) dL/dsigma_aa = (F^T dL/dP_t)_aa;  s-bar = sum_a axis_a sigma-bar_aa
-    if (j_act >= 0) {
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        float s = 0.0f;
-#pragma unroll
-        for (int g = 0; g < D; ++g) s += F[g * D + a] * Ptb[g * D + a];
-        sb_act += sc.axis[a] * s;
-      }
-    }
-    if (!finite_all(Fb, D * D)) eb |= EB_NONFINITE;
-    if (ok) store_mat<D>(A.g0.F, A.ld, p, Fb);
+            for (int k = 0; k < D * D; ++k) mub += Ptb[k] * (Fr[k] - S.FiT[k]);
+            A.gmat[p] += mub;
+            A.gmat[(int64_t)A.ld + p] += S.lnJ * inner;
+          }
+        },
+        eb, sb_act);
   }
   if (active && !ok) {
     float z[D * D] = {};
@@ -2537,6 +3005,7 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     store_mat<D>(A.g0.F, A.ld, p, z);
   }
   if (eb) atomicOr(A.err, eb);
+  if (A.sb_part && active) A.sb_part[p] = ok && j_act >= 0 ? sb_act : 0.0f;
   if (A.gact != nullptr) {
     if (act_lds) {
       if (ok && j_act >= 0)
@@ -2548,6 +3017,174 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     } else if (ok && j_act >= 0) {
       unsafeAtomicAdd(&A.gact[sc.act_off + j_act], (double)sb_act);
     }
+  }
+}
+
+// The reverse of substep n's G2P/P2G gather fused with the adjoint scatter
+// of substep n-1, in one pass over a tile (3D): the tile's box of the
+// adjoint grid of substep n is staged in LDS, each thread runs the gather
+// (supplement (F)-(K)) for its particles and writes the adjoint of state n,
+// and hands that adjoint from registers to the scatter's record step of
+// substep n-1 ((A)-(C) with x^{n-1}, F^{n-1}), so the adjoint of state n is
+// not read back from HBM.  Particles whose stencil left the box read the
+// adjoint grid from HBM (gather) or add to it with global atomics (scatter).
+// F^n and dL/dF^{n+1} are read a second time after the stencil loop
+// (cached), which keeps the kernel within three workgroups per CU.
+template <int D, bool DET>
+__global__ __launch_bounds__(256, 2) void k_adj_gather_scatter(AdjFusedArgs A) {
+  static_assert(D == 3, "the fused reverse pass is built for 3D tiles");
+  using SC = SortedCell<D>;
+  constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, B = SC::B;
+  __shared__ SortedCellSmem<D, D, 2, false, false, DET> sm;
+  __shared__ AdjNode s_n[SV];
+  __shared__ double s_act[LDS_ACT];
+  const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
+  if (A.tiles.cnt[tile] == 0) return;
+  const DevScene sc = A.scenes[A.tiles.scene[tile]];
+  const int t = threadIdx.x;
+  int org[D];
+  tile_origin<D, B>(tile - sc.tile_off, sc.nt, org);
+  for (int i = t; i < SV; i += 256) {
+    const int g[3] = {org[0] + i / (S * S), org[1] + (i / S) % S, org[2] + i % S};
+    const bool in = g[0] >= 0 && g[0] < sc.n && g[1] >= 0 && g[1] < sc.n &&
+                    g[2] >= 0 && g[2] < sc.n;
+    AdjNode nd{};
+    if (in) nd = adj_node_global<D>(A, sc.g_off + ((int64_t)g[0] * sc.n + g[1]) * sc.n + g[2]);
+    s_n[i] = nd;
+  }
+  const bool act_lds = sc.n_act <= LDS_ACT && A.gact != nullptr;
+  if (act_lds)
+    for (int i = t; i < sc.n_act; i += 256) s_act[i] = 0.0;
+  // (the scatter synchronises before its record step reads s_n and s_act)
+  const Mat m = scene_mat(sc);
+  auto part = [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
+                  float (&Cdx)[D][D], unsigned &eb) {
+    // --- reverse of substep n: gather ------------------------------------
+    float xn[D], fn[D], v[D], C[D * D], F[D * D], gx1[D], gv1[D], gC1[D * D], gF1[D * D];
+    int bn[D];
+    load_vec<D>(A.s.x, A.ld, p, xn);
+    load_vec<D>(A.s.v, A.ld, p, v);
+    load_mat<D>(A.s.C, A.ld, p, C);
+    load_mat<D>(A.s.F, A.ld, p, F);
+    load_vec<D>(A.g1.x, A.ld, p, gx1);
+    load_vec<D>(A.g1.v, A.ld, p, gv1);
+    load_mat<D>(A.g1.C, A.ld, p, gC1);
+    load_mat<D>(A.g1.F, A.ld, p, gF1);
+    const int j_act = A.act_id[p];
+    bool ok = stencil_base<D>(xn, sc, bn, fn, eb);
+    float vt[D], Cb[D * D], Fb[D * D];
+    float sb_act = 0.0f;
+    if (A.n >= sc.t_end) {
+      // past the scene's horizon substep n is the identity: the adjoint of
+      // state n+1 is carried over
+      store_vec<D>(A.g0.x, A.ld, p, gx1);
+      store_vec<D>(A.g0.v, A.ld, p, gv1);
+      store_mat<D>(A.g0.C, A.ld, p, gC1);
+      store_mat<D>(A.g0.F, A.ld, p, gF1);
+#pragma unroll
+      for (int a = 0; a < D; ++a) vt[a] = gv1[a] + sc.dt * gx1[a];
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) {
+        Cb[k] = gC1[k];
+        Fb[k] = gF1[k];
+      }
+      if (A.sb_part) A.sb_part[p] = 0.0f;
+      ok = true;
+    } else if (ok) {
+      int lb[D];
+      bool inb = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        lb[a] = bn[a] - org[a];
+        inb = inb && lb[a] >= 0 && lb[a] < BC;
+      }
+      const int lbase = (lb[0] * S + lb[1]) * S + lb[2];
+      const int64_t gbase = sc.g_off + node_index<D>(bn, sc.n);
+      const float s_n_act = j_act >= 0 ? A.act[sc.act_off + j_act] : 0.0f;
+      ok = adj_gather_particle<D, false>(
+          sc, m, fn, v, C, F, gx1, gv1, gC1, gF1, s_n_act, j_act >= 0,
+          [&](int o0, int o1, int o2, AdjNode &nd) {
+            nd = inb ? s_n[lbase + (o0 * S + o1) * S + o2]
+                     : adj_node_global<D>(A, gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
+          },
+          [&](float *Fr, float *gFr) {
+            load_mat<D>(A.s.F, A.ld, p, Fr);
+            load_mat<D>(A.g1.F, A.ld, p, gFr);
+          },
+          [&](bool okp, const float *xb, const float *vb, const float *Cbar) {
+            if (okp) {
+              store_vec<D>(A.g0.x, A.ld, p, xb);
+              store_vec<D>(A.g0.v, A.ld, p, vb);
+              store_mat<D>(A.g0.C, A.ld, p, Cbar);
+            }
+            // (A) of substep n-1: dL/dv^n total = carried + dt dL/dx^n
+#pragma unroll
+            for (int a = 0; a < D; ++a) vt[a] = vb[a] + sc.dt * xb[a];
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) Cb[k] = Cbar[k];
+          },
+          [&](bool okp, const float *Fbar) {
+            if (okp) store_mat<D>(A.g0.F, A.ld, p, Fbar);
+#pragma unroll
+            for (int k = 0; k < D * D; ++k) Fb[k] = Fbar[k];
+          },
+          [](bool, float, const float *, const float *) {},
+          [](bool, const float *, const float *, const Stress<D> &, float) {}, eb,
+          sb_act);
+      if (ok && j_act >= 0 && A.gact != nullptr) {
+        if (act_lds)
+          __hip_atomic_fetch_add(&s_act[j_act], (double)sb_act, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          unsafeAtomicAdd(&A.gact[sc.act_off + j_act], (double)sb_act);
+      }
+    }
+    if (A.sb_part && A.n < sc.t_end) A.sb_part[p] = ok && j_act >= 0 ? sb_act : 0.0f;
+    if (!ok) {
+      float z[D * D] = {};
+      store_vec<D>(A.g0.x, A.ld, p, z);
+      store_vec<D>(A.g0.v, A.ld, p, z);
+      store_mat<D>(A.g0.C, A.ld, p, z);
+      store_mat<D>(A.g0.F, A.ld, p, z);
+      return false;  // a zero adjoint adds nothing to substep n-1
+    }
+    // --- adjoint scatter of substep n-1 -----------------------------------
+    if (A.n - 1 >= sc.t_end) return false;  // the identity past the horizon
+    float xp[D], Fp[D * D];
+    load_vec<D>(A.sp.x, A.ld, p, xp);
+    if (!stencil_base<D>(xp, sc, base, f, eb)) return false;
+    load_mat<D>(A.sp.F, A.ld, p, Fp);
+    // (B): dL/dC^n total = carried + dt dL/dF^n F^{n-1 T}
+    const float cs = sc.Dinv * sc.dx;
+#pragma unroll
+    for (int a = 0; a < D; ++a) bspline_w(f[a], w[a]);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      // (C): vt + (4/dx^2) Ct (x_i - x_p), x_i - x_p = (o - f) dx
+      float s0 = vt[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        float ct = 0.0f;
+#pragma unroll
+        for (int g = 0; g < D; ++g) ct += Fb[a * D + g] * Fp[b * D + g];
+        Cdx[a][b] = cs * (Cb[a * D + b] + sc.dt * ct);
+        s0 -= Cdx[a][b] * f[b];
+      }
+      c0[a] = s0;
+    }
+    return true;
+  };
+  // the scatter's cells come from x^{n-1} alone, before the gathers
+  auto cell = [&](int p, int *base, unsigned &eb) {
+    float xp[D], f[D];
+    load_vec<D>(A.sp.x, A.ld, p, xp);
+    return stencil_base<D>(xp, sc, base, f, eb);
+  };
+  sorted_cell_scatter<D, D, false, 2, false>(A, tile, sm, nullptr, A.vbar, part, cell);
+  if (act_lds) {
+    __syncthreads();
+    for (int i = t; i < sc.n_act; i += 256)
+      if (s_act[i] != 0.0) unsafeAtomicAdd(&A.gact[sc.act_off + i], s_act[i]);
   }
 }
 
@@ -2942,17 +3579,29 @@ int launch_adj_scatter_tile(int dim, const AdjScatterArgs &a, int n_tiles,
 
 int launch_p2g_sorted(int dim, const P2GArgs &a, int n_tiles, hipStream_t st) {
   if (a.mat) {
-    if (dim == 2) MPM_LAUNCH(k_p2g_sorted_pm<2>, n_tiles, 256, st, a);
-    MPM_LAUNCH(k_p2g_sorted_pm<3>, n_tiles, 256, st, a);
+    if (a.det) {
+      if (dim == 2) MPM_LAUNCH((k_p2g_sorted_pm<2, true>), n_tiles, 256, st, a);
+      MPM_LAUNCH((k_p2g_sorted_pm<3, true>), n_tiles, 256, st, a);
+    }
+    if (dim == 2) MPM_LAUNCH((k_p2g_sorted_pm<2, false>), n_tiles, 256, st, a);
+    MPM_LAUNCH((k_p2g_sorted_pm<3, false>), n_tiles, 256, st, a);
   }
-  if (dim == 2) MPM_LAUNCH(k_p2g_sorted<2>, n_tiles, 256, st, a);
-  MPM_LAUNCH(k_p2g_sorted<3>, n_tiles, 256, st, a);
+  if (a.det) {
+    if (dim == 2) MPM_LAUNCH((k_p2g_sorted<2, true>), n_tiles, 256, st, a);
+    MPM_LAUNCH((k_p2g_sorted<3, true>), n_tiles, 256, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_p2g_sorted<2, false>), n_tiles, 256, st, a);
+  MPM_LAUNCH((k_p2g_sorted<3, false>), n_tiles, 256, st, a);
 }
 
 int launch_adj_scatter_sorted(int dim, const AdjScatterArgs &a, int n_tiles,
                               hipStream_t st) {
-  if (dim == 2) MPM_LAUNCH(k_adj_scatter_sorted<2>, n_tiles, 256, st, a);
-  MPM_LAUNCH(k_adj_scatter_sorted<3>, n_tiles, 256, st, a);
+  if (a.det) {
+    if (dim == 2) MPM_LAUNCH((k_adj_scatter_sorted<2, true>), n_tiles, 256, st, a);
+    MPM_LAUNCH((k_adj_scatter_sorted<3, true>), n_tiles, 256, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_adj_scatter_sorted<2, false>), n_tiles, 256, st, a);
+  MPM_LAUNCH((k_adj_scatter_sorted<3, false>), n_tiles, 256, st, a);
 }
 
 int launch_p2g_cell(int dim, const P2GArgs &a, const int *cell_cnt,
@@ -2969,6 +3618,30 @@ int launch_adj_scatter_cell(int dim, const AdjScatterArgs &a,
   MPM_LAUNCH(k_adj_scatter_cell<3>, g, 256, st, a, cell_cnt, n_tiles);
 }
 
+// Persistent launches of the node-tile kernels: eight one-wave workgroups
+// per CU (256 CUs), each looping over its XCD's share of the node tiles.
+constexpr int PERSIST_WG = 8 * 256;
+
+int launch_grid_nt(int dim, const GridArgs &a, hipStream_t st) {
+  const int pg = std::min(a.n_nt, PERSIST_WG);
+  if (a.persist) {
+    if (dim == 2) MPM_LAUNCH((k_grid_nt<2, true>), pg, 64, st, a);
+    MPM_LAUNCH((k_grid_nt<3, true>), pg, 64, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_grid_nt<2, false>), a.n_nt, 64, st, a);
+  MPM_LAUNCH((k_grid_nt<3, false>), a.n_nt, 64, st, a);
+}
+
+int launch_adj_grid_nt(int dim, const AdjGridArgs &a, hipStream_t st) {
+  const int pg = std::min(a.n_nt, PERSIST_WG);
+  if (a.persist) {
+    if (dim == 2) MPM_LAUNCH((k_adj_grid_nt<2, true>), pg, 64, st, a);
+    MPM_LAUNCH((k_adj_grid_nt<3, true>), pg, 64, st, a);
+  }
+  if (dim == 2) MPM_LAUNCH((k_adj_grid_nt<2, false>), a.n_nt, 64, st, a);
+  MPM_LAUNCH((k_adj_grid_nt<3, false>), a.n_nt, 64, st, a);
+}
+
 int launch_grid(int dim, const GridArgs &a, hipStream_t st) {
   if (dim == 2) MPM_LAUNCH(k_grid<2>, a.n_blocks, 256, st, a);
   MPM_LAUNCH(k_grid<3>, a.n_blocks, 256, st, a);
@@ -2976,8 +3649,12 @@ int launch_grid(int dim, const GridArgs &a, hipStream_t st) {
 
 int launch_g2p_p2g_sorted(int dim, const G2P2GArgs &a, int n_tiles, hipStream_t st) {
   if (dim != 3) return -1;  // the caller only fuses 3D passes
-  if (a.mat) MPM_LAUNCH((k_g2p_p2g_sorted<3, true>), n_tiles, 256, st, a);
-  MPM_LAUNCH((k_g2p_p2g_sorted<3, false>), n_tiles, 256, st, a);
+  if (a.det) {
+    if (a.mat) MPM_LAUNCH((k_g2p_p2g_sorted<3, true, true>), n_tiles, 256, st, a);
+    MPM_LAUNCH((k_g2p_p2g_sorted<3, false, true>), n_tiles, 256, st, a);
+  }
+  if (a.mat) MPM_LAUNCH((k_g2p_p2g_sorted<3, true, false>), n_tiles, 256, st, a);
+  MPM_LAUNCH((k_g2p_p2g_sorted<3, false, false>), n_tiles, 256, st, a);
 }
 
 int launch_g2p(int dim, const G2PArgs &a, hipStream_t st) {
@@ -2998,6 +3675,88 @@ int launch_adj_scatter(int dim, const AdjScatterArgs &a, hipStream_t st) {
 int launch_adj_grid(int dim, const AdjGridArgs &a, hipStream_t st) {
   if (dim == 2) MPM_LAUNCH(k_adj_grid<2>, a.n_blocks, 256, st, a);
   MPM_LAUNCH(k_adj_grid<3>, a.n_blocks, 256, st, a);
+}
+
+// Deterministic per-actuator sum of one substep's dL/ds (deterministic
+// mode): workgroup b takes actuator b, walks its scene's particles (tape
+// order, a contiguous range) in a fixed strided order in FP64 and reduces
+// the 256 partial sums with a fixed tree; gact[b] += the total.
+__global__ __launch_bounds__(256) void k_sbar_reduce(const DevScene *scenes,
+                                                     const int *act_scene,
+                                                     const int *tile_start,
+                                                     const int *act_id,
+                                                     const float *sb_part,
+                                                     int dim, double *gact) {
+  __shared__ double s[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const DevScene sc = scenes[act_scene[b]];
+  const int a = b - sc.act_off;
+  const int nts = sc.nt * sc.nt * (dim == 3 ? sc.nt : 1);
+  const int p0 = tile_start[sc.tile_off], p1 = tile_start[sc.tile_off + nts];
+  double acc = 0.0;
+  for (int p = p0 + t; p < p1; p += 256)
+    if (act_id[p] == a) acc += (double)sb_part[p];
+  s[t] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) s[t] += s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) gact[b] += s[0];
+}
+
+int launch_sbar_reduce(const DevScene *scenes, const int *act_scene, int n_act,
+                       const int *tile_start, const int *act_id, const float *sb_part,
+                       int dim, double *gact, hipStream_t st) {
+  MPM_LAUNCH(k_sbar_reduce, n_act, 256, st, scenes, act_scene, tile_start, act_id,
+             sb_part, dim, gact);
+}
+
+// Deterministic ranks in a cell at binning: each cell's particles (listed
+// at their atomic rank) are sorted by index, one thread per cell, and the
+// rank becomes the position in that order.
+__global__ __launch_bounds__(256) void k_cell_fill(const int *ptile, const int *pcell,
+                                                   const int *prank, const int *cell_start,
+                                                   int cpt, int N, int *list) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const int tile = ptile[p];
+  if (tile < 0) return;
+  list[cell_start[(int64_t)tile * cpt + pcell[p]] + prank[p]] = p;
+}
+
+__global__ __launch_bounds__(256) void k_cell_sort(const int *cell_start, int n_cells,
+                                                   int *list, int *prank) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_cells) return;
+  const int lo = cell_start[c], hi = cell_start[c + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    const int v = list[i];
+    int k = i - 1;
+    while (k >= lo && list[k] > v) {
+      list[k + 1] = list[k];
+      --k;
+    }
+    list[k + 1] = v;
+  }
+  for (int i = lo; i < hi; ++i) prank[list[i]] = i - lo;
+}
+
+int launch_cell_fill(const int *ptile, const int *pcell, const int *prank,
+                     const int *cell_start, int cpt, int N, int *list, hipStream_t st) {
+  MPM_LAUNCH(k_cell_fill, blocks_for(N), 256, st, ptile, pcell, prank, cell_start, cpt,
+             N, list);
+}
+
+int launch_cell_sort(const int *cell_start, int n_cells, int *list, int *prank,
+                     hipStream_t st) {
+  MPM_LAUNCH(k_cell_sort, blocks_for(n_cells), 256, st, cell_start, n_cells, list, prank);
+}
+
+int launch_adj_gather_scatter(int dim, const AdjFusedArgs &a, int n_tiles, hipStream_t st) {
+  if (dim != 3) return -1;  // the caller only fuses 3D passes
+  if (a.det) MPM_LAUNCH((k_adj_gather_scatter<3, true>), n_tiles, 256, st, a);
+  MPM_LAUNCH((k_adj_gather_scatter<3, false>), n_tiles, 256, st, a);
 }
 
 int launch_adj_gather(int dim, const AdjGatherArgs &a, hipStream_t st) {

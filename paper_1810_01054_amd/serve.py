@@ -1,26 +1,34 @@
-"""Request loop for forward + gradient rollout requests.
+"""Request loop for forward + gradient rollout requests, with continuous
+batching.
 
 Each request is one scene (2D or 3D), a number of substeps T and its
 actuation parameters; serving it means a forward rollout and the reverse
 pass (final state, adjoint of the initial state, actuation gradient).
 
-Scheduling: requests are admitted in arrival order as soon as a slot is free
-and their device-memory footprint fits the budget.  Every admitted request
-gets its own libmpm context on its own HIP stream, so the rollouts of all
-admitted requests are in flight on the device at once and overlap there; a
-request that arrives while others are running starts without waiting for
-them.  Completion is detected with a stream event; latency is measured from
-arrival to completion.  ``fifo=True`` replays the plain one-at-a-time loop.
+Scheduling: `lanes` batch lanes, each with its own HIP stream and host
+thread.  Whenever a lane is free it admits the requests that have arrived
+and are waiting: the oldest one and, in arrival order, every other waiting
+request of the same dimension, up to `max_batch` requests and the
+device-memory budget.  The admitted requests become ONE multi-scene libmpm
+context: every kernel of a substep covers all of them in one launch, each
+scene held fixed past its own T (per-scene horizons), in one rollout of the
+largest T with its reverse pass.  A request that arrives while batches are
+running joins the next batch a lane admits, and the lanes' batches overlap on
+the device.  Completion is detected with a stream event; latency is measured
+from arrival to completion.  If a batch fails (a request left the grid or
+inverted), its requests are served again one by one, so a poisoned request
+fails alone.  ``fifo=True`` replays the plain one-at-a-time loop (one lane,
+batches of one).
 
 Marshalling and scheduling only: the simulation runs in the library.
 """
 from __future__ import annotations
 
-import collections
 import math
+import threading
 import time
-from dataclasses import dataclass, field
-from typing import List, Optional
+from dataclasses import dataclass
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -39,6 +47,7 @@ class Result:
     error: Optional[int] = None
     particles: int = 0
     substeps: int = 0
+    batch: int = 0          # requests in the batch that served it
     xT: Optional[torch.Tensor] = None
     g_v0: Optional[torch.Tensor] = None
     g_act: Optional[torch.Tensor] = None
@@ -49,9 +58,9 @@ class Result:
 
 
 def footprint_bytes(scene: S.Scene, T: int, ckpt_k: int, tile: Optional[int] = None) -> int:
-    """Upper estimate of the device memory one request holds: the context's
-    grids, tile boxes and binning arrays, the tape (checkpoints, segment
-    states, per-substep grids), and the request's own tensors."""
+    """Upper estimate of the device memory one request holds: its share of a
+    context's grids, tile boxes and binning arrays, of the tape
+    (checkpoints, segment states, per-substep grids), and its own tensors."""
     d, n, N = scene.dim, scene.n_grid, scene.n_particles
     B = tile or (8 if d == 2 else 4)
     G = n ** d
@@ -73,18 +82,25 @@ def footprint_bytes(scene: S.Scene, T: int, ckpt_k: int, tile: Optional[int] = N
     return int(1.1 * (ctx + tape + own)) + (8 << 20)
 
 
-class _Slot:
-    def __init__(self, res: Result, sim: Simulator, stream, event, keep, nbytes):
-        self.res, self.sim, self.stream, self.event = res, sim, stream, event
-        self.keep, self.nbytes = keep, nbytes
+def centroid_seed(sc: S.Scene) -> List[np.ndarray]:
+    """dL/dS^T of L = mean_p x_{p,0}^T (centroid x of the final state)."""
+    d, N = sc.dim, sc.n_particles
+    g = [np.zeros((d, N), np.float32), np.zeros((d, N), np.float32),
+         np.zeros((d * d, N), np.float32), np.zeros((d * d, N), np.float32)]
+    g[0][0] = 1.0 / N
+    return g
 
 
 class Server:
-    """Continuous admission of rollout requests onto concurrent streams."""
+    """Continuous batching of rollout requests over `lanes` concurrent
+    batch lanes (see the module docstring)."""
 
-    def __init__(self, max_slots: int = 8, hbm_budget: Optional[int] = None,
-                 ckpt_k: int = 32, keep_results: bool = False, poll_s: float = 2e-4):
-        self.max_slots = max_slots
+    def __init__(self, max_batch: int = 16, lanes: int = 2, hbm_budget: Optional[int] = None,
+                 ckpt_k: int = 32, keep_results: bool = False, poll_s: float = 2e-4,
+                 deterministic: bool = False,
+                 seed_of: Callable[[S.Scene], Sequence[np.ndarray]] = centroid_seed):
+        self.max_batch = max_batch
+        self.lanes = lanes
         if hbm_budget is None:
             free, total = torch.cuda.mem_get_info()
             hbm_budget = int(0.6 * free)
@@ -92,87 +108,130 @@ class Server:
         self.ckpt_k = ckpt_k
         self.keep_results = keep_results
         self.poll_s = poll_s
-        self.streams = [torch.cuda.Stream() for _ in range(max_slots)]
+        self.deterministic = deterministic
+        self.seed_of = seed_of
         self.peak_bytes = 0
+        self.batches: List[List[int]] = []
 
-    def _launch(self, i, req, res: Result, stream) -> _Slot:
-        sc = req.scene
-        nbytes = footprint_bytes(sc, req.T, self.ckpt_k)
+    # -- one batch on one lane -----------------------------------------------
+    def _serve(self, reqs: List[S.Request], idx: List[int], results: List[Result],
+               stream, t0: float):
+        """One multi-scene rollout (forward + reverse) of requests `idx`;
+        raises MPMError if the batch fails."""
+        scs = [reqs[i].scene for i in idx]
+        Ts = [reqs[i].T for i in idx]
+        T = max(Ts)
         dev = torch.device("cuda")
         with torch.cuda.stream(stream):
-            t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(
-                dev, non_blocking=False)
-            sim = Simulator([sc.params()], act_id=sc.act_id, stream=stream)
-            s0 = tuple(t(a) for a in sc.state)
-            act = act_bank_forward(req.T, sc.dt, t(sc.freq), t(sc.amp), t(sc.phase),
-                                   stream=stream)
-            gT = [torch.zeros_like(a) for a in s0]
-            gT[0][0].fill_(1.0 / sc.n_particles)   # L = centroid x of the final state
-            sT, g0, g_act = sim.rollout(s0, act, req.T, self.ckpt_k, tuple(gT))
-            ev = torch.cuda.Event()
-            ev.record(stream)
-        keep = (sT, g0, g_act, s0, act, gT)
-        return _Slot(res, sim, stream, ev, keep, nbytes)
+            t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(dev)
+            sim = Simulator([sc.params() for sc in scs],
+                            act_id=np.concatenate([sc.act_id for sc in scs]),
+                            stream=stream, deterministic=self.deterministic)
+            try:
+                sim.set_horizons(Ts)
+                s0 = tuple(t(np.concatenate([sc.state[c] for sc in scs], axis=1))
+                           for c in range(4))
+                acts = [act_bank_forward(T, sc.dt, t(sc.freq), t(sc.amp), t(sc.phase),
+                                         stream=stream) for sc in scs if sc.n_act > 0]
+                act = torch.cat(acts, dim=1).contiguous() if acts else None
+                seeds = [self.seed_of(sc) for sc in scs]
+                gT = tuple(t(np.concatenate([np.asarray(g[c], np.float32) for g in seeds],
+                                            axis=1)) for c in range(4))
+                sT, g0, g_act = sim.rollout(s0, act, T, self.ckpt_k, gT)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                ev.synchronize()
+                sim.sync_errors()
+                done = time.perf_counter() - t0
+                off = aoff = 0
+                for i, sc in zip(idx, scs):
+                    r = results[i]
+                    r.done = done
+                    r.batch = len(idx)
+                    N, na = sc.n_particles, sc.n_act
+                    if self.keep_results:
+                        r.xT = sT[0][:, off:off + N].clone()
+                        r.g_v0 = g0[1][:, off:off + N].clone()
+                        r.g_act = (None if g_act is None else
+                                   g_act[:reqs[i].T, aoff:aoff + na].clone())
+                    off += N
+                    aoff += na
+            finally:
+                sim.close()
 
-    def _finish(self, sl: _Slot, t0: float):
-        res = sl.res
-        res.done = time.perf_counter() - t0
-        try:
-            sl.sim.sync_errors()
-            if self.keep_results:
-                res.xT = sl.keep[0][0].clone()
-                res.g_v0 = sl.keep[1][1].clone()
-                res.g_act = None if sl.keep[2] is None else sl.keep[2].clone()
-        except MPMError as e:
-            res.error = e.code
-        sl.sim.close()
+    def _lane(self, reqs, results, pending, lock, stream, t0, fifo, state):
+        while True:
+            with lock:
+                if not pending:
+                    return
+                now = time.perf_counter() - t0
+                head = pending[0]
+                if reqs[head].arrival > now:
+                    wait = reqs[head].arrival - now
+                    idx = None
+                else:
+                    # the oldest waiting request, then in arrival order the
+                    # waiting requests of its dimension that fit the budget
+                    dim = reqs[head].scene.dim
+                    idx, nb = [], 0
+                    for i in list(pending):
+                        if reqs[i].arrival > now or len(idx) >= (1 if fifo else self.max_batch):
+                            break
+                        if reqs[i].scene.dim != dim:
+                            continue
+                        fb = footprint_bytes(reqs[i].scene, reqs[i].T, self.ckpt_k)
+                        if idx and state["used"] + nb + fb > self.budget:
+                            break
+                        idx.append(i)
+                        nb += fb
+                    for i in idx:
+                        pending.remove(i)
+                    state["used"] += nb
+                    state["active"] += 1
+                    self.peak_bytes = max(self.peak_bytes, state["used"])
+                    self.batches.append(list(idx))
+            if idx is None:
+                time.sleep(max(0.0, min(self.poll_s, wait)))
+                continue
+            start = time.perf_counter() - t0
+            for i in idx:
+                results[i].start = start
+            try:
+                self._serve(reqs, idx, results, stream, t0)
+            except MPMError:
+                # isolate the failing request(s): serve the batch one by one
+                for i in idx:
+                    try:
+                        self._serve(reqs, [i], results, stream, t0)
+                    except MPMError as e:
+                        results[i].error = e.code
+                        results[i].done = time.perf_counter() - t0
+            with lock:
+                state["used"] -= nb
+                state["active"] -= 1
 
     def run(self, requests: List[S.Request], fifo: bool = False) -> List[Result]:
         """Serve `requests` (arrival times in seconds from the start) in real
         time; returns one Result per request, in request order."""
         results = [Result(i, r.arrival, particles=r.scene.n_particles, substeps=r.T)
                    for i, r in enumerate(requests)]
-        pending = collections.deque(sorted(range(len(requests)),
-                                           key=lambda i: requests[i].arrival))
-        active: List[_Slot] = []
-        free_streams = list(self.streams)
-        used = 0
+        pending = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
+        lock = threading.Lock()
+        state = {"used": 0, "active": 0}
+        lanes = 1 if fifo else self.lanes
+        streams = [torch.cuda.Stream() for _ in range(lanes)]
+        self.batches = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        slots = 1 if fifo else self.max_slots
-        while pending or active:
-            now = time.perf_counter() - t0
-            progressed = False
-            for sl in list(active):
-                if sl.event.query():
-                    self._finish(sl, t0)
-                    active.remove(sl)
-                    free_streams.append(sl.stream)
-                    used -= sl.nbytes
-                    progressed = True
-            while pending and requests[pending[0]].arrival <= now and len(active) < slots:
-                i = pending[0]
-                nb = footprint_bytes(requests[i].scene, requests[i].T, self.ckpt_k)
-                if active and used + nb > self.budget:
-                    break
-                pending.popleft()
-                res = results[i]
-                res.start = time.perf_counter() - t0
-                stream = free_streams.pop()
-                try:
-                    sl = self._launch(i, requests[i], res, stream)
-                except MPMError as e:
-                    res.error = e.code
-                    res.done = time.perf_counter() - t0
-                    free_streams.append(stream)
-                    continue
-                active.append(sl)
-                used += sl.nbytes
-                self.peak_bytes = max(self.peak_bytes, used)
-                progressed = True
-            if not progressed:
-                nxt = requests[pending[0]].arrival - now if pending else self.poll_s
-                time.sleep(max(0.0, min(self.poll_s, nxt)))
+        threads = [threading.Thread(target=self._lane,
+                                    args=(requests, results, pending, lock, streams[k], t0,
+                                          fifo, state))
+                   for k in range(lanes)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
         return results
 
 
@@ -191,8 +250,10 @@ def summarize(results: List[Result], wall: Optional[float] = None) -> dict:
         return lat[lo] + (lat[hi] - lat[lo]) * (k - lo)
 
     pss = sum(r.particles * r.substeps for r in ok)
+    sizes = [r.batch for r in ok if r.batch]
     return {"requests": len(results), "failed": len(results) - len(ok),
             "requests_per_s": len(ok) / span if span > 0 else None,
             "particle_substeps_per_s": pss / span if span > 0 else None,
             "latency_s": {"p50": pct(0.5), "p99": pct(0.99), "max": lat[-1] if lat else None},
+            "mean_batch": float(np.mean(sizes)) if sizes else None,
             "span_s": span}

@@ -56,7 +56,8 @@ class Simulator:
 
     def __init__(self, scenes: Sequence[dict], act_id: Optional[np.ndarray] = None,
                  tile: int = 0, sort: bool = True, scatter: int = 0,
-                 recompute_grids: bool = False, graphs: bool = False, stream=None):
+                 recompute_grids: bool = False, graphs: bool = False, stream=None,
+                 fusion: int = 0, deterministic: bool = False, persistent: bool = False):
         self.L = _lib.lib()
         self.scenes = [dict(s) for s in scenes]
         self.dim = self.scenes[0]["dim"]
@@ -70,6 +71,9 @@ class Simulator:
         opts.tile, opts.sort, opts.scatter = tile, int(bool(sort)), scatter
         opts.recompute_grids = int(bool(recompute_grids))
         opts.graphs = int(bool(graphs))
+        opts.fusion = int(fusion)
+        opts.deterministic = int(bool(deterministic))
+        opts.persistent = int(bool(persistent))
         self.ctx = ctypes.c_void_p()
         self._stream = stream
         check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,
@@ -243,6 +247,19 @@ class Simulator:
         v = torch.empty(self.dim, self.G, device="cuda")
         check(self.L.mpm_get_grid(self.ctx, _ptr(m), _ptr(p), _ptr(v)), "mpm_get_grid")
         return m, p, v
+
+    def set_horizons(self, t_end=None):
+        """mpm_set_horizons: scene s is held fixed from substep t_end[s] on
+        (None removes the horizons)."""
+        if t_end is None:
+            check(self.L.mpm_set_horizons(self.ctx, None), "mpm_set_horizons")
+            return
+        arr = np.ascontiguousarray(t_end, dtype=np.int32)
+        if arr.shape != (len(self.scenes),):
+            raise ValueError(f"t_end needs one entry per scene ({len(self.scenes)})")
+        self._horizons = arr
+        check(self.L.mpm_set_horizons(self.ctx, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "mpm_set_horizons")
 
     def profile(self, kernels=()):
         """Bracket the named kernels (see _lib.KERNELS) with HIP events."""

@@ -1,0 +1,121 @@
+"""Per-scene horizons (mpm_set_horizons): a batch of scenes with different
+lengths in one rollout.  Each scene of the batch, held fixed from its own
+horizon on, must give the state, adjoint and actuation gradient of its own
+rollout of that many substeps: against the oracle's rollout of the scene
+alone (per field, the parity bounds of the other rollouts), with the rows of
+dL/ds past the horizon exactly zero.  2D and 3D (the fused forward kernel
+and, with fusion = 2, the fused reverse), memo, checkpointed and binomial
+tapes; in deterministic mode the batch reproduces each scene run alone bit
+for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1810_01054_amd import scenes as S
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, sim_for, concat_state, check_state
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _scenes(dim):
+    rng = np.random.default_rng(90 + dim)
+    if dim == 2:
+        scs = [S.floor_block(rng, 2, n, N, name=f"h{i}")
+               for i, (n, N) in enumerate([(32, 900), (64, 2500), (32, 1400)])]
+    else:
+        scs = [S.floor_block(rng, 3, n, N, name=f"h{i}")
+               for i, (n, N) in enumerate([(24, 2000), (24, 3500), (16, 900)])]
+    return [S.perturb(sc, 100 + i, v_scale=0.3, C_scale=0.5, F_scale=0.02)
+            for i, sc in enumerate(scs)]
+
+
+def _seed(sc, seed):
+    N, d = sc.n_particles, sc.dim
+    rng = np.random.default_rng(seed)
+    gx = np.zeros((d, N))
+    gx[0] += 1.0 / N
+    gx += rng.normal(size=(d, N)) / N     # makes dL/ds non-trivial
+    return [gx, np.zeros((d, N)), np.zeros((d * d, N)), np.zeros((d * d, N))]
+
+
+def _batch(scs, Ts, k, seeds, **kw):
+    T = max(Ts)
+    acts = [oracle.act_bank_fwd(T, s.dt, s.freq, s.amp, s.phase).astype(np.float32)
+            for s in scs]
+    act = np.concatenate(acts, axis=1)
+    gT = [np.concatenate([g[c] for g in seeds], axis=1).astype(np.float32) for c in range(4)]
+    sim = sim_for(scs, **kw)
+    sim.set_horizons(Ts)
+    sT, g0, gact = sim.rollout(to_gpu(concat_state(scs)), torch.tensor(act, device="cuda"),
+                               T, ckpt_k=k, gT=to_gpu(gT))
+    sim.sync_errors()
+    out = ([t.cpu().numpy() for t in sT], [t.cpu().numpy() for t in g0], gact.cpu().numpy())
+    sim.close()
+    return out, acts
+
+
+def _split(out, scs):
+    sT, g0, gact = out
+    res, off, aoff = [], 0, 0
+    for sc in scs:
+        N, na = sc.n_particles, sc.n_act
+        res.append(([a[:, off:off + N] for a in sT], [a[:, off:off + N] for a in g0],
+                    gact[:, aoff:aoff + na]))
+        off += N
+        aoff += na
+    return res
+
+
+@pytest.mark.parametrize("dim,k,fusion", [(2, 0, 0), (2, 8, 0), (3, 0, 0), (3, 8, 0),
+                                          (3, -3, 0), (3, 8, 2)])
+def test_batch_with_horizons_equals_each_scene_alone(dim, k, fusion):
+    scs = _scenes(dim)
+    Ts = [13, 30, 21]
+    seeds = [_seed(sc, 200 + i) for i, sc in enumerate(scs)]
+    say("horizons", dim, k, fusion, Ts)
+    out, acts = _batch(scs, Ts, k, seeds, fusion=fusion)
+    for sc, T, a, g, (sT, g0, ga) in zip(scs, Ts, acts, seeds, _split(out, scs)):
+        refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                             a[:T].astype(np.float64),
+                                             [x.astype(np.float32).astype(np.float64)
+                                              for x in g])
+        check_state([x.astype(np.float64) for x in sT], refT, 1.0 / sc.n_grid,
+                    label=f"horizon {sc.name} T={T}")
+        for c in range(4):
+            assert err(g0[c], ref0[c]) < GRAD_TOL, (sc.name, "xvCF"[c], err(g0[c], ref0[c]))
+        assert err(ga[:T], ref_act) < GRAD_TOL, (sc.name, err(ga[:T], ref_act))
+        assert not ga[T:].any(), (sc.name, "dL/ds past the horizon")
+
+
+def test_deterministic_batch_equals_each_scene_alone_bit_for_bit():
+    scs = _scenes(2)
+    Ts = [13, 30, 21]
+    seeds = [_seed(sc, 300 + i) for i, sc in enumerate(scs)]
+    say("horizons det")
+    mix = _split(_batch(scs, Ts, 8, seeds, deterministic=True)[0], scs)
+    for i, (sc, T) in enumerate(zip(scs, Ts)):
+        alone = _split(_batch([sc], [T], 8, [seeds[i]], deterministic=True)[0], [sc])[0]
+        for u, v in zip(mix[i][0] + mix[i][1], alone[0] + alone[1]):
+            assert np.array_equal(u.view(np.uint32), v.view(np.uint32)), sc.name
+        assert np.array_equal(mix[i][2][:T].view(np.uint32), alone[2][:T].view(np.uint32))
+
+
+def test_horizon_arguments():
+    from paper_1810_01054_amd._lib import MPMError
+    scs = _scenes(2)
+    sim = sim_for(scs)
+    with pytest.raises(MPMError):
+        sim.set_horizons([5, -1, 3])
+    with pytest.raises(ValueError):
+        sim.set_horizons([5, 3])
+    sim.set_horizons(None)
+    sim.close()

@@ -156,6 +156,30 @@ def test_rollout_c1b_100_steps():
     _rollout_case(S.config_1b(), 100, ks=[0, 32])
 
 
+@pytest.mark.parametrize("fusion", [0, 1, 2])
+def test_rollout_3d_fused_and_separate_kernels(fusion):
+    # 3D binned rollouts: G2P fused with the next P2G (default), every kernel
+    # separate, and also each reverse gather fused with the previous
+    # substep's adjoint scatter.  k = 1 leaves no substep pair to fuse in a
+    # segment, k = 2 one, memo (k = 0) the whole rollout; a ragged last
+    # segment (T = 23, k = 8)
+    sc = S.perturb(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=34), 35, v_scale=0.5,
+                   C_scale=0.5, F_scale=0.02)
+    _rollout_case(sc, 23, ks=[0, 1, 2, 8], fusion=fusion)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rollout_persistent_grid_kernels(dim):
+    # the node-tile grid kernels as persistent workgroups (a fixed number of
+    # one-wave workgroups looping over node tiles): rollouts against the
+    # oracle, and a batch of scenes of several grid sizes
+    if dim == 2:
+        _rollout_case(S.config_1b(), 40, ks=[0, 10], persistent=True)
+    else:
+        _rollout_case(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=39), 20, ks=[0, 8],
+                      persistent=True)
+
+
 @pytest.mark.parametrize("scatter", [1, 2, 3])
 def test_rollout_scatter_modes(scatter):
     # both binned scatter implementations (per-particle LDS atomics, per-cell
