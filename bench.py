@@ -260,7 +260,7 @@ def run_batched(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    from paper_1810_01054_amd.autotune import tune, tune_checkpoint
+    from paper_1810_01054_amd.autotune import tune, tune_checkpoint, tune_rebin
     N = sum(s.n_particles for s in scs)
     ids = np.concatenate([s.act_id for s in scs])
     tuned = tune([s.params() for s in scs], ids, state_of(scs), acts_of(scs), use_cache=False)
@@ -268,6 +268,8 @@ def run_batched(args):
     if args.ckpt_given is None:
         k = tune_checkpoint([s.params() for s in scs], ids, state_of(scs), acts_of(scs), T,
                             tuned, use_cache=False)
+    tuned["rebin"] = tune_rebin([s.params() for s in scs], ids, state_of(scs), acts_of(scs),
+                                T, k, tuned, use_cache=False)
     batched = [make(scs, **tuned)]
     run(batched, 1)
     wb = run(batched, args.steps)
@@ -308,7 +310,8 @@ def run_c2(args):
     with sinusoid banks), T = 1,000 substeps forward + reverse with a
     checkpoint every 64; loss = centroid x of the final state.  Its blocks
     travel several cells, so most particles leave their tile box's slack in
-    the second half of the rollout."""
+    the second half of the rollout; by default the particles are sorted into
+    tiles again at every checkpoint (``--rebin 0``: once per rollout)."""
     import numpy as np
     import torch
 
@@ -316,11 +319,12 @@ def run_c2(args):
     from paper_1810_01054_amd.sim import Simulator, act_bank_forward
 
     sc = S.config_2()
+    rebin = bool(args.rebin if args.rebin is not None else 1)
     T = args.T if args.T != 512 else 1000
     k = args.ckpt_given if args.ckpt_given is not None else 64
     dev = "cuda:0"
     t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
-    sim = Simulator([sc.params()], act_id=sc.act_id, fusion=args.fusion)
+    sim = Simulator([sc.params()], act_id=sc.act_id, fusion=args.fusion, rebin=rebin)
     s0 = tuple(t(a) for a in sc.state)
     act = act_bank_forward(T, sc.dt, t(sc.freq), t(sc.amp), t(sc.phase))
     N = sc.n_particles
@@ -344,8 +348,11 @@ def run_c2(args):
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                       "dtype": "f32", "data": "synthetic",
                       "config": {"workload": f"c2_2d256_98k: 6 blocks, {N} particles, "
-                                             f"T={T} fwd+bwd, checkpoint k={k}",
-                                 "particles": N, "substeps": T, "ckpt_k": k}}), flush=True)
+                                             f"T={T} fwd+bwd, checkpoint k={k}"
+                                             + (", re-binned at every checkpoint"
+                                                if rebin else ""),
+                                 "particles": N, "substeps": T, "ckpt_k": k,
+                                 "rebin": rebin}}), flush=True)
 
 
 def run_serving(args):
@@ -434,6 +441,9 @@ def main():
                     help="c3: 0 = G2P fused with the next P2G (default), 1 = every "
                          "kernel separate, 2 = also the reverse gather fused with the "
                          "previous adjoint scatter")
+    ap.add_argument("--rebin", type=int, default=None, choices=(0, 1),
+                    help="c2/c3: sort the particles into tiles again at every checkpoint "
+                         "(default: on for c2, whose blocks travel, off for c3)")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -488,7 +498,7 @@ def main():
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
     sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter,
-                    fusion=args.fusion)
+                    fusion=args.fusion, rebin=bool(args.rebin))
     t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
     x0, v0, C0, F0 = (t(a) for a in sc.state)
     v0.requires_grad_(True)
@@ -648,6 +658,7 @@ def main():
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
                    "scatter_mode": args.scatter,
                    "fusion": args.fusion,
+                   "rebin": bool(args.rebin),
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),
         # the particle-stream bytes the launched kernels move (launch counts

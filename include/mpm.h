@@ -121,7 +121,16 @@ typedef struct mpm_opts {
                           persistent workgroups (eight one-wave workgroups per
                           CU, each looping over its XCD's share of the node
                           tiles) instead of one workgroup per node tile    */
-  int32_t reserved[2]; /* must be 0                                         */
+  int32_t rebin;       /* 1: sorted rollouts with uniform checkpoints
+                          (1 <= ckpt_k < T) bin the particles again at every
+                          checkpoint (the reverse pass uses each segment's
+                          binning), so particles that travel stay within their
+                          tile box's slack; each re-binning waits for the
+                          device (tile counts), so such rollouts are never
+                          replayed as hipGraphs; ignored with a material field
+                          or a controller (binned once then); 0 = once per
+                          rollout                                            */
+  int32_t reserved[1]; /* must be 0                                         */
 } mpm_opts;
 
 /* Particle state or its adjoint (DEVICE pointers, layout above). */

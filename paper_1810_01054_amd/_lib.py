@@ -37,7 +37,7 @@ class Opts(ctypes.Structure):
                 ("scatter", ctypes.c_int32), ("recompute_grids", ctypes.c_int32),
                 ("graphs", ctypes.c_int32), ("fusion", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("rebin", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class State(ctypes.Structure):

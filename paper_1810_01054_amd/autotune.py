@@ -5,7 +5,8 @@ each candidate launch configuration (binned scatter mode and tile edge,
 persistent grid kernels, G2P fused with the next P2G or not in 3D, hipGraph
 replay) and keeps the one
 with the smallest median time over the repeats; `tune_checkpoint` then times
-the candidate checkpoint intervals k on a longer probe with those options.
+the candidate checkpoint intervals k on a longer probe with those options,
+and `tune_rebin` whether re-binning at every checkpoint pays at that k.
 Results are cached on disk, keyed by GPU architecture, dimension, grid sizes,
 scene count and a particle-count bucket (and, for k, the rollout length), so
 a configuration is measured once per shape class.
@@ -138,3 +139,30 @@ def tune_checkpoint(scenes: Sequence[dict], act_id: np.ndarray, state,
                       "candidates": [kk for _, kk in timings]}
         _store(cache)
     return k
+
+
+def tune_rebin(scenes: Sequence[dict], act_id: np.ndarray, state,
+               act: Optional[torch.Tensor], T: int, k: int, opts: dict,
+               T_probe: int = 512, repeats: int = 3, use_cache: bool = True) -> bool:
+    """Whether to sort the particles into tiles again at every checkpoint
+    (pays when they travel more than a cell per segment, which shows only
+    late in a rollout: the probe is min(T, T_probe) substeps long)."""
+    if k <= 0 or k >= T:
+        return False
+    key = f"{shape_key(scenes)}/T{T}/k{k}/rebin"
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return bool(cache[key]["rebin"])
+    Tp = min(T, T_probe)
+    act_p = None if act is None else act[:Tp].contiguous()
+    gT = tuple(torch.zeros_like(s) for s in state)
+    timings = []
+    for rebin in (False, True):
+        sim = Simulator(scenes, act_id=act_id, **dict(opts, rebin=rebin))
+        timings.append((_median_time(sim, state, act_p, Tp, k, gT, repeats), rebin))
+        sim.close()
+    best = min(timings)[1]
+    if use_cache:
+        cache[key] = {"rebin": best, "ms": [round(t * 1e3, 3) for t, _ in timings]}
+        _store(cache)
+    return best

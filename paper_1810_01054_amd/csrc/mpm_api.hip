@@ -31,6 +31,19 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// One binning of the particles (bin_particles): per-tile counts and ranges,
+// the sorted order with its gather chunks, the non-empty tiles.  perm:
+// sorted position -> caller index; act, pscene: actuator and scene of each
+// sorted particle; rel (re-bins): sorted position -> position in the
+// previous binning's order.
+struct BinSet {
+  int *tile_cnt = nullptr, *tile_start = nullptr, *perm = nullptr, *act = nullptr;
+  int *tile_list = nullptr, *pscene = nullptr, *rel = nullptr;
+  Chunk *chunks = nullptr;
+  int n_chunks = 0, n_ne = 0;
+  bool owned = false;  // buffers allocated for this set (re-bins)
+};
+
 }  // namespace
 
 struct mpm_ctx {
@@ -120,12 +133,19 @@ struct mpm_ctx {
   float *d_part = nullptr;   // tile boxes [n_tiles][d+1][S^d]
   int *d_tile_flag = nullptr, *d_tile_pos = nullptr, *d_tile_list = nullptr;
   int n_tiles_ne = 0;        // non-empty tiles (binned rollouts)
+  // binnings: [0] aliases the buffers above; with re-binning, [j] is the
+  // binning of checkpoint segment j of the current tape
+  std::vector<BinSet> bins;
+  int cur_bin = 0;
+  int rebin = 0;             // re-bin at every checkpoint (uniform tapes)
+  int n_bins = 1;            // binnings of the current tape
 
   // tape
   struct Tape {
     int valid = 0, T = 0, k = 0, memo = 0, sorted = 0, grids_all = 0;
     int rev = 0;              // > 0: binomial checkpointing with rev slots
     int rev_spine = 0;        // its first-descent checkpoints are intact
+    int rebin = 0;            // binned again at every checkpoint (bins[j]: segment j)
     float *states = nullptr;  // slots of one state each
     int64_t state_cap = 0;    // slots allocated
     float *grids = nullptr;   // slots of (1 + d) * G floats (m, p)
@@ -324,14 +344,17 @@ int read_err(mpm_ctx *c) {
 
 // ---- the three kernels of one forward substep ------------------------------
 
+BinSet &bin(mpm_ctx *c) { return c->bins[(size_t)c->cur_bin]; }
+
 TileInfo tile_info(mpm_ctx *c) {
+  const BinSet &b = bin(c);
   TileInfo t;
-  t.cnt = c->d_tile_cnt;
-  t.start = c->d_tile_start;
+  t.cnt = b.tile_cnt;
+  t.start = b.tile_start;
   t.scene = c->d_tile_scene;
   t.part = c->d_part;
   t.B = c->tile;
-  t.list = c->d_tile_list;
+  t.list = b.tile_list;
   t.nt_dirty = c->use_nt ? c->d_nt_dirty : nullptr;
   return t;
 }
@@ -360,7 +383,7 @@ int fwd_p2g(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   a.det = tiles && c->det;
   ProfScope ps(c, MPM_K_P2G);
   if (tiles && c->scatter_mode == 3)
-    return launch_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
+    return launch_p2g_sorted(c->dim, a, bin(c).n_ne, c->stream);
   a.tiles.list = nullptr;  // the other binned modes launch one block per tile
   if (tiles && c->scatter_mode == 2 && !c->has_mat)
     return launch_p2g_cell(c->dim, a, c->d_cell_cnt, c->n_tiles, c->stream);
@@ -379,7 +402,7 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
   a.gv = gv;
   a.G = c->G;
   a.zero_mp = zero_mp;
-  a.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
+  a.tile_cnt = tiles ? bin(c).tile_cnt : nullptr;
   a.part = tiles ? c->d_part : nullptr;
   a.B = c->tile;
   a.out_m = out_m;
@@ -445,7 +468,7 @@ int fwd_g2p_p2g(mpm_ctx *c, CState s, State out, const float *gv,
   a.mat = c->has_mat ? c->mat_sorted : nullptr;  // (binned rollouts only)
   a.det = c->det;
   ProfScope ps(c, MPM_K_G2P_P2G);
-  return launch_g2p_p2g_sorted(c->dim, a, c->n_tiles_ne, c->stream);
+  return launch_g2p_p2g_sorted(c->dim, a, bin(c).n_ne, c->stream);
 }
 
 // ---- the kernels of one reverse substep ------------------------------------
@@ -469,7 +492,7 @@ int bwd_scatter(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
   r1.det = tiles && c->det;
   ProfScope ps(c, MPM_K_ADJ_SCATTER);
   if (tiles && c->scatter_mode == 3)
-    return launch_adj_scatter_sorted(c->dim, r1, c->n_tiles_ne, c->stream);
+    return launch_adj_scatter_sorted(c->dim, r1, bin(c).n_ne, c->stream);
   r1.tiles.list = nullptr;
   if (tiles && c->scatter_mode == 2)
     return launch_adj_scatter_cell(c->dim, r1, c->d_cell_cnt, c->n_tiles, c->stream);
@@ -490,7 +513,7 @@ int bwd_grid(mpm_ctx *c, bool tiles, const float *gm, const float *gp) {
   r2.mbar = c->mbar;
   r2.gv = c->gv;
   r2.G = c->G;
-  r2.tile_cnt = tiles ? c->d_tile_cnt : nullptr;
+  r2.tile_cnt = tiles ? bin(c).tile_cnt : nullptr;
   r2.part = tiles ? c->d_part : nullptr;
   r2.B = c->tile;
   ProfScope ps(c, MPM_K_ADJ_GRID);
@@ -538,7 +561,7 @@ int bwd_gather(mpm_ctx *c, bool tiles, const Chunk *chunks, int n_chunks,
     RC(launch_adj_gather(c->dim, r3, c->stream));
   }
   if (det_s)
-    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, c->d_tile_start,
+    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, bin(c).tile_start,
                           act_id, c->sb_part, c->dim, gact, c->stream));
   return MPM_OK;
 }
@@ -583,10 +606,10 @@ int bwd_gather_scatter(mpm_ctx *c, CState s, CState sp, const int *act_id,
   }
   {
     ProfScope ps(c, MPM_K_ADJ_FUSED);
-    RC(launch_adj_gather_scatter(c->dim, a, c->n_tiles_ne, c->stream));
+    RC(launch_adj_gather_scatter(c->dim, a, bin(c).n_ne, c->stream));
   }
   if (det_s)
-    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, c->d_tile_start,
+    RC(launch_sbar_reduce(c->d_scenes, c->d_act_scene, c->n_act, bin(c).tile_start,
                           act_id, c->sb_part, c->dim, gact, c->stream));
   return MPM_OK;
 }
@@ -602,22 +625,27 @@ int ensure_gact(mpm_ctx *c, int64_t n) {
 
 // ---- binning: sorted order, chunks per tile --------------------------------
 
-int bin_particles(mpm_ctx *c, const float *x) {
+// Bins the particles whose positions are `x` into `dst`.  prev == nullptr:
+// x in the caller's order (the first binning of a tape: the node-tile flags
+// are cleared); otherwise x is in prev's sorted order and dst.rel maps the
+// new order to it.
+int bin_particles(mpm_ctx *c, const float *x, BinSet &dst, const BinSet *prev = nullptr) {
   const int cpt = c->dim == 2 ? c->tile * c->tile : c->tile * c->tile * c->tile;
   hipStream_t s = c->stream;
+  const int N = (int)c->N;
   RC(launch_fill_i32(c->d_cell_cnt, (int64_t)c->n_tiles * cpt, s));
-  RC(launch_fill_i32(c->d_tile_cnt, c->n_tiles, s));
+  RC(launch_fill_i32(dst.tile_cnt, c->n_tiles, s));
   // node tiles flagged by particles beyond their box's slack, for this tape
-  if (c->use_nt) RC(launch_fill_i32(c->d_nt_dirty, c->n_nt, s));
+  if (c->use_nt && !prev) RC(launch_fill_i32(c->d_nt_dirty, c->n_nt, s));
   SortArgs a;
   a.scenes = c->d_scenes;
-  a.pscene = c->d_pscene;
-  a.N = (int)c->N;
+  a.pscene = prev ? prev->pscene : c->d_pscene;
+  a.N = N;
   a.x = x;
-  a.ld = (int)c->N;
+  a.ld = N;
   a.tile = c->tile;
   a.cell_cnt = c->d_cell_cnt;
-  a.tile_cnt = c->d_tile_cnt;
+  a.tile_cnt = dst.tile_cnt;
   a.ptile = c->d_ptile;
   a.pcell = c->d_pcell;
   a.prank = c->d_prank;
@@ -630,60 +658,69 @@ int bin_particles(mpm_ctx *c, const float *x) {
     // ranks in a cell by particle index instead of atomic arrival
     const int64_t ncell = (int64_t)c->n_tiles * cpt;
     RC(launch_scan_i32(c->d_cell_cnt, c->d_cell_start, (int)ncell, s));
-    RC(launch_cell_fill(c->d_ptile, c->d_pcell, c->d_prank, c->d_cell_start, cpt,
-                        (int)c->N, c->d_cell_list, s));
+    RC(launch_cell_fill(c->d_ptile, c->d_pcell, c->d_prank, c->d_cell_start, cpt, N,
+                        c->d_cell_list, s));
     RC(launch_cell_sort(c->d_cell_start, (int)ncell, c->d_cell_list, c->d_prank, s));
   }
-  RC(launch_scan_i32(c->d_tile_cnt, c->d_tile_start, c->n_tiles, s));
-  RC(launch_sort_place(c->dim, a, c->d_tile_start, c->d_perm, s));
-  RC(launch_chunk_count(c->d_tile_cnt, c->n_tiles, c->d_nch, s));
+  RC(launch_scan_i32(dst.tile_cnt, dst.tile_start, c->n_tiles, s));
+  if (prev) {
+    RC(launch_sort_place(c->dim, a, dst.tile_start, dst.rel, s));
+    RC(launch_permute_i32(prev->perm, dst.perm, dst.rel, N, s));
+  } else {
+    RC(launch_sort_place(c->dim, a, dst.tile_start, dst.perm, s));
+  }
+  RC(launch_chunk_count(dst.tile_cnt, c->n_tiles, c->d_nch, s));
   RC(launch_scan_i32(c->d_nch, c->d_chunk_start, c->n_tiles, s));
-  RC(launch_build_chunks(c->d_tile_cnt, c->d_tile_start, c->d_chunk_start,
-                         c->d_tile_scene, c->n_tiles, c->d_chunks_sorted, s));
-  RC(launch_permute_i32(c->d_act_id, c->d_act_sorted, c->d_perm, (int)c->N, s));
+  RC(launch_build_chunks(dst.tile_cnt, dst.tile_start, c->d_chunk_start,
+                         c->d_tile_scene, c->n_tiles, dst.chunks, s));
+  RC(launch_permute_i32(c->d_act_id, dst.act, dst.perm, N, s));
+  if (dst.pscene) RC(launch_permute_i32(c->d_pscene, dst.pscene, dst.perm, N, s));
   if (c->has_mat)
-    RC(launch_permute_rows(c->mat_user, c->mat_sorted, c->d_perm, (int)c->N,
-                           (int)c->N, 3, 0, s));
-  RC(launch_nonempty_flag(c->d_tile_cnt, c->n_tiles, c->d_tile_flag, s));
+    RC(launch_permute_rows(c->mat_user, c->mat_sorted, dst.perm, N, N, 3, 0, s));
+  RC(launch_nonempty_flag(dst.tile_cnt, c->n_tiles, c->d_tile_flag, s));
   RC(launch_scan_i32(c->d_tile_flag, c->d_tile_pos, c->n_tiles, s));
-  RC(launch_compact(c->d_tile_flag, c->d_tile_pos, c->n_tiles, c->d_tile_list, s));
+  RC(launch_compact(c->d_tile_flag, c->d_tile_pos, c->n_tiles, dst.tile_list, s));
   int nch = 0, nne = 0;
   RC(hip_ok(hipMemcpyAsync(&nch, c->d_chunk_start + c->n_tiles, sizeof(int),
                            hipMemcpyDeviceToHost, s)));
   RC(hip_ok(hipMemcpyAsync(&nne, c->d_tile_pos + c->n_tiles, sizeof(int),
                            hipMemcpyDeviceToHost, s)));
   RC(read_err(c));  // synchronises
-  c->n_chunks_sorted = nch;
-  c->n_tiles_ne = nne;
+  dst.n_chunks = nch;
+  dst.n_ne = nne;
   // launch the fullest tiles first: one workgroup per tile takes time
   // roughly in proportion to its particles, and the small tiles then fill
   // the last round of workgroup slots instead of trailing it
   if (nne > 1) {
     std::vector<int> cnt(c->n_tiles), list(nne);
-    RC(hip_ok(hipMemcpyAsync(cnt.data(), c->d_tile_cnt, sizeof(int) * c->n_tiles,
+    RC(hip_ok(hipMemcpyAsync(cnt.data(), dst.tile_cnt, sizeof(int) * c->n_tiles,
                              hipMemcpyDeviceToHost, s)));
-    RC(hip_ok(hipMemcpyAsync(list.data(), c->d_tile_list, sizeof(int) * nne,
+    RC(hip_ok(hipMemcpyAsync(list.data(), dst.tile_list, sizeof(int) * nne,
                              hipMemcpyDeviceToHost, s)));
     RC(hip_ok(hipStreamSynchronize(s)));
     std::stable_sort(list.begin(), list.end(),
                      [&](int a, int b) { return cnt[a] > cnt[b]; });
-    RC(hip_ok(hipMemcpyAsync(c->d_tile_list, list.data(), sizeof(int) * nne,
+    RC(hip_ok(hipMemcpyAsync(dst.tile_list, list.data(), sizeof(int) * nne,
                              hipMemcpyHostToDevice, s)));
     RC(hip_ok(hipStreamSynchronize(s)));  // `list` is host memory
   }
   return MPM_OK;
 }
 
-int permute_state(mpm_ctx *c, const mpm_state &src, State dst, int scatter) {
+int permute_state_by(mpm_ctx *c, const mpm_state &src, State dst, const int *perm,
+                     int scatter) {
   // gather: dst[i] = src[perm[i]];  scatter: dst[perm[i]] = src[i]
   const int d = c->dim, N = (int)c->N;
-  RC(launch_permute_rows(src.x, dst.x, c->d_perm, N, N, d, scatter, c->stream));
-  RC(launch_permute_rows(src.v, dst.v, c->d_perm, N, N, d, scatter, c->stream));
-  RC(launch_permute_rows(src.C, dst.C, c->d_perm, N, N, d * d, scatter,
-                         c->stream));
-  RC(launch_permute_rows(src.F, dst.F, c->d_perm, N, N, d * d, scatter,
-                         c->stream));
+  RC(launch_permute_rows(src.x, dst.x, perm, N, N, d, scatter, c->stream));
+  RC(launch_permute_rows(src.v, dst.v, perm, N, N, d, scatter, c->stream));
+  RC(launch_permute_rows(src.C, dst.C, perm, N, N, d * d, scatter, c->stream));
+  RC(launch_permute_rows(src.F, dst.F, perm, N, N, d * d, scatter, c->stream));
   return MPM_OK;
+}
+
+// between the caller's order and the current binning's
+int permute_state(mpm_ctx *c, const mpm_state &src, State dst, int scatter) {
+  return permute_state_by(c, src, dst, bin(c).perm, scatter);
 }
 
 int copy_state(mpm_ctx *c, const mpm_state &src, State dst) {
@@ -746,15 +783,15 @@ float *slot_grid(mpm_ctx *c, int64_t i) {
 
 const Chunk *cur_chunks(mpm_ctx *c, int *n) {
   if (c->tape.sorted) {
-    *n = c->n_chunks_sorted;
-    return c->d_chunks_sorted;
+    *n = bin(c).n_chunks;
+    return bin(c).chunks;
   }
   *n = c->n_chunks_user;
   return c->d_chunks_user;
 }
 
 const int *cur_act_id(mpm_ctx *c) {
-  return c->tape.sorted ? c->d_act_sorted : c->d_act_id;
+  return c->tape.sorted ? bin(c).act : c->d_act_id;
 }
 
 // forward state S^n for the rollout (ckpt mode; n is a checkpoint or lives in
@@ -773,7 +810,8 @@ float *fwd_slot(mpm_ctx *c, const Layout &L, int n) {
 template <typename F>
 int run_maybe_graph(mpm_ctx *c, mpm_ctx::GraphSlot &slot,
                     const mpm_ctx::GraphKey &key, F &&body) {
-  if (!c->use_graphs || c->prof.mask || c->tape.T == 0) return body();
+  // (re-binning synchronises with the host: never captured)
+  if (!c->use_graphs || c->prof.mask || c->tape.T == 0 || c->tape.rebin) return body();
   if (!slot.valid || !(slot.key == key)) {
     if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
     slot.exec = nullptr;
@@ -814,7 +852,7 @@ mpm_ctx::GraphKey graph_key(mpm_ctx *c) {
   int nch = 0;
   k.p[6] = cur_chunks(c, &nch);
   k.nch = nch;
-  k.nne = c->n_tiles_ne;
+  k.nne = bin(c).n_ne;
   k.p[0] = t.states;
   k.p[1] = t.grids;
   k.p[2] = t.act;
@@ -1016,12 +1054,46 @@ int ctl_adjoint(mpm_ctx *c, int n, const double *sbar, const State &g) {
   return launch_ctl_adjoint(a, c->stream) ? MPM_ERR_HIP : MPM_OK;
 }
 
+// Binning sets 1 .. n-1 for re-binned tapes (allocated once, kept).
+int ensure_bins(mpm_ctx *c, int n) {
+  const int64_t N = std::max<int64_t>(c->N, 1), nt = c->n_tiles;
+  while ((int)c->bins.size() < n) {
+    BinSet b;
+    b.owned = true;
+    RC(dmalloc(&b.tile_cnt, nt, c->stream));
+    RC(dmalloc(&b.tile_start, nt + 1, c->stream));
+    RC(dmalloc(&b.perm, N, c->stream));
+    RC(dmalloc(&b.act, N, c->stream));
+    RC(dmalloc(&b.tile_list, nt, c->stream));
+    RC(dmalloc(&b.pscene, N, c->stream));
+    RC(dmalloc(&b.rel, N, c->stream));
+    RC(dmalloc(&b.chunks, N / CH + nt + 1, c->stream));
+    c->bins.push_back(b);
+  }
+  return MPM_OK;
+}
+
+// Re-binning at checkpoint j: `slot` holds S^{jk} in binning j-1's order;
+// binning j is computed from its positions and the state is put into the
+// new order in place (through the scratch state).
+int rebin_at(mpm_ctx *c, int j, float *slot) {
+  BinSet &dst = c->bins[(size_t)j];
+  RC(bin_particles(c, state_at(c, slot).x, dst, &c->bins[(size_t)j - 1]));
+  const State tmp = state_at(c, c->scratch);
+  RC(permute_state_by(c, ms(state_at(c, slot)), tmp, dst.rel, 0));
+  RC(copy_state(c, ms(tmp), state_at(c, slot)));
+  c->cur_bin = j;
+  c->n_bins = j + 1;
+  return MPM_OK;
+}
+
 int rollout_forward(mpm_ctx *c, const Layout &L) {
   if (c->tape.rev) return rollout_forward_revolve(c, L.T);
   int nch = 0;
   const Chunk *chunks = cur_chunks(c, &nch);
   const int *ids = cur_act_id(c);
   const bool tiles = c->tape.sorted;
+  const bool rebin = c->tape.rebin != 0;
   // 3D binned rollouts with the sorted scatter fuse each G2P with the next
   // substep's P2G (state n+1 goes from registers to the scatter)
   // (not with a closed-loop controller: the actuation of substep n+1 needs
@@ -1034,12 +1106,19 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };
   for (int n = 0; n < L.T; ++n) {
+    // re-binned tapes: every checkpoint starts a new binning
+    const bool new_bin = rebin && n > 0 && n % L.k == 0;
+    if (new_bin) {
+      RC(rebin_at(c, n / L.k, fwd_slot(c, L, n)));
+      chunks = cur_chunks(c, &nch);
+      ids = cur_act_id(c);
+    }
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
     // the controller's component sums of state n come from the G2P that
     // produced it (substep 0: their own kernel)
     if (c->ctl.on) RC(ctl_forward(c, s, n, n > 0 ? nch : 0));
-    if (!fuse || n == 0)
+    if (!fuse || n == 0 || new_bin)
       RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp, n));
     if (c->tape.grids_all) {
       float *g = slot_grid(c, n);  // keep this substep's grid on the tape
@@ -1047,7 +1126,7 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
     } else {
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
-    if (fuse && n + 1 < L.T) {
+    if (fuse && n + 1 < L.T && !(rebin && (n + 1) % L.k == 0)) {
       // state n+1 is read back only through x and F unless the tape keeps
       // it (memo, or a checkpoint)
       RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1),
@@ -1068,7 +1147,14 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
 }
 
 // Reverse pass over library-owned buffers only: reads the adjoint of S^T
-// from adj slot 0, leaves the adjoint of S^0 in adj slot (T & 1).
+// from adj slot 0, leaves the adjoint of S^0 in adj slot adj_out_slot(c).
+// (one swap of the two adjoint slots per substep and, on re-binned tapes,
+// one per change of binning)
+int adj_out_slot(const mpm_ctx *c) {
+  const auto &t = c->tape;
+  return (t.T + (t.rebin ? c->n_bins - 1 : 0)) & 1;
+}
+
 int rollout_backward_core(mpm_ctx *c) {
   auto &t = c->tape;
   const Layout L{t.T, t.k, t.memo, t.memo ? t.T + 1 : (t.T + t.k - 1) / t.k + 1};
@@ -1117,13 +1203,21 @@ int rollout_backward_core(mpm_ctx *c) {
   auto Gr = [&](int n0, int n) -> float * {
     return t.grids_all ? slot_grid(c, n) : slot_grid(c, n - n0);
   };
+  // re-binned tapes: segment j's states are in binning j's order
+  auto seg_chunks = [&](int j, int *n) -> const Chunk * {
+    if (!t.rebin) return cur_chunks(c, n);
+    *n = c->bins[(size_t)j].n_chunks;
+    return c->bins[(size_t)j].chunks;
+  };
   // recompute segment j's states from its checkpoint with G2P alone,
   // reading each substep's stored grid
   auto recompute = [&](int j, hipStream_t st) -> int {
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
+    int nc = 0;
+    const Chunk *ch = seg_chunks(j, &nc);
     for (int n = n0; n + 1 < n1; ++n) {
       const float *g = Gr(n0, n);
-      RC(fwd_g2p(c, chunks, nch, cs(state_at(c, S(j, n))), state_at(c, S(j, n + 1)),
+      RC(fwd_g2p(c, ch, nc, cs(state_at(c, S(j, n))), state_at(c, S(j, n + 1)),
                  nullptr, g, g + c->G, st, false, n));
     }
     return MPM_OK;
@@ -1145,6 +1239,11 @@ int rollout_backward_core(mpm_ctx *c) {
   }
   for (int j = nseg - 1; j >= 0; --j) {
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
+    if (t.rebin) {
+      c->cur_bin = j;
+      chunks = cur_chunks(c, &nch);
+      ids = cur_act_id(c);
+    }
     if (overlap) {
       // segment j's states are ready; start segment j-1's recompute once the
       // adjoint of segment j+1 (same bank) is done
@@ -1203,6 +1302,11 @@ int rollout_backward_core(mpm_ctx *c) {
         std::swap(A0, A1);
       }
     }
+    if (t.rebin && j > 0) {
+      // the adjoint of S^{n0} from binning j's order into binning j-1's
+      RC(permute_state_by(c, ms(A1), A0, c->bins[(size_t)j].rel, 1));
+      std::swap(A0, A1);
+    }
     if (overlap) RC(hip_ok(hipEventRecord(c->ev_adj, c->stream)));
   }
   return MPM_OK;
@@ -1213,6 +1317,8 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   auto &t = c->tape;
   const int64_t sf = c->state_floats();
   const State A_in = state_at(c, t.adj);
+  // the seed is put into the order of the last binning of the tape
+  if (t.rebin) c->cur_bin = c->n_bins - 1;
   if (t.sorted) RC(permute_state(c, *gT, A_in, 0));
   else RC(copy_state(c, *gT, A_in));
   const int64_t nga = (int64_t)t.T * c->n_act;
@@ -1221,7 +1327,8 @@ int rollout_backward(mpm_ctx *c, const mpm_state *gT, mpm_state *g0,
   t.rev_spine = 0;  // (outside the captured body: replays skip the body)
   c->gmat_sorted = t.sorted;
   c->gmat_valid = c->has_mat;
-  const State A_out = state_at(c, t.adj + (t.T & 1) * sf);
+  c->cur_bin = 0;
+  const State A_out = state_at(c, t.adj + adj_out_slot(c) * sf);
   if (t.sorted) RC(permute_state(c, ms(A_out), st(*g0), 1));
   else RC(copy_state(c, ms(A_out), st(*g0)));
   if (g_act && nga > 0)
@@ -1298,6 +1405,18 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_tile_flag, c->stream);
   dfree(c->d_tile_pos, c->stream);
   dfree(c->d_tile_list, c->stream);
+  for (auto &b : c->bins) {
+    dfree(b.pscene, c->stream);
+    if (!b.owned) continue;
+    dfree(b.tile_cnt, c->stream);
+    dfree(b.tile_start, c->stream);
+    dfree(b.perm, c->stream);
+    dfree(b.act, c->stream);
+    dfree(b.tile_list, c->stream);
+    dfree(b.rel, c->stream);
+    dfree(b.chunks, c->stream);
+  }
+  c->bins.clear();
   dfree(c->d_nt_scene, c->stream);
   dfree(c->d_nt_dirty, c->stream);
   dfree(c->d_cell_start, c->stream);
@@ -1334,11 +1453,14 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   int fusion = 0;
   int det = 0;
   int persistent = 0;
+  int rebin = 0;
   if (opts) {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 1; ++k)
       if (opts->reserved[k]) return MPM_ERR_ARG;
     if (opts->persistent != 0 && opts->persistent != 1) return MPM_ERR_ARG;
     persistent = opts->persistent;
+    if (opts->rebin != 0 && opts->rebin != 1) return MPM_ERR_ARG;
+    rebin = opts->rebin;
     if (opts->fusion < 0 || opts->fusion > 2) return MPM_ERR_ARG;
     fusion = opts->fusion;
     if (opts->deterministic != 0 && opts->deterministic != 1) return MPM_ERR_ARG;
@@ -1382,6 +1504,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   c->keep_grids = !recompute_grids;
   c->use_graphs = graphs;
   c->persistent = persistent;
+  c->rebin = rebin;
   c->fuse_forward = fusion != 1;
   c->fuse_reverse = fusion == 2;
   {
@@ -1492,6 +1615,17 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   TRY(dmalloc(&c->d_tile_flag, n_tiles, c->stream));
   TRY(dmalloc(&c->d_tile_pos, n_tiles + 1, c->stream));
   TRY(dmalloc(&c->d_tile_list, n_tiles, c->stream));
+  {
+    BinSet b0;
+    b0.tile_cnt = c->d_tile_cnt;
+    b0.tile_start = c->d_tile_start;
+    b0.perm = c->d_perm;
+    b0.act = c->d_act_sorted;
+    b0.tile_list = c->d_tile_list;
+    b0.chunks = c->d_chunks_sorted;
+    if (c->rebin) TRY(dmalloc(&b0.pscene, std::max<int64_t>(N, 1), c->stream));
+    c->bins.assign(1, b0);
+  }
   c->n_nt = (int)ntoff;
   c->use_nt = c->scatter_mode == 3 && c->n_nt > 0;
   if (c->use_nt) {
@@ -1908,13 +2042,20 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   t.rev = rev;
   t.grids_all = grids_all;
   t.sorted = c->sort && c->N > 0;
+  // re-binning at every checkpoint: checkpointed tapes of binned rollouts
+  // without a controller (its component sums follow one order) or a
+  // per-particle material field (sorted once per tape)
+  t.rebin = c->rebin && t.sorted && !memo && !rev && k < T && !ctl && !c->has_mat;
+  if (t.rebin) RC(ensure_bins(c, (T + k - 1) / k));
   if (!ctl && c->n_act && T > 0)
     RC(hip_ok(hipMemcpyAsync(t.act, act, sizeof(float) * T * c->n_act,
                              hipMemcpyDeviceToDevice, c->stream)));
   const Layout L{T, k, memo, ncp};
   const State S0 = state_at(c, slot_state(c, 0));
   if (t.sorted) {
-    RC(bin_particles(c, s0->x));
+    c->cur_bin = 0;
+    c->n_bins = 1;
+    RC(bin_particles(c, s0->x, c->bins[0]));
     RC(permute_state(c, *s0, S0, 0));
   } else {
     RC(copy_state(c, *s0, S0));

@@ -57,7 +57,8 @@ class Simulator:
     def __init__(self, scenes: Sequence[dict], act_id: Optional[np.ndarray] = None,
                  tile: int = 0, sort: bool = True, scatter: int = 0,
                  recompute_grids: bool = False, graphs: bool = False, stream=None,
-                 fusion: int = 0, deterministic: bool = False, persistent: bool = False):
+                 fusion: int = 0, deterministic: bool = False, persistent: bool = False,
+                 rebin: bool = False):
         self.L = _lib.lib()
         self.scenes = [dict(s) for s in scenes]
         self.dim = self.scenes[0]["dim"]
@@ -74,6 +75,7 @@ class Simulator:
         opts.fusion = int(fusion)
         opts.deterministic = int(bool(deterministic))
         opts.persistent = int(bool(persistent))
+        opts.rebin = int(bool(rebin))
         self.ctx = ctypes.c_void_p()
         self._stream = stream
         check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,

@@ -57,7 +57,7 @@ def seeds(shape_state, seed):
 # Final state of a rollout (up to ~100 substeps) against the oracle: bound on
 # err() per field (normwise and per element, relative to the field's largest
 # magnitude) and on the largest position error in grid cells.  Positions
-# follow the benchmark spec's bound (1e-5 after 100 substeps).  The FP32 velocity
+# follow the required bound (1e-5 after 100 substeps).  The FP32 velocity
 # and affine matrix come out of 3^d-node weighted sums of grid velocities
 # (v_i = p_i / m_i with cancellation in p_i), and C' = (4/dx^2) sum N v_i
 # (x_i - x_p) differences node velocities across a cell: each substep's

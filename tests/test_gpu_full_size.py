@@ -10,7 +10,7 @@ the largest per-element error relative to the field's largest magnitude.
 
 The benchmark's own scene (unperturbed C3, checkpoint every 32 substeps with
 recompute) is also compared over 100 substeps forward and backward, the
-horizon of the benchmark spec's bounds (positions 1e-5, gradients 1e-3)."""
+horizon of the required bounds (positions 1e-5, gradients 1e-3)."""
 import time
 
 import numpy as np

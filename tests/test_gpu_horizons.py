@@ -4,9 +4,9 @@ horizon on, must give the state, adjoint and actuation gradient of its own
 rollout of that many substeps: against the oracle's rollout of the scene
 alone (per field, the parity bounds of the other rollouts), with the rows of
 dL/ds past the horizon exactly zero.  2D and 3D (the fused forward kernel
-and, with fusion = 2, the fused reverse), memo, checkpointed and binomial
-tapes; in deterministic mode the batch reproduces each scene run alone bit
-for bit."""
+and, with fusion = 2, the fused reverse), memo, checkpointed (also
+re-binned at every checkpoint) and binomial tapes; in deterministic mode the
+batch reproduces each scene run alone bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -75,14 +75,15 @@ def _split(out, scs):
     return res
 
 
-@pytest.mark.parametrize("dim,k,fusion", [(2, 0, 0), (2, 8, 0), (3, 0, 0), (3, 8, 0),
-                                          (3, -3, 0), (3, 8, 2)])
-def test_batch_with_horizons_equals_each_scene_alone(dim, k, fusion):
+@pytest.mark.parametrize("dim,k,fusion,rebin", [
+    (2, 0, 0, False), (2, 8, 0, False), (3, 0, 0, False), (3, 8, 0, False),
+    (3, -3, 0, False), (3, 8, 2, False), (2, 8, 0, True), (3, 8, 0, True)])
+def test_batch_with_horizons_equals_each_scene_alone(dim, k, fusion, rebin):
     scs = _scenes(dim)
     Ts = [13, 30, 21]
     seeds = [_seed(sc, 200 + i) for i, sc in enumerate(scs)]
-    say("horizons", dim, k, fusion, Ts)
-    out, acts = _batch(scs, Ts, k, seeds, fusion=fusion)
+    say("horizons", dim, k, fusion, rebin, Ts)
+    out, acts = _batch(scs, Ts, k, seeds, fusion=fusion, rebin=rebin)
     for sc, T, a, g, (sT, g0, ga) in zip(scs, Ts, acts, seeds, _split(out, scs)):
         refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
                                              a[:T].astype(np.float64),

@@ -7,8 +7,8 @@ Tolerances (normwise relative error, ||gpu - oracle|| / ||oracle||):
     adjoints involve differences of nearly equal node values (x_i - x_p is
     O(dx) while x is O(1), so cancellation costs up to log2(n) bits), which
     the 2e-5 bound covers with a margin of ~10x at n = 256;
-  * positions after 100 substeps: 1e-5 (the north-star bound);
-  * gradients (one step or a whole rollout): 1e-3 (the benchmark spec's bound).
+  * positions after 100 substeps: 1e-5 (the required bound);
+  * gradients (one step or a whole rollout): 1e-3 (the required bound).
 """
 import numpy as np
 import pytest

@@ -1,0 +1,160 @@
+"""Re-binning at every checkpoint (mpm_opts.rebin): checkpointed tapes of
+binned rollouts sort the particles into tiles again at each checkpoint
+(segment j runs in its own order; the reverse pass carries the state adjoint
+from one order to the previous at every segment boundary).  The scenes drift
+several cells over the rollout, so later segments bin differently from the
+first.  Every case is held to the oracle (final state, adjoint of the
+initial state, dL/ds) and to the same rollout without re-binning; a ragged
+last segment, the fused reverse kernel, persistent grid kernels, a deferred
+reverse pass run twice and deterministic mode (bit for bit) are covered."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1810_01054_amd import scenes as S
+from tests.helpers import oscene, f64, err
+from tests.gpu_helpers import require_gpu, say, to_gpu, sim_for, check_state
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _drifting(dim):
+    """A block moving along +x: about 11 cells over 60 substeps (2D, 64^2)
+    or 4.5 cells over 30 substeps (3D, 24^3), with random v, C, F on top."""
+    if dim == 2:
+        sc, vx, T = S.config_1b(), 30.0, 60
+    else:
+        sc, vx, T = S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=36), 60.0, 30
+    sc = S.perturb(sc, 5, v_scale=0.3, C_scale=0.5, F_scale=0.02)
+    sc.v[0] += np.float32(vx)
+    return sc, T
+
+
+def _seed(sc, seed):
+    N, d = sc.n_particles, sc.dim
+    rng = np.random.default_rng(seed)
+    gx = np.zeros((d, N))
+    gx[0] += 1.0 / N
+    gx += rng.normal(size=(d, N)) / N
+    return (gx.astype(np.float32), np.zeros((d, N), np.float32),
+            np.zeros((d * d, N), np.float32), np.zeros((d * d, N), np.float32))
+
+
+def _acts(sc, T):
+    return oracle.act_bank_fwd(T, sc.dt, sc.freq, sc.amp, sc.phase).astype(np.float32)
+
+
+def _run(sim, sc, acts, T, k, gT):
+    sT, g0, gact = sim.rollout(to_gpu(sc.state), torch.tensor(acts, device="cuda"), T,
+                               ckpt_k=k, gT=to_gpu(gT))
+    sim.sync_errors()
+    return [t.detach().cpu().numpy() for t in (*sT, *g0, gact)]
+
+
+def _oracle_check(sc, acts, T, gT, out, label):
+    refT, ref0, ref_act = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                                         acts.astype(np.float64), f64(gT))
+    check_state([o.astype(np.float64) for o in out[:4]], refT, 1.0 / sc.n_grid, label=label)
+    for c in range(4):
+        assert err(out[4 + c], ref0[c]) < GRAD_TOL, (label, "xvCF"[c], err(out[4 + c], ref0[c]))
+    assert err(out[8], ref_act) < GRAD_TOL, (label, err(out[8], ref_act))
+    return ref0, ref_act
+
+
+def test_drift_moves_particles_out_of_their_first_tiles():
+    """The scenes below really re-bin: the oracle's final positions are
+    several cells from the initial ones (more than the tile boxes' slack)."""
+    for dim in (2, 3):
+        sc, T = _drifting(dim)
+        xT = oracle.rollout(oscene(sc), f64(sc.state), T, sc.act_id,
+                            _acts(sc, T).astype(np.float64))[0]
+        moved = (xT[0] - sc.x[0]) * sc.n_grid
+        assert np.median(moved) > (8.0 if dim == 2 else 3.0), (dim, np.median(moved))
+
+
+@pytest.mark.parametrize("dim,k,opts", [
+    (2, 16, {}),                                   # 4 segments, last one 12
+    (2, 7, {"persistent": True}),                  # 9 segments, last one 4
+    (3, 8, {}),                                    # 4 segments, last one 6
+    (3, 8, {"fusion": 2}),
+    (3, 5, {"fusion": 1, "persistent": True}),
+])
+def test_rebinned_rollout_matches_oracle_and_plain_rollout(dim, k, opts):
+    sc, T = _drifting(dim)
+    acts = _acts(sc, T)
+    gT = _seed(sc, 80 + dim)
+    say("rebin", dim, k, opts)
+    sim = sim_for(sc, rebin=True, **opts)
+    out = _run(sim, sc, acts, T, k, gT)
+    sim.close()
+    _oracle_check(sc, acts, T, gT, out, f"rebin {dim}d k={k} {opts}")
+    say("no rebin", dim, k, opts)
+    plain_sim = sim_for(sc, **opts)
+    plain = _run(plain_sim, sc, acts, T, k, gT)
+    plain_sim.close()
+    # both within the oracle's bounds; against each other, the binning only
+    # changes the order of the FP32 sums
+    check_state([o.astype(np.float64) for o in out[:4]],
+                [p.astype(np.float64) for p in plain[:4]], 1.0 / sc.n_grid,
+                label="rebin vs plain")
+    for c in range(5):
+        assert err(out[4 + c], plain[4 + c]) < GRAD_TOL, ("vs plain", c)
+
+
+# Bitwise comparisons need sums in a fixed order: deterministic mode, and
+# segments short enough that no particle leaves its tile box's slack (one
+# cell) before the next re-binning (2D: at most 0.2 cells per substep,
+# 3D: 0.15), where no float atomics remain.
+BITWISE_K = {2: 5, 3: 6}
+
+
+def test_rebinned_tape_reverse_pass_twice_and_memo_unchanged():
+    """A deferred reverse pass over a re-binned tape, run twice, gives the
+    same bits as the one inside the rollout call; memo tapes and k >= T
+    (one segment) ignore the option."""
+    sc, T = _drifting(3)
+    acts = _acts(sc, T)
+    gT = _seed(sc, 90)
+    sim = sim_for(sc, rebin=True, deterministic=True)
+    say("rebin deferred reverse")
+    out = _run(sim, sc, acts, T, BITWISE_K[3], gT)
+    _oracle_check(sc, acts, T, gT, out, "rebin det deferred")
+    for rep in range(2):
+        g0, gact = sim.rollout_backward(to_gpu(gT), T)
+        sim.sync_errors()
+        for a, b in zip(out[4:], [t.cpu().numpy() for t in (*g0, gact)]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), rep
+    say("rebin memo / k=T")
+    for k in (0, T):
+        o = _run(sim, sc, acts, T, k, gT)
+        _oracle_check(sc, acts, T, gT, o, f"rebin option, k={k}")
+    sim.close()
+
+
+def test_deterministic_rebinned_rollouts_repeat_bit_for_bit():
+    sc, T = _drifting(2)
+    acts = _acts(sc, T)
+    gT = _seed(sc, 91)
+    say("rebin det")
+    k = BITWISE_K[2]
+    sim = sim_for(sc, rebin=True, deterministic=True)
+    a = _run(sim, sc, acts, T, k, gT)
+    b = _run(sim, sc, acts, T, k, gT)
+    for i, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), i
+    # graphs requested: re-binned tapes run eagerly, with the same bits
+    other = sim_for(sc, rebin=True, deterministic=True, graphs=True)
+    c = _run(other, sc, acts, T, k, gT)
+    for i, (x, y) in enumerate(zip(a, c)):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), ("graphs", i)
+    _oracle_check(sc, acts, T, gT, a, "rebin det")
+    sim.close()
+    other.close()
