@@ -151,6 +151,63 @@ __device__ __forceinline__ void bspline_dw(float f, float inv_dx, float *dw) {
   dw[2] = (f - 0.5f) * inv_dx;
 }
 
+// G2P stencil sums of one 3D particle (section III, G2P), taken axis by axis:
+// vn = sum_o N(o) v_o and Bm[a][b] = sum_o N(o) v_o,a (o_b - f_b) with
+// N(o) = w[0][o0] w[1][o1] w[2][o2].  Summing along axis 2, then 1, then 0,
+// each node velocity enters six multiply-adds (sixteen when every node forms
+// N(o) v_o (o - f)^T).  vel(o0, o1, o2, v) fetches the velocity of node
+// base + o; the outer axis stays a loop (nine node fetches in flight).  Every
+// 3D G2P uses this one summation order, so a state recomputed from the tape
+// equals the forward pass's bit for bit.
+template <typename Vel>
+__device__ __forceinline__ void g2p_sums3(const float (&w)[3][3], const float *f,
+                                          Vel &&vel, float *vn, float (&Bm)[3][3]) {
+  float wd1[3], wd2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    wd1[k] = w[1][k] * ((float)k - f[1]);
+    wd2[k] = w[2][k] * ((float)k - f[2]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vn[a] = 0.0f;
+    Bm[a][0] = Bm[a][1] = Bm[a][2] = 0.0f;
+  }
+#pragma unroll 1
+  for (int o0 = 0; o0 < 3; ++o0) {
+    float Y0[3] = {}, Y1[3] = {}, Y2[3] = {};
+#pragma unroll
+    for (int o1 = 0; o1 < 3; ++o1) {
+      float Z0[3] = {}, Z2[3] = {};
+#pragma unroll
+      for (int o2 = 0; o2 < 3; ++o2) {
+        float v[3];
+        vel(o0, o1, o2, v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Z0[a] += w[2][o2] * v[a];
+          Z2[a] += wd2[o2] * v[a];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        Y0[a] += w[1][o1] * Z0[a];
+        Y1[a] += wd1[o1] * Z0[a];
+        Y2[a] += w[1][o1] * Z2[a];
+      }
+    }
+    const float wx = o0 == 0 ? w[0][0] : (o0 == 1 ? w[0][1] : w[0][2]);
+    const float wdx = wx * ((float)o0 - f[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vn[a] += wx * Y0[a];
+      Bm[a][0] += wdx * Y0[a];
+      Bm[a][1] += wx * Y1[a];
+      Bm[a][2] += wx * Y2[a];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // workgroup bounding box of stencil bases
 // ---------------------------------------------------------------------------
@@ -1548,7 +1605,7 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
   using SC = SortedCell<D>;
   constexpr int S = SC::S, SV = SC::SV, BC = SC::BC, B = SC::B;
   __shared__ SortedCellSmem<D, D + 1, 2, true, PM, DET> sm;
-  __shared__ float s_v[D * SV];
+  __shared__ float4 s_v[SV];  // node-major grid velocities of the tile box
   const int tile = A.tiles.list ? A.tiles.list[blockIdx.x] : blockIdx.x;
   if (A.tiles.cnt[tile] == 0) return;
   const DevScene sc = A.scenes[A.tiles.scene[tile]];
@@ -1559,8 +1616,8 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
     const bool in = g[0] >= 0 && g[0] < sc.n && g[1] >= 0 && g[1] < sc.n &&
                     g[2] >= 0 && g[2] < sc.n;
     const int64_t gi = sc.g_off + ((int64_t)g[0] * sc.n + g[1]) * sc.n + g[2];
-#pragma unroll
-    for (int a = 0; a < D; ++a) s_v[a * SV + i] = in ? A.gv[a * A.G + gi] : 0.0f;
+    s_v[i] = in ? make_float4(A.gv[gi], A.gv[A.G + gi], A.gv[2 * A.G + gi], 0.0f)
+                : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   // (the scatter synchronises before its record step reads s_v)
   // past the scene's horizon (substep n >= t_end) state n is carried over
@@ -1606,42 +1663,38 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
         float w0[D][3];
 #pragma unroll
         for (int a = 0; a < D; ++a) bspline_w(f0[a], w0[a]);
-        float vn[D] = {}, Bm[D * D] = {};  // sum N v_i, sum N v_i (o - f)^T
-#pragma unroll 1
-        for (int o0 = 0; o0 < 3; ++o0)
+        float vn[D], Bm[D][D];  // sum N v_i, sum N v_i (o - f)^T
+        // every lane of the wave inside the box (the common case): LDS only
+        if (__all(inb)) {
+          g2p_sums3(w0, f0, [&](int o0, int o1, int o2, float *v) {
+            const float4 n4 = s_v[lbase + (o0 * S + o1) * S + o2];
+            v[0] = n4.x;
+            v[1] = n4.y;
+            v[2] = n4.z;
+          }, vn, Bm);
+        } else {
+          g2p_sums3(w0, f0, [&](int o0, int o1, int o2, float *v) {
+            if (inb) {
+              const float4 n4 = s_v[lbase + (o0 * S + o1) * S + o2];
+              v[0] = n4.x;
+              v[1] = n4.y;
+              v[2] = n4.z;
+            } else {
+              const int64_t gi = gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2;
 #pragma unroll
-          for (int o1 = 0; o1 < 3; ++o1) {
-            const float w01 = w0[0][o0] * w0[1][o1];
-#pragma unroll
-            for (int o2 = 0; o2 < 3; ++o2) {
-              const float N = w01 * w0[2][o2];
-              const float d[3] = {(float)o0 - f0[0], (float)o1 - f0[1], (float)o2 - f0[2]};
-              float vi[3];
-              if (inb) {
-                const int li = lbase + (o0 * S + o1) * S + o2;
-#pragma unroll
-                for (int a = 0; a < D; ++a) vi[a] = s_v[a * SV + li];
-              } else {
-                const int64_t gi = gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2;
-#pragma unroll
-                for (int a = 0; a < D; ++a) vi[a] = A.gv[a * A.G + gi];
-              }
-#pragma unroll
-              for (int a = 0; a < D; ++a) {
-                const float Nv = N * vi[a];
-                vn[a] += Nv;
-#pragma unroll
-                for (int b = 0; b < D; ++b) Bm[a * D + b] += Nv * d[b];
-              }
+              for (int a = 0; a < D; ++a) v[a] = A.gv[a * A.G + gi];
             }
-          }
+          }, vn, Bm);
+        }
         load_mat<D>(A.s.F, A.ld, p, F);
         // C' = (4/dx^2) sum N v_i (x_i - x_p)^T; F' = (I + dt C') F;
         // x' = x + dt v'
         const float cs = sc.Dinv * sc.dx;
         float Cn[D * D], Fn[D * D], xn[D];
 #pragma unroll
-        for (int k = 0; k < D * D; ++k) Cn[k] = cs * Bm[k];
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) Cn[a * D + b] = cs * Bm[a][b];
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -2162,7 +2215,8 @@ __device__ __forceinline__ void ctl_wave_add(int c, const float *val8, float *ro
 // next substep only reduces the rows.
 template <int D, bool CTL>
 __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
-  __shared__ float s_v[D * LDS_NODES];
+  // staged node velocities: planes in 2D, node-major float4 in 3D
+  __shared__ float s_v[D == 3 ? 4 * LDS_NODES : D * LDS_NODES];
   __shared__ float s_ctl[CTL ? 4 : 1][CTL ? CTL_MAX_NZS : 1];
   const int chunk = xcd_block_id();
   const Chunk ch = A.chunks[chunk];
@@ -2213,8 +2267,12 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
     for (int i = t; i < box.vol; i += CH) {
       float v[D];
       vel(box_node<D>(box, i, sc.n), v);
+      if constexpr (D == 3) {
+        reinterpret_cast<float4 *>(s_v)[i] = make_float4(v[0], v[1], v[2], 0.0f);
+      } else {
 #pragma unroll
-      for (int a = 0; a < D; ++a) s_v[a * LDS_NODES + i] = v[a];
+        for (int a = 0; a < D; ++a) s_v[a * LDS_NODES + i] = v[a];
+      }
     }
     __syncthreads();
   }
@@ -2264,37 +2322,24 @@ __global__ __launch_bounds__(CH) void k_g2p(G2PArgs A) {
         }
       }
   } else {
-    // the outer stencil row stays a loop: nine LDS records in flight instead
-    // of 27 keeps the kernel at five waves per SIMD
-#pragma unroll 1
-    for (int o0 = 0; o0 < 3; ++o0)
+    float Bm[3][3];
+    if (box.lds) {  // (uniform over the workgroup)
+      const float4 *s4 = reinterpret_cast<const float4 *>(s_v);
+      g2p_sums3(w, f, [&](int o0, int o1, int o2, float *v) {
+        const float4 n4 = s4[lbase + (o0 * box.e[1] + o1) * box.e[2] + o2];
+        v[0] = n4.x;
+        v[1] = n4.y;
+        v[2] = n4.z;
+      }, vn, Bm);
+    } else {
+      g2p_sums3(w, f, [&](int o0, int o1, int o2, float *v) {
+        vel((int)(gbase - sc.g_off) + (o0 * sc.n + o1) * sc.n + o2, v);
+      }, vn, Bm);
+    }
 #pragma unroll
-      for (int o1 = 0; o1 < 3; ++o1) {
-        const float w01 = w[0][o0] * w[1][o1];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int o2 = 0; o2 < 3; ++o2) {
-          const float N = w01 * w[2][o2];
-          const float d0 = (float)o0 - f[0], d1 = (float)o1 - f[1],
-                      d2 = (float)o2 - f[2];
-          float vi[3];
-          if (box.lds) {
-            const int li = lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
-            vi[0] = s_v[li];
-            vi[1] = s_v[LDS_NODES + li];
-            vi[2] = s_v[2 * LDS_NODES + li];
-          } else {
-            vel((int)(gbase - sc.g_off) + (o0 * sc.n + o1) * sc.n + o2, vi);
-          }
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const float Nv = N * vi[a];
-            vn[a] += Nv;
-            B[a * 3 + 0] += Nv * d0;
-            B[a * 3 + 1] += Nv * d1;
-            B[a * 3 + 2] += Nv * d2;
-          }
-        }
-      }
+      for (int b = 0; b < 3; ++b) B[a * 3 + b] = Bm[a][b];
   }
   // F is loaded after the stencil loop so it is not live across it
   float F[D * D];

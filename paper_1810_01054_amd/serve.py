@@ -180,16 +180,22 @@ class Server:
                         if reqs[i].scene.dim != dim:
                             continue
                         fb = footprint_bytes(reqs[i].scene, reqs[i].T, self.ckpt_k)
-                        if idx and state["used"] + nb + fb > self.budget:
+                        # a request larger than the whole budget still runs,
+                        # alone, once nothing else holds memory
+                        if state["used"] + nb + fb > self.budget and (idx or state["used"] > 0):
                             break
                         idx.append(i)
                         nb += fb
-                    for i in idx:
-                        pending.remove(i)
-                    state["used"] += nb
-                    state["active"] += 1
-                    self.peak_bytes = max(self.peak_bytes, state["used"])
-                    self.batches.append(list(idx))
+                    if not idx:
+                        # the oldest request waits for memory to free up
+                        idx, wait = None, self.poll_s
+                    else:
+                        for i in idx:
+                            pending.remove(i)
+                        state["used"] += nb
+                        state["active"] += 1
+                        self.peak_bytes = max(self.peak_bytes, state["used"])
+                        self.batches.append(list(idx))
             if idx is None:
                 time.sleep(max(0.0, min(self.poll_s, wait)))
                 continue
