@@ -669,6 +669,36 @@ __device__ __forceinline__ void tile_origin(int lt, int nt, int *org) {
   }
 }
 
+// Position in a stored box plane of box node i (node-major, last axis
+// fastest).  A 3D box of a 4^3-cell tile (8^3 nodes) is stored as 2 x 2 x 2
+// blocks of 4^3 nodes, each block contiguous: box u spans the node tiles u
+// and u+1 of the grid kernels per axis, so the nodes a grid-kernel wave takes
+// from one box are one whole block (256 contiguous bytes per channel).
+// Other boxes are stored node-major.
+template <int D, int B>
+__device__ __forceinline__ int box_pos(int i) {
+  if constexpr (D == 3 && B == 4) {
+    const int l0 = i >> 6, l1 = (i >> 3) & 7, l2 = i & 7;
+    const int blk = ((l0 >> 2) * 2 + (l1 >> 2)) * 2 + (l2 >> 2);
+    return (blk << 6) | (((l0 & 3) * 4 + (l1 & 3)) * 4 + (l2 & 3));
+  } else {
+    return i;
+  }
+}
+// The box node stored at position j (inverse of box_pos).
+template <int D, int B>
+__device__ __forceinline__ int box_node_at(int j) {
+  if constexpr (D == 3 && B == 4) {
+    const int blk = j >> 6, r = j & 63;
+    const int l0 = ((blk >> 2) & 1) * 4 + (r >> 4);
+    const int l1 = ((blk >> 1) & 1) * 4 + ((r >> 2) & 3);
+    const int l2 = (blk & 1) * 4 + (r & 3);
+    return (l0 * 8 + l1) * 8 + l2;
+  } else {
+    return j;
+  }
+}
+
 // Tile version (binned particles): one workgroup per tile, LDS accumulation,
 // whole box stored with plain coalesced stores; particles whose stencil left
 // the box add to the grid with global atomics.
@@ -723,7 +753,8 @@ __global__ __launch_bounds__(256) void k_p2g_tile(P2GArgs A) {
   if (eb) atomicOr(A.err, eb);
   __syncthreads();
   float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
-  for (int i = t; i < (D + 1) * SV; i += 256) dst[i] = s_grid[i];
+  for (int i = t; i < (D + 1) * SV; i += 256)
+    dst[i] = s_grid[(i / SV) * SV + box_node_at<D, B>(i % SV)];
 }
 
 // ---------------------------------------------------------------------------
@@ -858,7 +889,7 @@ __device__ __forceinline__ void cell_scatter_wave(const Args &A,
     MPM_LDS_ORDER();
   }
   float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
-  for (int i = lane; i < NCH * SV; i += 64) dst[i] = box[i];
+  for (int i = lane; i < NCH * SV; i += 64) dst[i] = box[(i / SV) * SV + box_node_at<D, B>(i % SV)];
 }
 
 // Sorted per-cell scatter (drift-proof).  One workgroup (4 waves) per tile.
@@ -1313,7 +1344,8 @@ __device__ __forceinline__ void sorted_cell_scatter(
   float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
   if constexpr (V4) {
     for (int i = t; i < SV; i += 256) {
-      const float4 a = reinterpret_cast<const float4 *>(sm.box)[box_slot<true>(i)];
+      const float4 a =
+          reinterpret_cast<const float4 *>(sm.box)[box_slot<true>(box_node_at<D, B>(i))];
       dst[i] = a.x;
       dst[SV + i] = a.y;
       if constexpr (NCH > 2) dst[2 * SV + i] = a.z;
@@ -1321,7 +1353,7 @@ __device__ __forceinline__ void sorted_cell_scatter(
     }
   } else {
     for (int i = t; i < NCH * SV; i += 256)
-      dst[i] = sm.box[(i / SV) * SV + box_slot<false>(i % SV)];
+      dst[i] = sm.box[(i / SV) * SV + box_slot<false>(box_node_at<D, B>(i % SV))];
   }
 }
 
@@ -1834,7 +1866,7 @@ __device__ __forceinline__ bool add_tile_boxes(const DevScene &sc, int li,
     // line for the whole wave, value dropped below): no branch, and no HBM
     // traffic for boxes that no kernel wrote
     const float *bx =
-        part + (cnt[k] != 0 ? ((int64_t)tile[k] * nch + c_lo) * SV + loc[k] : 0);
+        part + (cnt[k] != 0 ? ((int64_t)tile[k] * nch + c_lo) * SV + box_pos<D, B>(loc[k]) : 0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) val[k][c] = bx[c * SV];
   }
@@ -2137,7 +2169,7 @@ __device__ __forceinline__ void grid_nt_item(const GridArgs &A, int ntg) {
 #pragma unroll
   for (int k = 0; k < NodeTile<D, B>::K; ++k)
     if (nt.nz[k] && nt.cov[k]) {
-      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + nt.loc[k];
+      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + box_pos<D, B>(nt.loc[k]);
 #pragma unroll
       for (int c = 0; c <= D; ++c) val[k][c] = bx[c * SV];
     }
@@ -2510,7 +2542,8 @@ __global__ __launch_bounds__(256) void k_adj_scatter_tile(AdjScatterArgs A) {
   if (eb) atomicOr(A.err, eb);
   __syncthreads();
   float *dst = A.tiles.part + (int64_t)tile * (D + 1) * SV;
-  for (int i = t; i < D * SV; i += 256) dst[i] = s_grid[i];
+  for (int i = t; i < D * SV; i += 256)
+    dst[i] = s_grid[(i / SV) * SV + box_node_at<D, B>(i % SV)];
 }
 
 // ---------------------------------------------------------------------------
@@ -2599,7 +2632,7 @@ __device__ __forceinline__ void adj_grid_nt_item(const AdjGridArgs &A, int ntg) 
 #pragma unroll
   for (int k = 0; k < NodeTile<D, B>::K; ++k)
     if (nt.nz[k] && nt.cov[k]) {
-      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + nt.loc[k];
+      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + box_pos<D, B>(nt.loc[k]);
 #pragma unroll
       for (int c = 0; c < D; ++c) val[k][c] = bx[c * SV];
     }
