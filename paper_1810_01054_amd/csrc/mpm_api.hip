@@ -796,11 +796,23 @@ const int *cur_act_id(mpm_ctx *c) {
 
 // forward state S^n for the rollout (ckpt mode; n is a checkpoint or lives in
 // the ping-pong pair)
+// First substep of the last segment of a checkpointed tape.
+int last_seg_start(const Layout &L) { return L.T > 0 ? ((L.T - 1) / L.k) * L.k : 0; }
+
+// Checkpointed tapes with stored grids keep the states of their last
+// segment from the forward pass (its own bank, 2): the reverse pass starts
+// on it at once instead of first recomputing it.
+bool keeps_last_segment(const mpm_ctx *c, const Layout &L, int n) {
+  return c->tape.grids_all && !L.memo && !c->tape.rev && n > last_seg_start(L) && n < L.T;
+}
+
 float *fwd_slot(mpm_ctx *c, const Layout &L, int n) {
   if (c->tape.rev) return slot_state(c, n == L.T && n > 0 ? c->tape.rev + 2 : 0);
   if (L.memo) return slot_state(c, n);
   if (n % L.k == 0) return slot_state(c, n / L.k);
   if (n == L.T) return slot_state(c, L.ncp - 1);
+  if (keeps_last_segment(c, L, n))
+    return slot_state(c, L.ncp + 2 * (int64_t)L.k + (n - last_seg_start(L)));
   return c->tape.pp + (int64_t)(n & 1) * c->state_floats();
 }
 
@@ -1130,7 +1142,7 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
       // state n+1 is read back only through x and F unless the tape keeps
       // it (memo, or a checkpoint)
       RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1),
-                     L.memo || (n + 1) % L.k == 0, n));
+                     L.memo || (n + 1) % L.k == 0 || keeps_last_segment(c, L, n + 1), n));
     } else if (c->det && c->tape.grids_all) {
       // deterministic mode: the velocities are rebuilt from the stored
       // (m, p) exactly as the reverse pass's recompute does, so a
@@ -1192,12 +1204,13 @@ int rollout_backward_core(mpm_ctx *c) {
                     !c->has_mat && c->fuse_reverse;
   // state n of segment j (segment states alternate between two banks when
   // the grids are kept, so one segment can be recomputed while the adjoint
-  // of the next one runs)
+  // of the next one runs; the last segment's states, kept by the forward
+  // pass, are in a third bank)
   auto S = [&](int j, int n) -> float * {
     const int n0 = j * seglen;
     if (t.memo) return slot_state(c, n);
     if (n == n0) return slot_state(c, j);
-    const int64_t bank = keep ? (j & 1) : 0;
+    const int64_t bank = keep ? (j == nseg - 1 ? 2 : (j & 1)) : 0;
     return slot_state(c, L.ncp + bank * t.k + (n - n0));
   };
   auto Gr = [&](int n0, int n) -> float * {
@@ -1212,6 +1225,7 @@ int rollout_backward_core(mpm_ctx *c) {
   // recompute segment j's states from its checkpoint with G2P alone,
   // reading each substep's stored grid
   auto recompute = [&](int j, hipStream_t st) -> int {
+    if (j == nseg - 1) return MPM_OK;  // kept by the forward pass
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
     int nc = 0;
     const Chunk *ch = seg_chunks(j, &nc);
@@ -2030,10 +2044,11 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   const int k = memo || rev ? 1 : std::min(ckpt_k, std::max(T, 1));
   const int ncp = rev ? rev + 3 : memo ? T + 1 : (T + k - 1) / k + 1;
   const int grids_all = !rev && (memo || c->keep_grids);
-  // checkpointed tapes with stored grids keep two banks of segment states:
-  // the reverse pass recomputes one segment while it runs the adjoint of
-  // the next; binomial tapes hold rev + 3 states and one grid
-  const int64_t nstates = rev ? ncp : memo ? T + 1 : ncp + (grids_all ? 2 * k : k);
+  // checkpointed tapes with stored grids keep three banks of segment
+  // states: two for the reverse pass, which recomputes one segment while it
+  // runs the adjoint of the next, and one for the last segment, kept by the
+  // forward pass; binomial tapes hold rev + 3 states and one grid
+  const int64_t nstates = rev ? ncp : memo ? T + 1 : ncp + (grids_all ? 3 * k : k);
   const int64_t ngrids = rev ? 1 : grids_all ? T : k;
   RC(ensure_tape(c, nstates, ngrids, (int64_t)T * c->n_act));
   t.T = T;

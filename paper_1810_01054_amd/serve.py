@@ -75,7 +75,7 @@ def footprint_bytes(scene: S.Scene, T: int, ckpt_k: int, tile: Optional[int] = N
            + tiles * (d + 1) * S_ ** d * 4)  # tile boxes
     k = max(1, min(ckpt_k, T)) if ckpt_k > 0 else 1
     ncp = (T + k - 1) // k + 1 if ckpt_k > 0 else T + 1
-    tape = ((ncp + (2 * k if ckpt_k > 0 else 0) + 4) * state
+    tape = ((ncp + (3 * k if ckpt_k > 0 else 0) + 4) * state
             + T * (1 + d) * G * 4
             + T * max(scene.n_act, 1) * 12)
     own = 5 * state + T * max(scene.n_act, 1) * 8
