@@ -441,6 +441,10 @@ def main():
                     help="c3: 0 = G2P fused with the next P2G (default), 1 = every "
                          "kernel separate, 2 = also the reverse gather fused with the "
                          "previous adjoint scatter")
+    ap.add_argument("--drift", type=float, default=0.0,
+                    help="c3: add this x-velocity (domain units per second) to every "
+                         "particle, so the body travels across cells and tiles during "
+                         "the rollout (1.0: 3.3 cells over 512 substeps)")
     ap.add_argument("--rebin", type=int, default=None, choices=(0, 1),
                     help="c2/c3: sort the particles into tiles again at every checkpoint "
                          "(default: on for c2, whose blocks travel, off for c3)")
@@ -466,7 +470,7 @@ def main():
     ctrl = args.workload == "c3ctrl"
     cpu = None
     if (args.workload == "c3" and args.cpu_sample > 0 and args.friction is None
-            and not args.materials):
+            and not args.materials and not args.drift):
         # the oracle first, while no process has touched the GPU (its
         # all-cores leg forks one worker per host core)
         cpu = cpu_baseline(sc, args.cpu_sample, max(1, args.cpu_sample // 2))
@@ -495,6 +499,8 @@ def main():
 
     if args.friction is not None:
         sc.bc, sc.friction = 1, float(np.float32(args.friction))
+    if args.drift:
+        sc.v[0, :] += np.float32(args.drift)
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
     sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter,
@@ -659,6 +665,7 @@ def main():
                    "scatter_mode": args.scatter,
                    "fusion": args.fusion,
                    "rebin": bool(args.rebin),
+                   "drift_vx": args.drift,
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),
         # the particle-stream bytes the launched kernels move (launch counts

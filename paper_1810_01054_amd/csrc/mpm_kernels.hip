@@ -537,19 +537,31 @@ __device__ __forceinline__ bool p2g_particle_m(const P2GArgs &A,
 
 // Per-particle adjoint-scatter quantities (supplement (A)-(C)):
 // vt + (4/dx^2) Ct (x_i - x_p) = c0 + sum_b Cdx[.][b] o_b.
+// The streams the adjoint scatter reads for particle p: F^n and the adjoint
+// of state n+1.
+template <int D>
+struct AdjScatterIn {
+  float F[D * D], gx[D], gv[D], gC[D * D], gF[D * D];
+};
+template <int D>
+__device__ __forceinline__ void adj_scatter_load(const AdjScatterArgs &A, int p,
+                                                 AdjScatterIn<D> &in) {
+  load_mat<D>(A.s.F, A.ld, p, in.F);
+  load_vec<D>(A.g1.x, A.ld, p, in.gx);
+  load_vec<D>(A.g1.v, A.ld, p, in.gv);
+  load_mat<D>(A.g1.C, A.ld, p, in.gC);
+  load_mat<D>(A.g1.F, A.ld, p, in.gF);
+}
+
 template <int D>
 __device__ __forceinline__ void adj_scatter_particle(const AdjScatterArgs &A,
                                                      const DevScene &sc,
-                                                     int p, const float *f,
+                                                     const AdjScatterIn<D> &in,
+                                                     const float *f,
                                                      float (&w)[D][3],
                                                      float *c0,
                                                      float (&Cdx)[D][D]) {
-  float F[D * D], gx[D], gv[D], gC[D * D], gF[D * D];
-  load_mat<D>(A.s.F, A.ld, p, F);
-  load_vec<D>(A.g1.x, A.ld, p, gx);
-  load_vec<D>(A.g1.v, A.ld, p, gv);
-  load_mat<D>(A.g1.C, A.ld, p, gC);
-  load_mat<D>(A.g1.F, A.ld, p, gF);
+  const float *F = in.F, *gx = in.gx, *gv = in.gv, *gC = in.gC, *gF = in.gF;
   float vt[D], Ct[D * D];
   // (A): dL/dv^{n+1} total = carried + dt dL/dx^{n+1}
 #pragma unroll
@@ -935,7 +947,8 @@ struct SortedCellSmem {
   static constexpr int SV = SortedCell<D>::SV;
   static constexpr int MW = PER * 8;  // mask words per cell
   float box[V4 ? 4 * SV : NCH * SV];
-  float rec[(SortedCell<D>::REC + (PM ? 1 : 0)) * PER * 256];  // field-major, swizzled slots
+  float rec[(SortedCell<D>::REC + (PM ? 1 : 0)) * PER * 256];  // field-major
+  short sidx[PER * 256];  // record slot of each sorted position (swizzled positions)
   int cnt[256];
   int off[256];
   short order[256];  // the tile's own cells, then the occupied ring cells
@@ -1036,10 +1049,10 @@ __device__ __forceinline__ int box_slot(int li) {
 // acc at offsets W, W+4, ...
 template <int D, int NCH, bool HAS_MASS, int W, bool PM = false>
 __device__ __forceinline__ void cell_offsets_sum(const float *rec, int NR,
-                                                 int o, int n, float mp,
-                                                 float *acc) {
+                                                 const short *sidx, int o, int n,
+                                                 float mp, float *acc) {
   for (int k = 0; k < n; ++k) {
-    const int ps = rec_slot(o + k);
+    const int ps = sidx ? (int)sidx[rec_slot(o + k)] : rec_slot(o + k);
     float w[D][3], c0[D], L[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -1159,10 +1172,13 @@ __device__ __forceinline__ void sorted_cell_scatter(
   }
   unsigned eb = 0;
   __syncthreads();
+  // non-split: each record goes to LDS slot h * 256 + t as soon as it is
+  // built (no record stays in registers across the batch) and the sorted
+  // order is an index of those slots
+  const short *sidx = SPLIT ? nullptr : sm.sidx;
   for (int b0 = 0; b0 < cnt; b0 += PER * 256) {
     // 1. records, cells and ranks of up to PER particles per thread
     int lc[PER], rank[PER];
-    float rec[SPLIT ? 1 : PER][RECP];
     if constexpr (SPLIT) {
 #pragma unroll
       for (int h = 0; h < PER; ++h) {
@@ -1209,14 +1225,15 @@ __device__ __forceinline__ void sorted_cell_scatter(
       }
       if (inbox) {
         lc[h] = D == 2 ? l[0] * BC + l[1] : (l[0] * BC + l[1]) * BC + l[2];
+        const int us = h * 256 + t;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          rec[h][a] = f[a];
-          rec[h][D + a] = c0[a];
+          sm.rec[a * NR + us] = f[a];
+          sm.rec[(D + a) * NR + us] = c0[a];
 #pragma unroll
-          for (int b = 0; b < D; ++b) rec[h][2 * D + a * D + b] = L[a][b];
+          for (int b = 0; b < D; ++b) sm.rec[(2 * D + a * D + b) * NR + us] = L[a][b];
         }
-        if constexpr (PM) rec[h][REC] = mpp;
+        if constexpr (PM) sm.rec[REC * NR + us] = mpp;
         if constexpr (DET) det_mark<MW>(sm.mask, lc[h], h * 256 + t);
         else rank[h] = atomicAdd(&sm.cnt[lc[h]], 1);
       } else {
@@ -1286,12 +1303,8 @@ __device__ __forceinline__ void sorted_cell_scatter(
       }
     } else {
 #pragma unroll
-      for (int h = 0; h < PER; ++h) {
-        if (lc[h] < 0) continue;
-        const int ps = rec_slot(sm.off[lc[h]] + rank[h]);
-#pragma unroll
-        for (int k = 0; k < RECP; ++k) sm.rec[k * NR + ps] = rec[h][k];
-      }
+      for (int h = 0; h < PER; ++h)
+        if (lc[h] >= 0) sm.sidx[rec_slot(sm.off[lc[h]] + rank[h])] = (short)(h * 256 + t);
     }
     __syncthreads();
     // 3. per-cell sums of this wave's offsets, then the waves' read-add-write
@@ -1306,10 +1319,10 @@ __device__ __forceinline__ void sorted_cell_scatter(
 #pragma unroll
       for (int k = 0; k < NQ * NCH; ++k) acc[k] = 0.0f;
       switch (wave) {
-        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
-        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
-        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
-        default: cell_offsets_sum<D, NCH, HAS_MASS, 3, PM>(sm.rec, NR, o, n, sc.mp, acc); break;
+        case 0: cell_offsets_sum<D, NCH, HAS_MASS, 0, PM>(sm.rec, NR, sidx, o, n, sc.mp, acc); break;
+        case 1: cell_offsets_sum<D, NCH, HAS_MASS, 1, PM>(sm.rec, NR, sidx, o, n, sc.mp, acc); break;
+        case 2: cell_offsets_sum<D, NCH, HAS_MASS, 2, PM>(sm.rec, NR, sidx, o, n, sc.mp, acc); break;
+        default: cell_offsets_sum<D, NCH, HAS_MASS, 3, PM>(sm.rec, NR, sidx, o, n, sc.mp, acc); break;
       }
       int cc[D];
       {
@@ -1605,7 +1618,9 @@ __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
         A, tile, sm, nullptr, A.vbar,
         [&](int p, const float *, const float *f, float (&w)[D][3], float *c0,
             float (&L)[D][D], unsigned &) {
-          adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+          AdjScatterIn<D> in;
+          adj_scatter_load<D>(A, p, in);
+          adj_scatter_particle<D>(A, sc, in, f, w, c0, L);
           return true;
         });
   } else {
@@ -1614,10 +1629,14 @@ __global__ __launch_bounds__(256) void k_adj_scatter_sorted(AdjScatterArgs A) {
         A, tile, sm, nullptr, A.vbar,
         [&](int p, int *base, float *f, float (&w)[D][3], float *c0,
             float (&L)[D][D], unsigned &eb) {
+          // all of the particle's streams requested at once (one HBM
+          // round trip instead of two)
           float xp[D];
+          AdjScatterIn<D> in;
           load_vec<D>(A.s.x, A.ld, p, xp);
+          adj_scatter_load<D>(A, p, in);
           if (!stencil_base<D>(xp, sc, base, f, eb)) return false;
-          adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+          adj_scatter_particle<D>(A, sc, in, f, w, c0, L);
           return true;
         });
   }
@@ -1673,10 +1692,10 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
           return false;
         }
         load_vec<D>(A.s.x, A.ld, p, x);
+        load_mat<D>(A.s.F, A.ld, p, F);
         if (!stencil_base<D>(x, sc, b0, f0, eb)) {
           // keep state n+1 defined (the rollout reports the error)
           float z[D * D] = {};
-          load_mat<D>(A.s.F, A.ld, p, F);
           store_vec<D>(A.out.x, A.ld, p, x);
           store_vec<D>(A.out.v, A.ld, p, z);
           store_mat<D>(A.out.C, A.ld, p, z);
@@ -1718,7 +1737,6 @@ __global__ __launch_bounds__(256, 3) void k_g2p_p2g_sorted(G2P2GArgs A) {
             }
           }, vn, Bm);
         }
-        load_mat<D>(A.s.F, A.ld, p, F);
         // C' = (4/dx^2) sum N v_i (x_i - x_p)^T; F' = (I + dt C') F;
         // x' = x + dt v'
         const float cs = sc.Dinv * sc.dx;
@@ -1806,7 +1824,9 @@ __global__ __launch_bounds__(256) void k_adj_scatter_cell(AdjScatterArgs A,
       [&](int p, const float *, const int *, const float *f, float (&w)[D][3],
           float *c0, float (&L)[D][D], unsigned &) {
         const DevScene sc = A.scenes[A.tiles.scene[tile]];
-        adj_scatter_particle<D>(A, sc, p, f, w, c0, L);
+        AdjScatterIn<D> in;
+        adj_scatter_load<D>(A, p, in);
+        adj_scatter_particle<D>(A, sc, in, f, w, c0, L);
         return true;
       });
 }
@@ -2446,7 +2466,11 @@ __global__ __launch_bounds__(CH) void k_adj_scatter(AdjScatterArgs A) {
   }
   const Box<D> box = chunk_box<D>(ok, base);
   float w[D][3], c0[D], Cdx[D][D];
-  if (ok) adj_scatter_particle<D>(A, sc, p, f, w, c0, Cdx);
+  if (ok) {
+    AdjScatterIn<D> in;
+    adj_scatter_load<D>(A, p, in);
+    adj_scatter_particle<D>(A, sc, in, f, w, c0, Cdx);
+  }
   if (box.lds) {
     for (int i = t; i < D * LDS_NODES; i += CH) s_grid[i] = 0.0f;
     __syncthreads();
@@ -2511,10 +2535,12 @@ __global__ __launch_bounds__(256) void k_adj_scatter_tile(AdjScatterArgs A) {
     const int p = start + j;
     float xp[D], f[D];
     int base[D];
+    AdjScatterIn<D> in;
     load_vec<D>(A.s.x, A.ld, p, xp);
+    adj_scatter_load<D>(A, p, in);
     if (!stencil_base<D>(xp, sc, base, f, eb)) continue;
     float w[D][3], c0[D], Cdx[D][D];
-    adj_scatter_particle<D>(A, sc, p, f, w, c0, Cdx);
+    adj_scatter_particle<D>(A, sc, in, f, w, c0, Cdx);
     int l[D];
     bool inbox = true;
 #pragma unroll
