@@ -319,7 +319,7 @@ def run_c2(args):
     from paper_1810_01054_amd.sim import Simulator, act_bank_forward
 
     sc = S.config_2()
-    rebin = bool(args.rebin if args.rebin is not None else 1)
+    rebin = int(args.rebin if args.rebin is not None else 1)
     T = args.T if args.T != 512 else 1000
     k = args.ckpt_given if args.ckpt_given is not None else 64
     dev = "cuda:0"
@@ -445,9 +445,11 @@ def main():
                     help="c3: add this x-velocity (domain units per second) to every "
                          "particle, so the body travels across cells and tiles during "
                          "the rollout (1.0: 3.3 cells over 512 substeps)")
-    ap.add_argument("--rebin", type=int, default=None, choices=(0, 1),
+    ap.add_argument("--rebin", type=int, default=None, choices=(0, 1, 2),
                     help="c2/c3: sort the particles into tiles again at every checkpoint "
-                         "(default: on for c2, whose blocks travel, off for c3)")
+                         "(1), or at the checkpoints where more than 1%% of the last "
+                         "segment's particle-substeps overflowed their tile boxes (2); "
+                         "default: 1 for c2, whose blocks travel, 0 for c3")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -504,7 +506,7 @@ def main():
     T, k = args.T, args.ckpt
     N, d = sc.n_particles, sc.dim
     sim = Simulator([sc.params()], act_id=sc.act_id, scatter=args.scatter,
-                    fusion=args.fusion, rebin=bool(args.rebin))
+                    fusion=args.fusion, rebin=int(args.rebin or 0))
     t = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
     x0, v0, C0, F0 = (t(a) for a in sc.state)
     v0.requires_grad_(True)
@@ -664,7 +666,7 @@ def main():
                    "particles": N, "grid": "64^3", "substeps": T, "ckpt_k": k,
                    "scatter_mode": args.scatter,
                    "fusion": args.fusion,
-                   "rebin": bool(args.rebin),
+                   "rebin": int(args.rebin or 0),
                    "drift_vx": args.drift,
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),

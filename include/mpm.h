@@ -125,11 +125,14 @@ typedef struct mpm_opts {
                           (1 <= ckpt_k < T) bin the particles again at every
                           checkpoint (the reverse pass uses each segment's
                           binning), so particles that travel stay within their
-                          tile box's slack; each re-binning waits for the
-                          device (tile counts), so such rollouts are never
-                          replayed as hipGraphs; ignored with a material field
-                          or a controller (binned once then); 0 = once per
-                          rollout                                            */
+                          tile box's slack; 2: at the checkpoints where more
+                          than 1% of the last segment's particle-substeps
+                          scattered beyond their tile box's slack (global
+                          atomics; the count is read back at every
+                          checkpoint); re-binning waits for the device, so
+                          such rollouts are never replayed as hipGraphs;
+                          ignored with a material field or a controller
+                          (binned once then); 0 = once per rollout          */
   int32_t reserved[1]; /* must be 0                                         */
 } mpm_opts;
 
@@ -252,6 +255,13 @@ int64_t mpm_revolve_split(int64_t L, int32_t slots);
  * a different value means that reverse pass would differentiate another
  * rollout.  Errors: MPM_ERR_ARG (NULL argument). */
 int mpm_tape_generation(const mpm_ctx *ctx, uint64_t *gen);
+
+/* Binnings the forward pass of the current tape used (HOST out): 1 when the
+ * particles were binned once (or the rollout is not binned), else 1 + the
+ * checkpoints that sorted them into tiles again (mpm_opts.rebin; with
+ * rebin = 2 the overflow count decides).  Errors: MPM_ERR_ARG (NULL
+ * argument). */
+int mpm_tape_binnings(const mpm_ctx *ctx, int32_t *n);
 
 /* Reverse pass over the tape of the last mpm_rollout: chain rule across the
  * T substeps from dL/ds^T (`gT`) to dL/ds^0 (`g0`) and dL/ds [T][n_act_tot]

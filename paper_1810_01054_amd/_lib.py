@@ -58,7 +58,7 @@ EXPORTS = ["mpm_init", "mpm_destroy", "mpm_set_stream", "mpm_info",
            "mpm_profile", "mpm_profile_read", "mpm_rollout_ctrl",
            "mpm_rollout_ctrl_backward", "mpm_revolve_steps", "mpm_revolve_split",
            "mpm_set_materials", "mpm_material_grad", "mpm_tape_generation",
-           "mpm_step_forward_noalloc", "mpm_set_horizons"]
+           "mpm_step_forward_noalloc", "mpm_set_horizons", "mpm_tape_binnings"]
 
 KERNELS = ["p2g", "grid", "g2p", "adj_scatter", "adj_grid", "adj_gather", "g2p_p2g",
            "adj_fused"]
@@ -96,6 +96,7 @@ def lib():
     L.mpm_set_horizons.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mpm_material_grad.argtypes = [vp, vp, vp]
     L.mpm_tape_generation.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.mpm_tape_binnings.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mpm_revolve_steps.argtypes = [ctypes.c_int64, ctypes.c_int32]
     L.mpm_revolve_steps.restype = ctypes.c_int64
     L.mpm_revolve_split.argtypes = [ctypes.c_int64, ctypes.c_int32]

@@ -137,15 +137,18 @@ struct mpm_ctx {
   // binning of checkpoint segment j of the current tape
   std::vector<BinSet> bins;
   int cur_bin = 0;
-  int rebin = 0;             // re-bin at every checkpoint (uniform tapes)
+  int rebin = 0;             // 1: re-bin at every checkpoint, 2: when particles overflow
   int n_bins = 1;            // binnings of the current tape
+  int *d_over = nullptr;     // particles scattered beyond their tile box's slack
+  int *h_over = nullptr;     // (pinned host copy, read at checkpoints)
 
   // tape
   struct Tape {
     int valid = 0, T = 0, k = 0, memo = 0, sorted = 0, grids_all = 0;
     int rev = 0;              // > 0: binomial checkpointing with rev slots
     int rev_spine = 0;        // its first-descent checkpoints are intact
-    int rebin = 0;            // binned again at every checkpoint (bins[j]: segment j)
+    int rebin = 0;            // re-binned tape: segment j uses bins[seg_bin[j]]
+    std::vector<int> seg_bin; // binning of each checkpoint segment
     float *states = nullptr;  // slots of one state each
     int64_t state_cap = 0;    // slots allocated
     float *grids = nullptr;   // slots of (1 + d) * G floats (m, p)
@@ -356,6 +359,7 @@ TileInfo tile_info(mpm_ctx *c) {
   t.B = c->tile;
   t.list = b.tile_list;
   t.nt_dirty = c->use_nt ? c->d_nt_dirty : nullptr;
+  t.n_over = c->tape.rebin == 2 ? c->d_over : nullptr;
   return t;
 }
 
@@ -1085,9 +1089,9 @@ int ensure_bins(mpm_ctx *c, int n) {
   return MPM_OK;
 }
 
-// Re-binning at checkpoint j: `slot` holds S^{jk} in binning j-1's order;
-// binning j is computed from its positions and the state is put into the
-// new order in place (through the scratch state).
+// Re-binning into binning j: `slot` holds a checkpoint state in binning
+// j-1's order; binning j is computed from its positions and the state is put
+// into the new order in place (through the scratch state).
 int rebin_at(mpm_ctx *c, int j, float *slot) {
   BinSet &dst = c->bins[(size_t)j];
   RC(bin_particles(c, state_at(c, slot).x, dst, &c->bins[(size_t)j - 1]));
@@ -1097,6 +1101,19 @@ int rebin_at(mpm_ctx *c, int j, float *slot) {
   c->cur_bin = j;
   c->n_bins = j + 1;
   return MPM_OK;
+}
+
+// Adaptive re-binning (rebin = 2): at a checkpoint, the particles that the
+// last segment's scatters sent beyond their tile box's slack (global
+// atomics) are read back; past 1% of the segment's particle-substeps the
+// particles are binned again.  The count restarts at every checkpoint.
+constexpr double REBIN_OVERFLOW = 0.01;
+int overflow_wants_rebin(mpm_ctx *c, int seg_len, bool *want) {
+  RC(hip_ok(hipMemcpyAsync(c->h_over, c->d_over, sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream)));
+  RC(hip_ok(hipStreamSynchronize(c->stream)));
+  *want = (double)*c->h_over > REBIN_OVERFLOW * (double)c->N * (double)seg_len;
+  return launch_fill_i32(c->d_over, 1, c->stream);
 }
 
 int rollout_forward(mpm_ctx *c, const Layout &L) {
@@ -1117,20 +1134,30 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
   auto act_of = [&](int n) {
     return c->n_act ? c->tape.act + (int64_t)n * c->n_act : nullptr;
   };
+  if (rebin) c->tape.seg_bin.assign((size_t)((L.T + L.k - 1) / L.k), 0);
+  if (c->tape.rebin == 2) RC(launch_fill_i32(c->d_over, 1, c->stream));
   for (int n = 0; n < L.T; ++n) {
-    // re-binned tapes: every checkpoint starts a new binning
-    const bool new_bin = rebin && n > 0 && n % L.k == 0;
-    if (new_bin) {
-      RC(rebin_at(c, n / L.k, fwd_slot(c, L, n)));
-      chunks = cur_chunks(c, &nch);
-      ids = cur_act_id(c);
+    // re-binned tapes: a checkpoint starts a new binning (every one, or
+    // where the last segment's particles overflowed their tile boxes)
+    bool new_bin = false;
+    if (rebin && n > 0 && n % L.k == 0) {
+      new_bin = true;
+      if (c->tape.rebin == 2) RC(overflow_wants_rebin(c, L.k, &new_bin));
+      if (new_bin) {
+        RC(rebin_at(c, c->n_bins, fwd_slot(c, L, n)));
+        chunks = cur_chunks(c, &nch);
+        ids = cur_act_id(c);
+      }
+      c->tape.seg_bin[(size_t)(n / L.k)] = c->n_bins - 1;
     }
     const State s = state_at(c, fwd_slot(c, L, n));
     const State o = state_at(c, fwd_slot(c, L, n + 1));
     // the controller's component sums of state n come from the G2P that
     // produced it (substep 0: their own kernel)
     if (c->ctl.on) RC(ctl_forward(c, s, n, n > 0 ? nch : 0));
-    if (!fuse || n == 0 || new_bin)
+    // (on re-binned tapes the G2P before a checkpoint runs unfused, whether
+    // or not the checkpoint changes the binning)
+    if (!fuse || n == 0 || (rebin && n % L.k == 0))
       RC(fwd_p2g(c, tiles, chunks, nch, cs(s), ids, act_of(n), c->gm, c->gp, n));
     if (c->tape.grids_all) {
       float *g = slot_grid(c, n);  // keep this substep's grid on the tape
@@ -1139,6 +1166,8 @@ int rollout_forward(mpm_ctx *c, const Layout &L) {
       RC(fwd_grid(c, tiles, c->gm, c->gp, c->gv, 1));
     }
     if (fuse && n + 1 < L.T && !(rebin && (n + 1) % L.k == 0)) {
+      // (a checkpoint of a re-binned tape may change the order: P2G there
+      // runs after the decision)
       // state n+1 is read back only through x and F unless the tape keeps
       // it (memo, or a checkpoint)
       RC(fwd_g2p_p2g(c, cs(s), o, c->gv, ids, act_of(n + 1),
@@ -1216,11 +1245,12 @@ int rollout_backward_core(mpm_ctx *c) {
   auto Gr = [&](int n0, int n) -> float * {
     return t.grids_all ? slot_grid(c, n) : slot_grid(c, n - n0);
   };
-  // re-binned tapes: segment j's states are in binning j's order
+  // re-binned tapes: segment j's states are in binning seg_bin[j]'s order
   auto seg_chunks = [&](int j, int *n) -> const Chunk * {
     if (!t.rebin) return cur_chunks(c, n);
-    *n = c->bins[(size_t)j].n_chunks;
-    return c->bins[(size_t)j].chunks;
+    const BinSet &b = c->bins[(size_t)t.seg_bin[(size_t)j]];
+    *n = b.n_chunks;
+    return b.chunks;
   };
   // recompute segment j's states from its checkpoint with G2P alone,
   // reading each substep's stored grid
@@ -1254,7 +1284,7 @@ int rollout_backward_core(mpm_ctx *c) {
   for (int j = nseg - 1; j >= 0; --j) {
     const int n0 = j * seglen, n1 = std::min(t.T, n0 + seglen);
     if (t.rebin) {
-      c->cur_bin = j;
+      c->cur_bin = t.seg_bin[(size_t)j];
       chunks = cur_chunks(c, &nch);
       ids = cur_act_id(c);
     }
@@ -1316,9 +1346,9 @@ int rollout_backward_core(mpm_ctx *c) {
         std::swap(A0, A1);
       }
     }
-    if (t.rebin && j > 0) {
-      // the adjoint of S^{n0} from binning j's order into binning j-1's
-      RC(permute_state_by(c, ms(A1), A0, c->bins[(size_t)j].rel, 1));
+    if (t.rebin && j > 0 && t.seg_bin[(size_t)j] != t.seg_bin[(size_t)j - 1]) {
+      // the adjoint of S^{n0} from segment j's binning into the one before
+      RC(permute_state_by(c, ms(A1), A0, c->bins[(size_t)t.seg_bin[(size_t)j]].rel, 1));
       std::swap(A0, A1);
     }
     if (overlap) RC(hip_ok(hipEventRecord(c->ev_adj, c->stream)));
@@ -1375,6 +1405,8 @@ const char *mpm_strerror(int code) {
 void mpm_destroy(mpm_ctx *c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  dfree(c->d_over, c->stream);
+  if (c->h_over) (void)hipHostFree(c->h_over);
   dfree(c->d_scenes, c->stream);
   dfree(c->d_chunks_user, c->stream);
   dfree(c->d_gblocks, c->stream);
@@ -1473,7 +1505,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
       if (opts->reserved[k]) return MPM_ERR_ARG;
     if (opts->persistent != 0 && opts->persistent != 1) return MPM_ERR_ARG;
     persistent = opts->persistent;
-    if (opts->rebin != 0 && opts->rebin != 1) return MPM_ERR_ARG;
+    if (opts->rebin < 0 || opts->rebin > 2) return MPM_ERR_ARG;
     rebin = opts->rebin;
     if (opts->fusion < 0 || opts->fusion > 2) return MPM_ERR_ARG;
     fusion = opts->fusion;
@@ -1640,6 +1672,10 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
     if (c->rebin) TRY(dmalloc(&b0.pscene, std::max<int64_t>(N, 1), c->stream));
     c->bins.assign(1, b0);
   }
+  if (c->rebin == 2) {
+    TRY(dmalloc(&c->d_over, 1, c->stream));
+    TRY(hip_ok(hipHostMalloc((void **)&c->h_over, sizeof(int), hipHostMallocDefault)));
+  }
   c->n_nt = (int)ntoff;
   c->use_nt = c->scatter_mode == 3 && c->n_nt > 0;
   if (c->use_nt) {
@@ -1707,6 +1743,12 @@ int mpm_set_stream(mpm_ctx *c, void *stream) {
 int mpm_tape_generation(const mpm_ctx *c, uint64_t *gen) {
   if (!c || !gen) return MPM_ERR_ARG;
   *gen = c->tape_gen;
+  return MPM_OK;
+}
+
+int mpm_tape_binnings(const mpm_ctx *c, int32_t *n) {
+  if (!c || !n) return MPM_ERR_ARG;
+  *n = c->n_bins;
   return MPM_OK;
 }
 
@@ -2060,16 +2102,16 @@ int rollout_run(mpm_ctx *c, int T, int ckpt_k, const mpm_state *s0,
   // re-binning at every checkpoint: checkpointed tapes of binned rollouts
   // without a controller (its component sums follow one order) or a
   // per-particle material field (sorted once per tape)
-  t.rebin = c->rebin && t.sorted && !memo && !rev && k < T && !ctl && !c->has_mat;
+  t.rebin = c->rebin && t.sorted && !memo && !rev && k < T && !ctl && !c->has_mat ? c->rebin : 0;
   if (t.rebin) RC(ensure_bins(c, (T + k - 1) / k));
   if (!ctl && c->n_act && T > 0)
     RC(hip_ok(hipMemcpyAsync(t.act, act, sizeof(float) * T * c->n_act,
                              hipMemcpyDeviceToDevice, c->stream)));
   const Layout L{T, k, memo, ncp};
   const State S0 = state_at(c, slot_state(c, 0));
+  c->cur_bin = 0;
+  c->n_bins = 1;
   if (t.sorted) {
-    c->cur_bin = 0;
-    c->n_bins = 1;
     RC(bin_particles(c, s0->x, c->bins[0]));
     RC(permute_state(c, *s0, S0, 0));
   } else {

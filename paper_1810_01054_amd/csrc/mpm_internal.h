@@ -87,6 +87,8 @@ struct TileInfo {
   const int *list;   // non-null: workgroup b handles tile list[b] (non-empty tiles)
   int *nt_dirty;     // non-null: node tiles that particles beyond their box's slack
                      // reached with global atomics (set to 1, per rollout)
+  int *n_over = nullptr;  // non-null: particles scattered with global atomics
+                          // (beyond their box's slack) are counted here
 };
 
 struct P2GArgs {

@@ -1109,6 +1109,11 @@ __device__ __forceinline__ void offsets_flush(float *box, int lcell,
 template <int D>
 __device__ __forceinline__ void mark_dirty(const TileInfo &T, const DevScene &sc,
                                            const int *base) {
+  if (T.n_over) {
+    // one atomic per wave: the lowest calling lane adds the wave's count
+    const unsigned long long m = __ballot(1);
+    if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(T.n_over, __popcll(m));
+  }
   if (!T.nt_dirty) return;
   int lo[D], hi[D];
 #pragma unroll

@@ -58,7 +58,7 @@ class Simulator:
                  tile: int = 0, sort: bool = True, scatter: int = 0,
                  recompute_grids: bool = False, graphs: bool = False, stream=None,
                  fusion: int = 0, deterministic: bool = False, persistent: bool = False,
-                 rebin: bool = False):
+                 rebin: int = 0):
         self.L = _lib.lib()
         self.scenes = [dict(s) for s in scenes]
         self.dim = self.scenes[0]["dim"]
@@ -75,7 +75,7 @@ class Simulator:
         opts.fusion = int(fusion)
         opts.deterministic = int(bool(deterministic))
         opts.persistent = int(bool(persistent))
-        opts.rebin = int(bool(rebin))
+        opts.rebin = int(rebin)  # 0 off, 1 (or True) every checkpoint, 2 on overflow
         self.ctx = ctypes.c_void_p()
         self._stream = stream
         check(self.L.mpm_init(ctypes.byref(self.ctx), arr, len(scenes), ids,
@@ -280,6 +280,12 @@ class Simulator:
 
     def sync_errors(self):
         check(self.L.mpm_sync_errors(self.ctx), "device error")
+
+    def tape_binnings(self) -> int:
+        """Binnings the current tape's forward pass used (mpm_tape_binnings)."""
+        n = ctypes.c_int32()
+        check(self.L.mpm_tape_binnings(self.ctx, ctypes.byref(n)), "mpm_tape_binnings")
+        return n.value
 
     def tape_generation(self) -> int:
         """The context's tape generation (mpm_tape_generation): changes with

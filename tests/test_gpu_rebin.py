@@ -158,3 +158,37 @@ def test_deterministic_rebinned_rollouts_repeat_bit_for_bit():
     _oracle_check(sc, acts, T, gT, a, "rebin det")
     sim.close()
     other.close()
+
+
+@pytest.mark.parametrize("dim,k", [(2, 16), (3, 8)])
+def test_adaptive_rebin_follows_the_overflow_and_matches_oracle(dim, k):
+    """rebin = 2: the drifting scenes overflow their tile boxes within a
+    segment, so the tape re-bins at some checkpoints; the results are held to
+    the oracle like every other tape."""
+    sc, T = _drifting(dim)
+    acts = _acts(sc, T)
+    gT = _seed(sc, 95 + dim)
+    say("adaptive rebin", dim, k)
+    sim = sim_for(sc, rebin=2)
+    out = _run(sim, sc, acts, T, k, gT)
+    nb = sim.tape_binnings()
+    sim.close()
+    assert nb > 1, nb
+    _oracle_check(sc, acts, T, gT, out, f"adaptive rebin {dim}d k={k}")
+
+
+def test_adaptive_rebin_keeps_one_binning_without_drift():
+    """The drifting 3D block without its drift velocity: no particle leaves
+    its tile box's slack within a segment, so the tape keeps its first
+    binning and equals the once-binned rollout within the parity bounds."""
+    sc = S.perturb(S.box_3d(24, (6, 3, 7), (14, 9, 13), seed=36), 5, v_scale=0.3,
+                   C_scale=0.5, F_scale=0.02)
+    T, k = 30, 8
+    acts = _acts(sc, T)
+    gT = _seed(sc, 97)
+    say("adaptive rebin, no drift")
+    sim = sim_for(sc, rebin=2)
+    out = _run(sim, sc, acts, T, k, gT)
+    assert sim.tape_binnings() == 1
+    sim.close()
+    _oracle_check(sc, acts, T, gT, out, "adaptive rebin without drift")
