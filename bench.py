@@ -447,7 +447,7 @@ def main():
                          "the rollout (1.0: 3.3 cells over 512 substeps)")
     ap.add_argument("--rebin", type=int, default=None, choices=(0, 1, 2),
                     help="c2/c3: sort the particles into tiles again at every checkpoint "
-                         "(1), or at the checkpoints where more than 1%% of the last "
+                         "(1), or at the checkpoints where more than 0.5%% of the last "
                          "segment's particle-substeps overflowed their tile boxes (2); "
                          "default: 1 for c2, whose blocks travel, 0 for c3")
     ap.add_argument("--no-profile", action="store_true",
@@ -668,6 +668,7 @@ def main():
                    "fusion": args.fusion,
                    "rebin": int(args.rebin or 0),
                    "drift_vx": args.drift,
+                   "binnings_per_rollout": sim.tape_binnings(),
                    "global_batch": 1, "parallelism": "single GPU"},
         "pct_hbm_peak_672B_per_pss": round(672.0 * value / (HBM_PEAK_GBS * 1e9), 4),
         # the particle-stream bytes the launched kernels move (launch counts

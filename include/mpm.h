@@ -126,7 +126,7 @@ typedef struct mpm_opts {
                           checkpoint (the reverse pass uses each segment's
                           binning), so particles that travel stay within their
                           tile box's slack; 2: at the checkpoints where more
-                          than 1% of the last segment's particle-substeps
+                          than 0.5% of the last segment's particle-substeps
                           scattered beyond their tile box's slack (global
                           atomics; the count is read back at every
                           checkpoint); re-binning waits for the device, so

@@ -1105,9 +1105,9 @@ int rebin_at(mpm_ctx *c, int j, float *slot) {
 
 // Adaptive re-binning (rebin = 2): at a checkpoint, the particles that the
 // last segment's scatters sent beyond their tile box's slack (global
-// atomics) are read back; past 1% of the segment's particle-substeps the
+// atomics) are read back; past 0.5% of the segment's particle-substeps the
 // particles are binned again.  The count restarts at every checkpoint.
-constexpr double REBIN_OVERFLOW = 0.01;
+constexpr double REBIN_OVERFLOW = 0.005;
 int overflow_wants_rebin(mpm_ctx *c, int seg_len, bool *want) {
   RC(hip_ok(hipMemcpyAsync(c->h_over, c->d_over, sizeof(int), hipMemcpyDeviceToHost,
                            c->stream)));

@@ -3330,7 +3330,16 @@ __global__ __launch_bounds__(256) void k_sort_count(SortArgs A) {
   }
   const int tile = sc.tile_off + tl;
   const int rank = atomicAdd(&A.cell_cnt[(int64_t)tile * ipow<D>(TB) + cl], 1);
-  atomicAdd(&A.tile_cnt[tile], 1);
+  // per-tile counts: the lanes of a wave mostly share a tile (particles in
+  // tile order), so one atomic per distinct tile of the wave
+  unsigned long long pending = __ballot(1);
+  while (pending) {
+    const int lead = __ffsll((long long)pending) - 1;
+    const int lt = __shfl(tile, lead, 64);
+    const unsigned long long same = __ballot(tile == lt) & pending;
+    if ((int)(threadIdx.x & 63) == lead) atomicAdd(&A.tile_cnt[lt], __popcll(same));
+    pending &= ~same;
+  }
   A.ptile[p] = tile;
   A.pcell[p] = cl;
   A.prank[p] = rank;
