@@ -39,6 +39,7 @@ struct DevBuf {
 struct BinSet {
   int *tile_cnt = nullptr, *tile_start = nullptr, *perm = nullptr, *act = nullptr;
   int *tile_list = nullptr, *pscene = nullptr, *rel = nullptr;
+  int *nt_cand = nullptr;  // 3D node tiles: covering tiles with particles [n_nt][8]
   Chunk *chunks = nullptr;
   int n_chunks = 0, n_ne = 0;
   bool owned = false;  // buffers allocated for this set (re-bins)
@@ -417,6 +418,7 @@ int fwd_grid(mpm_ctx *c, bool tiles, float *gm, float *gp, float *gv,
     a.nt_dirty = c->d_nt_dirty;
     a.n_nt = c->n_nt;
     a.persist = c->persistent;
+    a.nt_cand = bin(c).nt_cand;
     return launch_grid_nt(c->dim, a, c->stream);
   }
   return launch_grid(c->dim, a, c->stream);
@@ -526,6 +528,7 @@ int bwd_grid(mpm_ctx *c, bool tiles, const float *gm, const float *gp) {
     r2.nt_dirty = c->d_nt_dirty;
     r2.n_nt = c->n_nt;
     r2.persist = c->persistent;
+    r2.nt_cand = bin(c).nt_cand;
     return launch_adj_grid_nt(c->dim, r2, c->stream);
   }
   return launch_adj_grid(c->dim, r2, c->stream);
@@ -667,6 +670,8 @@ int bin_particles(mpm_ctx *c, const float *x, BinSet &dst, const BinSet *prev = 
     RC(launch_cell_sort(c->d_cell_start, (int)ncell, c->d_cell_list, c->d_prank, s));
   }
   RC(launch_scan_i32(dst.tile_cnt, dst.tile_start, c->n_tiles, s));
+  if (dst.nt_cand)
+    RC(launch_nt_cand(c->d_scenes, c->d_nt_scene, c->n_nt, dst.tile_cnt, dst.nt_cand, s));
   if (prev) {
     RC(launch_sort_place(c->dim, a, dst.tile_start, dst.rel, s));
     RC(launch_permute_i32(prev->perm, dst.perm, dst.rel, N, s));
@@ -1084,6 +1089,7 @@ int ensure_bins(mpm_ctx *c, int n) {
     RC(dmalloc(&b.pscene, N, c->stream));
     RC(dmalloc(&b.rel, N, c->stream));
     RC(dmalloc(&b.chunks, N / CH + nt + 1, c->stream));
+    if (c->use_nt && c->dim == 3) RC(dmalloc(&b.nt_cand, (int64_t)c->n_nt * 8, c->stream));
     c->bins.push_back(b);
   }
   return MPM_OK;
@@ -1453,6 +1459,7 @@ void mpm_destroy(mpm_ctx *c) {
   dfree(c->d_tile_list, c->stream);
   for (auto &b : c->bins) {
     dfree(b.pscene, c->stream);
+    dfree(b.nt_cand, c->stream);
     if (!b.owned) continue;
     dfree(b.tile_cnt, c->stream);
     dfree(b.tile_start, c->stream);
@@ -1681,6 +1688,7 @@ int mpm_init(mpm_ctx **out, const mpm_scene *scenes, int n_scenes,
   if (c->use_nt) {
     TRY(dmalloc(&c->d_nt_scene, c->n_nt, c->stream));
     TRY(dmalloc(&c->d_nt_dirty, c->n_nt, c->stream));
+    if (c->dim == 3) TRY(dmalloc(&c->bins[0].nt_cand, (int64_t)c->n_nt * 8, c->stream));
   }
   if (c->det) {
     TRY(dmalloc(&c->d_cell_start, n_tiles * cpt + 1, c->stream));

@@ -124,6 +124,9 @@ struct GridArgs {
   const int *nt_scene = nullptr;
   const int *nt_dirty = nullptr;
   int n_nt = 0;  int persist = 0;  // persistent launch: a few workgroups loop over the node tiles
+  // 3D, 4^3-cell tiles: per node tile the 8 covering tiles that hold
+  // particles (-1 for none), built at binning ([n_nt][8]; null: from counts)
+  const int *nt_cand = nullptr;
 };
 
 struct G2PArgs {
@@ -195,6 +198,7 @@ struct AdjGridArgs {
   const int *nt_scene = nullptr;  // node-tile launch (see GridArgs)
   const int *nt_dirty = nullptr;
   int n_nt = 0;  int persist = 0;  // persistent launch: a few workgroups loop over the node tiles
+  const int *nt_cand = nullptr;    // see GridArgs
 };
 
 struct AdjGatherArgs {
@@ -335,6 +339,9 @@ int launch_chunk_count(const int *tile_cnt, int n_tiles, int *nch,
 // flag[i] = tile_cnt[i] > 0; list[pos[i]] = i for flagged tiles.
 int launch_nonempty_flag(const int *tile_cnt, int n_tiles, int *flag,
                          hipStream_t st);
+// Per node tile of 3D 4^3-cell tiles, the 8 covering tiles holding particles.
+int launch_nt_cand(const DevScene *scenes, const int *nt_scene, int n_nt,
+                   const int *tile_cnt, int *cand, hipStream_t st);
 int launch_compact(const int *flag, const int *pos, int n_tiles, int *list,
                    hipStream_t st);
 int launch_build_chunks(const int *tile_cnt, const int *tile_start,

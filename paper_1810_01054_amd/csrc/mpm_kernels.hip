@@ -2169,11 +2169,121 @@ __device__ __forceinline__ NodeTile<D, B> node_tile(const DevScene &sc, int lt,
   return r;
 }
 
+// Candidate table of the 3D node-tile kernels, built once per binning: for
+// node tile ntg the global index of each of its 8 covering tiles (tiles t-1
+// and t per axis, axis 0 slowest) that exists and holds particles, else -1.
+// With 4^3-cell tiles every candidate's box covers the whole node tile, as
+// its block (1 - offset) per axis (box_pos), so the grid kernels read the
+// boxes from this table without waiting for the tile counts.
+__global__ __launch_bounds__(256) void k_nt_cand(const DevScene *scenes,
+                                                 const int *nt_scene, int n_nt,
+                                                 const int *tile_cnt, int *cand) {
+  const int ntg = blockIdx.x * 256 + threadIdx.x;
+  if (ntg >= n_nt) return;
+  const DevScene sc = scenes[nt_scene[ntg]];
+  int t[3], l = ntg - sc.nt_off;
+#pragma unroll
+  for (int a = 2; a >= 0; --a) {
+    t[a] = l % sc.nnt;
+    l /= sc.nnt;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    bool ok = true;
+    int tl = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int u = t[a] - 1 + ((k >> (2 - a)) & 1);
+      ok = ok && u >= 0 && u < sc.nt;
+      tl = tl * sc.nt + (ok ? u : 0);
+    }
+    const int tile = sc.tile_off + tl;
+    cand[(int64_t)ntg * 8 + k] = ok && tile_cnt[tile] != 0 ? tile : -1;
+  }
+}
+
+// Box entries of node tile ntg's lane from its candidate table (3D, 4^3-cell
+// tiles): NC channels of each candidate (zeros for none).
+template <int NC>
+__device__ __forceinline__ bool nt_cand_boxes(const int *nt_cand, const float *part,
+                                              int ntg, float (&val)[8][NC]) {
+  constexpr int SV = 512;
+  const int lane = threadIdx.x & 63;
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int tk = nt_cand[(int64_t)ntg * 8 + k];
+    any = any || tk >= 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[k][c] = 0.0f;
+    if (tk >= 0) {
+      const int blk = ((1 - ((k >> 2) & 1)) * 2 + (1 - ((k >> 1) & 1))) * 2 + (1 - (k & 1));
+      const float *bx = part + (int64_t)tk * 4 * SV + blk * 64 + lane;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) val[k][c] = bx[c * SV];
+    }
+  }
+  return any;
+}
+
+// Node index (scene-local) of this lane in node tile ntg and whether it lies
+// in the grid (3D, 4^3-node node tiles).
+__device__ __forceinline__ bool nt_node(const DevScene &sc, int ntg, int *li) {
+  int l = ntg - sc.nt_off, ll = (int)threadIdx.x & 63, g[3];
+#pragma unroll
+  for (int a = 2; a >= 0; --a) {
+    g[a] = (l % sc.nnt) * 4 - 1 + ll % 4;
+    l /= sc.nnt;
+    ll /= 4;
+  }
+  *li = (g[0] * sc.n + g[1]) * sc.n + g[2];
+  return g[0] >= 0 && g[0] < sc.n && g[1] >= 0 && g[1] < sc.n && g[2] >= 0 && g[2] < sc.n;
+}
+
 // Grid operations over node tiles (see k_grid): direct adds (only where a
 // particle beyond its box's slack flagged the node tile) then the candidate
 // boxes in the nested-loop order.
 template <int D>
 __device__ __forceinline__ void grid_nt_item(const GridArgs &A, int ntg) {
+  if constexpr (D == 3) {
+    if (A.nt_cand) {
+      // the box loads go out with the scene and flag loads (candidate table)
+      float val[8][4];
+      const bool any = nt_cand_boxes<4>(A.nt_cand, A.part, ntg, val);
+      const bool dirty = A.nt_dirty[ntg] != 0;
+      if (!any && !dirty) return;
+      const DevScene sc = A.scenes[A.nt_scene[ntg]];
+      int li;
+      if (!nt_node(sc, ntg, &li)) return;
+      const int64_t gi = sc.g_off + li;
+      float mp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (dirty) {
+        mp[0] = A.gm[gi];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mp[1 + a] = A.gp[a * A.G + gi];
+      }
+      const bool direct = mp[0] != 0.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) mp[c] += val[k][c];
+      float v[3];
+      node_velocity<3>(sc, li, mp[0], mp + 1, v);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) A.gv[a * A.G + gi] = v[a];
+      if (A.zero_mp && direct) {
+        A.gm[gi] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.gp[a * A.G + gi] = 0.0f;
+      }
+      if (A.out_m) {
+        A.out_m[gi] = mp[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.out_p[a * A.G + gi] = mp[1 + a];
+      }
+      return;
+    }
+  }
   constexpr int B = D == 2 ? 8 : 4;
   constexpr int S = TileBox<B>::S, SV = D == 2 ? S * S : S * S * S;
   const DevScene sc = A.scenes[A.nt_scene[ntg]];
@@ -2641,38 +2751,72 @@ template <int D>
 __device__ __forceinline__ void adj_grid_nt_item(const AdjGridArgs &A, int ntg) {
   constexpr int B = D == 2 ? 8 : 4;
   constexpr int S = TileBox<B>::S, SV = D == 2 ? S * S : S * S * S;
-  const DevScene sc = A.scenes[A.nt_scene[ntg]];
-  const NodeTile<D, B> nt = node_tile<D, B>(sc, ntg - sc.nt_off, A.tile_cnt);
-  const bool dirty = A.nt_dirty[ntg] != 0;
-  if ((!nt.any && !dirty) || !nt.valid) return;
-  const int li = nt.li;
-  const int64_t gi = sc.g_off + li;
+  int li;
+  int64_t gi;
   float vb[D];
   bool nz = false;
+  float m;
+  DevScene sc;
+  bool from_cand = false;
+  if constexpr (D == 3) {
+    if (A.nt_cand) {
+      // the box loads go out with the scene and flag loads (candidate table)
+      from_cand = true;
+      float val[8][3];
+      const bool any = nt_cand_boxes<3>(A.nt_cand, A.part, ntg, val);
+      const bool dirty = A.nt_dirty[ntg] != 0;
+      if (!any && !dirty) return;
+      sc = A.scenes[A.nt_scene[ntg]];
+      if (!nt_node(sc, ntg, &li)) return;
+      gi = sc.g_off + li;
 #pragma unroll
-  for (int a = 0; a < D; ++a) vb[a] = 0.0f;
-  if (dirty) {
+      for (int a = 0; a < D; ++a) vb[a] = 0.0f;
+      if (dirty) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      vb[a] = A.vbar[a * A.G + gi];
-      nz = nz || vb[a] != 0.0f;
+        for (int a = 0; a < D; ++a) {
+          vb[a] = A.vbar[a * A.G + gi];
+          nz = nz || vb[a] != 0.0f;
+        }
+      }
+      m = A.gm[gi];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int c = 0; c < D; ++c) vb[c] += val[k][c];
     }
   }
-  const float m = A.gm[gi];
-  float val[NodeTile<D, B>::K][D];
+  if (!from_cand) {
+    sc = A.scenes[A.nt_scene[ntg]];
+    const NodeTile<D, B> nt = node_tile<D, B>(sc, ntg - sc.nt_off, A.tile_cnt);
+    const bool dirty = A.nt_dirty[ntg] != 0;
+    if ((!nt.any && !dirty) || !nt.valid) return;
+    li = nt.li;
+    gi = sc.g_off + li;
 #pragma unroll
-  for (int k = 0; k < NodeTile<D, B>::K; ++k)
-    if (nt.nz[k] && nt.cov[k]) {
-      const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + box_pos<D, B>(nt.loc[k]);
+    for (int a = 0; a < D; ++a) vb[a] = 0.0f;
+    if (dirty) {
 #pragma unroll
-      for (int c = 0; c < D; ++c) val[k][c] = bx[c * SV];
+      for (int a = 0; a < D; ++a) {
+        vb[a] = A.vbar[a * A.G + gi];
+        nz = nz || vb[a] != 0.0f;
+      }
     }
+    m = A.gm[gi];
+    float val[NodeTile<D, B>::K][D];
 #pragma unroll
-  for (int k = 0; k < NodeTile<D, B>::K; ++k)
-    if (nt.nz[k] && nt.cov[k]) {
+    for (int k = 0; k < NodeTile<D, B>::K; ++k)
+      if (nt.nz[k] && nt.cov[k]) {
+        const float *bx = A.part + (int64_t)nt.tile[k] * (D + 1) * SV + box_pos<D, B>(nt.loc[k]);
 #pragma unroll
-      for (int c = 0; c < D; ++c) vb[c] += val[k][c];
-    }
+        for (int c = 0; c < D; ++c) val[k][c] = bx[c * SV];
+      }
+#pragma unroll
+    for (int k = 0; k < NodeTile<D, B>::K; ++k)
+      if (nt.nz[k] && nt.cov[k]) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) vb[c] += val[k][c];
+      }
+  }
   const bool wall = is_wall<D>(li, sc.n, sc.wall);
   float pb[D], v[D];
   float mb = 0.0f;
@@ -3998,6 +4142,11 @@ int launch_chunk_count(const int *tile_cnt, int n, int *nch, hipStream_t st) {
 
 int launch_nonempty_flag(const int *tile_cnt, int n, int *flag, hipStream_t st) {
   MPM_LAUNCH(k_nonempty_flag, blocks_for(n), 256, st, tile_cnt, n, flag);
+}
+
+int launch_nt_cand(const DevScene *scenes, const int *nt_scene, int n_nt,
+                   const int *tile_cnt, int *cand, hipStream_t st) {
+  MPM_LAUNCH(k_nt_cand, (n_nt + 255) / 256, 256, st, scenes, nt_scene, n_nt, tile_cnt, cand);
 }
 
 int launch_compact(const int *flag, const int *pos, int n, int *list,
