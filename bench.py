@@ -369,9 +369,13 @@ def run_serving(args):
 
     n_req = args.requests
     base = S.config_5(n_requests=n_req, rate=1.0, seed=1815)
-    warm = S.config_5(n_requests=6, rate=1.0, seed=1816)
+    # warm-up: a burst of two full batches per lane through the batched
+    # server (its multi-scene contexts grow the device memory pool to the
+    # steady state), then a few requests through the plain loop
+    warm = S.config_5(n_requests=2 * args.max_batch * args.lanes, rate=1.0, seed=1816)
     Server(max_batch=args.max_batch, lanes=args.lanes, ckpt_k=args.ckpt).run(
         [S.Request(0.0, r.scene, r.T) for r in warm])
+    Server(ckpt_k=args.ckpt).run([S.Request(0.0, r.scene, r.T) for r in warm[:6]], fifo=True)
     burst = [S.Request(0.0, r.scene, r.T) for r in base]
     cap_res = Server(ckpt_k=args.ckpt).run(burst, fifo=True)
     cap = summarize(cap_res)["requests_per_s"]
