@@ -443,8 +443,12 @@ __device__ __forceinline__ void scatter_stencil(const float (&w)[D][3],
         float val[D + M];
         if constexpr (HAS_MASS) val[0] = N * m0;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          val[M + a] = N * (c0[a] + L[a][0] * o0 + L[a][1] * o1);
+        for (int a = 0; a < 2; ++a) {
+          float v = c0[a];  // zero offset components left out
+          if (o0) v += L[a][0] * o0;
+          if (o1) v += L[a][1] * o1;
+          val[M + a] = N * v;
+        }
         sink(o0, o1, 0, val);
       }
   } else {
@@ -459,9 +463,13 @@ __device__ __forceinline__ void scatter_stencil(const float (&w)[D][3],
           float val[D + M];
           if constexpr (HAS_MASS) val[0] = N * m0;
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-            val[M + a] =
-                N * (c0[a] + L[a][0] * o0 + L[a][1] * o1 + L[a][2] * o2);
+          for (int a = 0; a < 3; ++a) {
+            float v = c0[a];  // zero offset components left out
+            if (o0) v += L[a][0] * o0;
+            if (o1) v += L[a][1] * o1;
+            if (o2) v += L[a][2] * o2;
+            val[M + a] = N * v;
+          }
           sink(o0, o1, o2, val);
         }
       }
@@ -1020,10 +1028,14 @@ __device__ __forceinline__ void offsets_add(const float (&w)[D][3], float mp,
     if constexpr (D == 3) N *= w[2][O::o2];
     int ch = 0;
     if constexpr (HAS_MASS) acc[J * NCH + ch++] += N * mp;
+    // terms with a zero offset component are left out (the compiler keeps
+    // a multiply by 0.0f, which is not an identity in IEEE arithmetic)
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      float v = c0[a] + L[a][0] * (float)O::o0 + L[a][1] * (float)O::o1;
-      if constexpr (D == 3) v += L[a][2] * (float)O::o2;
+      float v = c0[a];
+      if constexpr (O::o0 != 0) v += L[a][0] * (float)O::o0;
+      if constexpr (O::o1 != 0) v += L[a][1] * (float)O::o1;
+      if constexpr (D == 3 && O::o2 != 0) v += L[a][2] * (float)O::o2;
       acc[J * NCH + ch + a] += N * v;
     }
     offsets_add<D, NCH, HAS_MASS, W, J + 1>(w, mp, c0, L, acc);
@@ -2955,8 +2967,10 @@ __device__ __forceinline__ bool adj_gather_particle(
       float cv = cV[a], q = cq[a];
 #pragma unroll
       for (int b = 0; b < D; ++b) {
-        cv += CdxD[a][b] * o[b];
-        q += Gdx[a][b] * o[b];
+        if (o[b] != 0.0f) {  // constant after unrolling; zero terms left out
+          cv += CdxD[a][b] * o[b];
+          q += Gdx[a][b] * o[b];
+        }
       }
       // (J) v-term and C-term (N parts), p-term (N part)
       s_all += vi[a] * cv + pb[a] * q;
@@ -2965,8 +2979,10 @@ __device__ __forceinline__ bool adj_gather_particle(
       Sv[a] += Nv;    // delta part of the (J) C-term
 #pragma unroll
       for (int b = 0; b < D; ++b) {
-        Gb[a * D + b] += Npb * o[b];
-        Co[a * D + b] += Nv * o[b];
+        if (o[b] != 0.0f) {
+          Gb[a * D + b] += Npb * o[b];
+          Co[a * D + b] += Nv * o[b];
+        }
       }
     }
 #pragma unroll
@@ -2986,7 +3002,10 @@ __device__ __forceinline__ bool adj_gather_particle(
       }
   } else {
     // rows of the stencil are not unrolled: one row of node records in
-    // flight instead of all 27 keeps the register count near the bound
+    // flight instead of all 27 keeps the register count near the bound.
+    // Within a row (o0, o1) only o2 varies, so the o0 and o1 columns of Go
+    // and Co take the row's sums R = sum N p_i and Rv = sum N v_i once per
+    // row, and Spb, Sv add the row sums.
 #pragma unroll 1
     for (int o0 = 0; o0 < 3; ++o0)
 #pragma unroll 1
@@ -2994,14 +3013,52 @@ __device__ __forceinline__ bool adj_gather_particle(
         const float w01 = w[0][o0] * w[1][o1];
         const float d01 = dw[0][o0] * w[1][o1];
         const float w0d1 = w[0][o0] * dw[1][o1];
+        const float fo0 = (float)o0, fo1 = (float)o1;
+        float cv0[3], q0[3];  // cV + CdxD (o0, o1, 0), cq + Gdx (o0, o1, 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          cv0[a] = cV[a] + CdxD[a][0] * fo0 + CdxD[a][1] * fo1;
+          q0[a] = cq[a] + Gdx[a][0] * fo0 + Gdx[a][1] * fo1;
+        }
+        float R[3] = {}, Rv[3] = {};
 #pragma unroll
         for (int o2 = 0; o2 < 3; ++o2) {
           const float N = w01 * w[2][o2];
           const float gN[3] = {d01 * w[2][o2], w0d1 * w[2][o2], w01 * dw[2][o2]};
-          const float o[3] = {(float)o0, (float)o1, (float)o2};
           AdjNode nd;
           node(o0, o1, o2, nd);
-          add_node(nd, N, gN, o);
+          const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
+          const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
+          float s_all = m.mp * nd.a.w;  // (J) m-term
+          if constexpr (PM) Nmb += N * nd.a.w;
+          const float No2 = N * (float)o2;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            // (J) v-term and C-term (N parts), p-term (N part)
+            float cv = cv0[a], q = q0[a];
+            if (o2 != 0) {
+              cv += CdxD[a][2] * (float)o2;
+              q += Gdx[a][2] * (float)o2;
+            }
+            s_all += vi[a] * cv + pb[a] * q;
+            R[a] = fmaf(N, pb[a], R[a]);
+            Rv[a] = fmaf(N, vi[a], Rv[a]);
+            if (o2 != 0) {
+              Gb[a * 3 + 2] = fmaf(No2, pb[a], Gb[a * 3 + 2]);
+              Co[a * 3 + 2] = fmaf(No2, vi[a], Co[a * 3 + 2]);
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xb[c] += gN[c] * s_all;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Spb[a] += R[a];  // (F), and the delta part of the (J) p-term
+          Sv[a] += Rv[a];  // delta part of the (J) C-term
+          Gb[a * 3 + 0] += R[a] * fo0;
+          Gb[a * 3 + 1] += R[a] * fo1;
+          Co[a * 3 + 0] += Rv[a] * fo0;
+          Co[a * 3 + 1] += Rv[a] * fo1;
         }
       }
   }
