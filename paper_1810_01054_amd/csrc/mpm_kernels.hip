@@ -2875,8 +2875,10 @@ __global__ __launch_bounds__(64) void k_adj_grid_nt(AdjGridArgs A) {
 // gather (supplement F-K)
 // ---------------------------------------------------------------------------
 
-// Node record staged in LDS for the adjoint gather: dL/dp (d), dL/dm, v (d),
-// padded to 8 floats so a node is two 16-byte LDS reads.
+// Node record of the adjoint gather: dL/dp (d), dL/dm, v (d), padded to 8
+// floats, so a node is two 16-byte LDS reads (k_adj_gather keeps the two
+// halves in separate arrays: a 16-byte node stride spreads the lanes of a
+// wave over more LDS banks than a 32-byte one).
 struct __align__(16) AdjNode {
   float4 a;  // pbar0, pbar1, pbar2 (or 0), mbar      (2D: pbar0, pbar1, 0, mbar)
   float4 b;  // v0, v1, v2 (or 0), unused
@@ -2906,10 +2908,12 @@ __device__ __forceinline__ AdjNode adj_node_global(const Args &A, int64_t gi) {
 // Out: xvc(ok, xb, vb, Cb) as soon as the x, v, C adjoints of state n are
 // final, then fout(ok, Fb) with the F adjoint; sb_act += (K) for an actuated
 // particle.  PM: pm_mass(ok, Nmb, Spb, Gb) and pm_stress(ok, Ptb, F, S,
-// inner) hand over what the per-particle material gradients need.  ok is
-// false (and eb set) when F^n is inverted; it is also returned.
-template <int D, bool PM, typename Node, typename Unpark, typename XVC, typename FOut,
-          typename PmMass, typename PmStress>
+// inner) hand over what the per-particle material gradients need.  MBS:
+// the records carry m_p dL/dm_i (one scene-wide m_p, scaled once per staged
+// node) in place of dL/dm_i.  ok is false (and eb set) when F^n is
+// inverted; it is also returned.
+template <int D, bool PM, bool MBS = false, typename Node, typename Unpark, typename XVC,
+          typename FOut, typename PmMass, typename PmStress>
 __device__ __forceinline__ bool adj_gather_particle(
     const DevScene &sc, const Mat &m, const float *f, const float *v, const float *C,
     const float *F0, const float *gx1, const float *gv1, const float *gC1,
@@ -2960,7 +2964,7 @@ __device__ __forceinline__ bool adj_gather_particle(
   auto add_node = [&](const AdjNode &nd, float N, const float *gN, const float *o) {
     const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
     const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
-    float s_all = m.mp * nd.a.w;  // (J) m-term
+    float s_all = MBS ? nd.a.w : m.mp * nd.a.w;  // (J) m-term
     if constexpr (PM) Nmb += N * nd.a.w;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -3029,7 +3033,7 @@ __device__ __forceinline__ bool adj_gather_particle(
           node(o0, o1, o2, nd);
           const float pb[3] = {nd.a.x, nd.a.y, nd.a.z};
           const float vi[3] = {nd.b.x, nd.b.y, nd.b.z};
-          float s_all = m.mp * nd.a.w;  // (J) m-term
+          float s_all = MBS ? nd.a.w : m.mp * nd.a.w;  // (J) m-term
           if constexpr (PM) Nmb += N * nd.a.w;
           const float No2 = N * (float)o2;
 #pragma unroll
@@ -3177,7 +3181,7 @@ __device__ __forceinline__ bool adj_gather_particle(
 // their gradients dL/dmu_p, dL/dla_p, dL/dm_p are added to A.gmat.
 template <int D, bool PM>
 __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
-  __shared__ AdjNode s_n[LDS_NODES];
+  __shared__ float4 s_na[LDS_NODES], s_nb[LDS_NODES];  // AdjNode halves a, b
   __shared__ double s_act[LDS_ACT];
   // F^n and dL/dF^{n+1} of each thread, kept for the post-loop algebra
   __shared__ float s_keep[D == 3 ? 2 * D * D * CH : 1];
@@ -3230,8 +3234,12 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
   if (act_lds)
     for (int i = t; i < sc.n_act; i += CH) s_act[i] = 0.0;
   if (box.lds) {
-    for (int i = t; i < box.vol; i += CH)
-      s_n[i] = adj_node_global<D>(A, sc.g_off + box_node<D>(box, i, sc.n));
+    for (int i = t; i < box.vol; i += CH) {
+      AdjNode r = adj_node_global<D>(A, sc.g_off + box_node<D>(box, i, sc.n));
+      if constexpr (!PM) r.a.w *= sc.mp;  // m_p dL/dm_i, the (J) m-term's factor
+      s_na[i] = r.a;
+      s_nb[i] = r.b;
+    }
   }
   __syncthreads();
 
@@ -3248,15 +3256,18 @@ __global__ __launch_bounds__(CH, 3) void k_adj_gather(AdjGatherArgs A) {
     }
     const int lbase = box.lds ? box_index<D>(box, base) : 0;
     const int64_t gbase = sc.g_off + node_index<D>(base, sc.n);
-    ok = adj_gather_particle<D, PM>(
+    ok = adj_gather_particle<D, PM, !PM>(
         sc, m, f, v, C, F, gx1, gv1, gC1, gF1, s_act, j_act >= 0,
         [&](int o0, int o1, int o2, AdjNode &nd) {
-          if constexpr (D == 2) {
-            nd = box.lds ? s_n[lbase + o0 * box.e[1] + o1]
-                         : adj_node_global<D>(A, gbase + o0 * sc.n + o1);
+          if (box.lds) {
+            const int li = D == 2 ? lbase + o0 * box.e[1] + o1
+                                  : lbase + (o0 * box.e[1] + o1) * box.e[2] + o2;
+            nd.a = s_na[li];
+            nd.b = s_nb[li];
           } else {
-            nd = box.lds ? s_n[lbase + (o0 * box.e[1] + o1) * box.e[2] + o2]
-                         : adj_node_global<D>(A, gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
+            nd = adj_node_global<D>(A, D == 2 ? gbase + o0 * sc.n + o1
+                                              : gbase + ((int64_t)o0 * sc.n + o1) * sc.n + o2);
+            if constexpr (!PM) nd.a.w *= sc.mp;
           }
         },
         [&](float *Fr, float *gFr) {
